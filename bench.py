@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Benchmark: order-0 discrete Hankel transform at N = 2^20, eps = 1e-8 on one MI355X.
+
+A step is one complete transform f = J_0(j_0 j_0^T / j_{0,N+1}) c of one
+seeded synthetic coefficient vector (c_n iid N(0,1), the paper's Sec. 6.1
+workload), input and output resident in HBM.  Prints one JSON line with
+points/s (N output points per transform), the roofline of the dominant
+kernel (HIP-event timing inside the timed region), and the CPU oracle timed
+on a bounded row sample on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector peak
+METRIC = "DHT0 points/sec at N=2^20, ε=1e-8 vs direct; batched p50/p99 latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--task", default="dht0")
+    ap.add_argument("--N", type=int, default=1 << 20)
+    ap.add_argument("--eps", type=float, default=1e-8)
+    ap.add_argument("--plan-mode", type=int, default=0)
+    ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-direct", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU (this build has no multi-GPU path); "
+              "got --gpus %d" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1501_01652_amd as hank
+    from paper_1501_01652_amd import inputs
+
+    task, N, eps = args.task, args.N, args.eps
+    c_host = inputs.workload(task, N)
+    c = torch.from_numpy(c_host).to("cuda")
+    out = torch.empty_like(c)
+    stream = torch.cuda.current_stream()
+    kw = dict(plan_mode=args.plan_mode, precision=args.precision)
+
+    t0 = time.perf_counter()
+    hank.transform(task, c, eps, out=out, **kw)  # builds the plan
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        hank.transform(task, c, eps, out=out, **kw)
+    torch.cuda.synchronize()
+
+    hank.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        hank.transform(task, c, eps, out=out, stream=stream, **kw)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stats = hank.profile_report()
+    hank.profile(False)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = N * args.steps / elapsed
+    info = hank.plan_info(task, N, eps, **kw)
+
+    kernels = {}
+    for s in stats:
+        avg_ms = s["total_ms"] / max(1, s["launches"])
+        k = {"launches": s["launches"], "avg_ms": avg_ms, "total_ms": s["total_ms"],
+             "ms_per_step": s["total_ms"] / args.steps}
+        if s["name"].startswith("pass") or s["name"] == "near_reduce":
+            k["GB/s"] = s["bytes"] / (s["total_ms"] * 1e-3) / 1e9 if s["total_ms"] > 0 else None
+        if s["name"] == "near":
+            k["entries_per_s"] = s["work"] / (s["total_ms"] * 1e-3) if s["total_ms"] > 0 else None
+        kernels[s["name"]] = k
+    dom = max(stats, key=lambda s: s["total_ms"]) if stats else None
+    roofline = None
+    if dom is not None:
+        if dom["name"] == "near":
+            # FP64 ALU bound: priced at the operation count of one large-argument
+            # J_0 evaluation plus the multiply-add (near-field roofline)
+            flops = dom["work"] * NEAR_FLOPS_PER_ENTRY
+            ach = flops / (dom["total_ms"] * 1e-3) / 1e12
+            roofline = {"kernel": "near", "bound": "alu", "achieved": ach, "peak": FP64_VECTOR_TFLOPS,
+                        "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_TFLOPS, "traffic": None}
+        else:
+            ach = dom["bytes"] / (dom["total_ms"] * 1e-3) / 1e9
+            roofline = {"kernel": dom["name"], "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                        "bytes_per_launch": dom["bytes"] / max(1, dom["launches"])}
+
+    direct = None
+    if not args.no_direct:
+        # the O(N^2) direct sum on the same GPU with the same J_0 (one transform)
+        hank.transform(task, c, eps, out=out, direct=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hank.transform(task, c, eps, out=out, direct=1)
+        torch.cuda.synchronize()
+        td = time.perf_counter() - t0
+        direct = {"points_per_s": N / td, "ms": td * 1e3, "speedup_fast_vs_direct": value / (N / td)}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        nthreads = oracle.default_threads()
+        probe = inputs.sampled_rows(N, 2 * nthreads, seed=inputs.SEED_SAMPLED_ROWS)[:nthreads]
+        t0 = time.perf_counter()
+        oracle.eval_rows(task, c_host, rows=probe, nthreads=nthreads)
+        tp = time.perf_counter() - t0
+        nrows = int(max(nthreads, min(N, args.cpu_seconds / max(tp, 1e-6) * len(probe))))
+        rows = np.sort(np.random.default_rng(inputs.SEED_SAMPLED_ROWS).choice(
+            np.arange(1, N + 1), size=nrows, replace=False))
+        t0 = time.perf_counter()
+        oracle.eval_rows(task, c_host, rows=rows, nthreads=nthreads)
+        tc = time.perf_counter() - t0
+        cpu = {"value": nrows / tc, "unit": "points/s", "cores": nthreads, "kind": "oracle",
+               "sample": "%d of %d output rows (uniform, seed %d), each a full %d-term FP64 direct sum; "
+                         "%.1f s" % (nrows, N, inputs.SEED_SAMPLED_ROWS, N, tc)}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if info["bulk_fp32"] else "f64", "data": "synthetic",
+        "config": {"workload": "%s N=%d eps=%g, c_n iid N(0,1) seed %d, %s plan, %s transform bulk" % (
+            task, N, eps, inputs.SEED_DHT0 if task == "dht0" else 0,
+            "paper" if args.plan_mode == 1 else "tuned", "fp32" if info["bulk_fp32"] else "fp64"),
+            "task": task, "N": N, "eps": eps, "blocks": info["nblocks"],
+            "near_entries": info["near_entries"], "far_transforms": info["far_transforms"],
+            "plan_build_s": plan_s},
+        "roofline": roofline, "cpu_baseline": cpu, "direct_gpu": direct, "kernels": kernels,
+    }
+    print(json.dumps(line))
+
+
+# operation count charged per near-field entry
+NEAR_FLOPS_PER_ENTRY = 60.0
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * hank.h -- C ABI of the MI355X (gfx950) library for fast order-0 Bessel sums
+ *
+ *     f_k = sum_{n=1}^{N} c_n J_0(r_k w_n),   1 <= k <= N,
+ *
+ * after A. Townsend, "A fast analysis-based discrete Hankel transform using
+ * asymptotic expansions" (Sec. 1, eq. (2)).  Three tasks:
+ *
+ *   Schlomilch expansion     w_n = n pi,        r_k = (k-1)/(N-1)      (Sec. 4)
+ *   Fourier-Bessel expansion w_n = j_{0,n},     r_k = (k-1)/(N-1)      (Sec. 5)
+ *   discrete Hankel transform of order 0
+ *                            w_n = j_{0,n},     r_k = j_{0,k}/j_{0,N+1} (Sec. 6, eq. (DHT))
+ *
+ * with j_{0,n} the n-th positive root of J_0.  The Schlomilch and
+ * Fourier-Bessel tasks also exist on the paper's own grid r_k = k/N.
+ *
+ * The result is accurate to O(eps * sum_n |c_n|) (Sec. 1): the library picks
+ * every algorithmic parameter (number of asymptotic terms, block partition,
+ * Neumann/Taylor truncation) from eps and N by the paper's error bounds.
+ *
+ * Conventions shared by every entry point:
+ *   - c and out are DEVICE pointers to FP64 arrays owned by the caller;
+ *     c has N entries (or ldc*nrhs), out has N entries (or ldo*nrhs).
+ *     Column j of a multi-right-hand-side call starts at c + j*ldc and
+ *     out + j*ldo.  out must not overlap c.
+ *   - stream is a hipStream_t (NULL: the default stream).  Calls enqueue work
+ *     on it and return without waiting; out is valid once the stream reaches
+ *     that point.  The first call for a given (task, N, eps, options) builds a
+ *     plan (host parameter selection, device root tables, chirp spectra) and
+ *     synchronises the stream once while doing so; later calls reuse it.
+ *   - On any error nothing is written to out and the call returns a non-zero
+ *     status; hank_last_error() gives a message (per calling thread).
+ *   - Calls from several host threads are serialised inside the library.
+ *     Results are deterministic: the same inputs give bitwise the same out.
+ */
+#ifndef HANK_H
+#define HANK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HANK_OK = 0,
+    HANK_EINVAL = 1,       /* bad argument (null pointer, N, eps, overlap, ...) */
+    HANK_ENOMEM = 2,       /* device allocation failed (nothing was written)     */
+    HANK_EDEVICE = 3,      /* a HIP runtime call failed                           */
+    HANK_EUNSUPPORTED = 4  /* valid request outside what this build supports      */
+} hank_status;
+
+/* Task codes for the generic entry points. */
+enum {
+    HANK_TASK_SCHLOMILCH = 0,            /* w_n = n pi,     r_k = (k-1)/(N-1)        */
+    HANK_TASK_FOURIER_BESSEL = 1,        /* w_n = j_{0,n},  r_k = (k-1)/(N-1)        */
+    HANK_TASK_DHT0 = 2,                  /* w_n = j_{0,n},  r_k = j_{0,k}/j_{0,N+1}  */
+    HANK_TASK_SCHLOMILCH_PAPER_GRID = 3, /* w_n = n pi,     r_k = k/N   (Sec. 4)     */
+    HANK_TASK_FOURIER_BESSEL_PAPER_GRID = 4 /* w_n = j_{0,n}, r_k = k/N (Sec. 5)     */
+};
+
+typedef void* hank_stream_t; /* a hipStream_t */
+
+/* Options; pass NULL for the defaults (all zero). */
+typedef struct {
+    int32_t plan_mode;  /* 0: GPU-tuned partition and per-block truncation (default)
+                           1: the paper's parameters (Table 4, K and T of Sec. 5.1/6) */
+    int32_t precision;  /* 0: auto -- FP32 transform bulk iff eps >= 1e-6, else FP64
+                           1: FP64 bulk   2: FP32 bulk (any eps; accuracy then limited) */
+    int32_t direct;     /* 1: skip the fast method and sum every entry on the GPU (the
+                           O(N^2) direct-summation baseline of Sec. 2.1)             */
+    int32_t prefer_far; /* 1: tuned mode prices direct entries 1000x higher, so the
+                           fast method is used wherever it is valid (small N tests)  */
+} hank_options;
+
+/* ---- The three transforms (Sec. 4, 5, 6) ---------------------------------
+ * c: device, N doubles.  out: device, N doubles.  eps in [1e-15, 1).
+ * Schlomilch and Fourier-Bessel need N >= 2 (their grid (k-1)/(N-1)), the
+ * DHT N >= 1.  N <= 2^24.
+ * Errors: HANK_EINVAL for a null pointer, N out of range, eps not finite or
+ * outside [1e-15, 1), or out overlapping c; HANK_ENOMEM, HANK_EDEVICE. */
+hank_status hank_schlomilch(const double* c, int64_t N, double eps, double* out,
+                            hank_stream_t stream);
+hank_status hank_fourier_bessel(const double* c, int64_t N, double eps, double* out,
+                                hank_stream_t stream);
+hank_status hank_dht0(const double* c, int64_t N, double eps, double* out,
+                      hank_stream_t stream);
+
+/* Generic form: any task code above, nrhs >= 1 right-hand sides stored as
+ * columns (c + j*ldc, out + j*ldo, ldc >= N, ldo >= N), options may be NULL. */
+hank_status hank_transform(int32_t task, const double* c, int64_t N, int64_t nrhs,
+                           int64_t ldc, double eps, double* out, int64_t ldo,
+                           const hank_options* options, hank_stream_t stream);
+
+/* ---- Batched submission ---------------------------------------------------
+ * Enqueue many independent transforms (different tasks, N, eps, nrhs) at once;
+ * their work is merged into shared launches.  Each request follows the
+ * conventions of hank_transform.  All requests are validated before any work
+ * is enqueued; on error nothing is enqueued. */
+typedef struct {
+    int32_t task;
+    int32_t precision; /* as hank_options.precision */
+    int64_t N;
+    int64_t nrhs;
+    int64_t ldc, ldo;
+    double eps;
+    const double* c;
+    double* out;
+} hank_request;
+
+hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t stream);
+
+/* ---- Library state --------------------------------------------------------- */
+const char* hank_last_error(void);   /* message of the calling thread's last error */
+hank_status hank_cache_clear(void);  /* drop every cached plan (device sync first)  */
+int64_t hank_cache_bytes(void);      /* device bytes held by cached plans          */
+
+/* ---- Kernel timing -----------------------------------------------------------
+ * hank_profile(1) brackets every kernel launch of later transforms with HIP
+ * events on the caller's stream (and clears the counters); hank_profile(0)
+ * stops.  hank_profile_report waits for the recorded events and returns one
+ * entry per kernel kind: launches, summed duration, and the ALGORITHMIC bytes
+ * (what the kernel must read and write at minimum) and work units (near field:
+ * matrix entries; far-field passes: FFT points x groups) of those launches.
+ * out may hold max entries; *count receives the number of kinds. */
+typedef struct {
+    char name[24];
+    int64_t launches;
+    double total_ms;
+    double bytes;
+    double work;
+} hank_kernel_stat;
+
+hank_status hank_profile(int32_t enable);
+hank_status hank_profile_report(hank_kernel_stat* out, int32_t max, int32_t* count);
+
+/* ---- Parameter selection, exposed for inspection (host only, no GPU) -----
+ * s_{nu,M}(eps): four fixed-point steps on the remainder bound (Sec. 3.1). */
+double hank_param_s(int32_t nu, int32_t M, double eps);
+/* t_{nu,T}(eps) of Sec. 3.2. */
+double hank_param_t(int32_t nu, int32_t T, double eps);
+/* 2 (eps/5.2)^(1/K) / e, the Neumann perturbation limit of Lemma 3.1. */
+double hank_param_neumann(int32_t K, double eps);
+/* p_K(eps) (eq. (pKe)) and q_T(eps) (eq. (qTe)). */
+double hank_param_pK(int32_t K, double eps);
+double hank_param_qT(int32_t T, double eps);
+
+/* Summary of the plan the library would use (host only, no GPU). */
+typedef struct {
+    int32_t M;             /* asymptotic terms (Table 4) of the paper rule          */
+    int32_t K, T;          /* Neumann and Taylor truncation (Sec. 5.1 / 6); 0 if none */
+    int32_t P;             /* partitions (Table 4; tuned mode: strips per side)     */
+    int32_t nblocks;       /* far-field blocks                                      */
+    double s;              /* s_{nu,M}(eps) used for the partition                  */
+    double alpha, beta;    /* Table 4                                                */
+    int64_t near_entries;  /* matrix entries summed directly                        */
+    int64_t far_transforms;/* complex chirp-z transforms over all blocks            */
+    int64_t fft_points;    /* sum over transforms of their FFT length               */
+    double fft_bytes;      /* algorithmic bytes of the far-field passes             */
+    int32_t first_direct;  /* columns (FB) or rows (DHT) summed directly, paper rule */
+    int32_t bulk_fp32;     /* 1 if the transform bulk runs in FP32                  */
+} hank_plan_summary;
+
+hank_status hank_plan_info(int32_t task, int64_t N, double eps, const hank_options* options,
+                           hank_plan_summary* out);
+
+/* Far-field block k of that plan (0 <= k < nblocks): rows [row0,row1] and
+ * columns [col0,col1] (1-based, inclusive), FFT length and group count. */
+typedef struct {
+    int64_t row0, row1, col0, col1;
+    int64_t fft_len;
+    int32_t groups;
+    int32_t terms;
+    double zmin; /* smallest z = r_k w_n inside the block */
+} hank_block_info;
+
+hank_status hank_plan_block(int32_t task, int64_t N, double eps, const hank_options* options,
+                            int32_t k, hank_block_info* out);
+
+/* ---- Device building blocks, exposed for testing ------------------------- */
+/* b[n-1] = j_{0,n} - (n - 1/4) pi for n = 1..nmax (Lemma 3.2), computed on the
+ * GPU by McMahon's expansion and Newton's method.  b: device, nmax doubles. */
+hank_status hank_root_offsets(int64_t nmax, double* b, hank_stream_t stream);
+/* out[i] = J_0(z[i]) by the library's device evaluator.  z, out: device. */
+hank_status hank_j0(const double* z, int64_t count, double* out, hank_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HANK_H */

@@ -1,0 +1,301 @@
+"""Python binding of libhank: fast order-0 Bessel sums on MI355X.
+
+    f_k = sum_n c_n J_0(r_k w_n)
+
+for Schlomilch expansions, Fourier-Bessel expansions and the order-0 discrete
+Hankel transform (Townsend, "A fast analysis-based discrete Hankel transform
+using asymptotic expansions").  Every function here only marshals arguments
+into the C ABI of ``include/hank.h``; all arithmetic runs in the library's HIP
+kernels.  Tensors are PyTorch tensors on the GPU (PyTorch supplies device
+memory and streams, nothing else).  The library must be built first
+(``paper_1501_01652_amd.build.build()``); without it every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhank.so")
+
+TASKS = {"schlomilch": 0, "fourier_bessel": 1, "dht0": 2,
+         "schlomilch_paper_grid": 3, "fourier_bessel_paper_grid": 4}
+
+STATUS = {0: "HANK_OK", 1: "HANK_EINVAL", 2: "HANK_ENOMEM", 3: "HANK_EDEVICE", 4: "HANK_EUNSUPPORTED"}
+
+EXPORTS = ["hank_schlomilch", "hank_fourier_bessel", "hank_dht0", "hank_transform", "hank_batch",
+           "hank_last_error", "hank_cache_clear", "hank_cache_bytes", "hank_param_s", "hank_param_t",
+           "hank_param_neumann", "hank_param_pK", "hank_param_qT", "hank_plan_info",
+           "hank_plan_block", "hank_root_offsets", "hank_j0", "hank_profile", "hank_profile_report"]
+
+
+class HankError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS.get(status, str(status)), message))
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("plan_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("direct", ctypes.c_int32), ("prefer_far", ctypes.c_int32)]
+
+
+class PlanSummary(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("K", ctypes.c_int32), ("T", ctypes.c_int32),
+                ("P", ctypes.c_int32), ("nblocks", ctypes.c_int32), ("s", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("near_entries", ctypes.c_int64), ("far_transforms", ctypes.c_int64),
+                ("fft_points", ctypes.c_int64), ("fft_bytes", ctypes.c_double),
+                ("first_direct", ctypes.c_int32), ("bulk_fp32", ctypes.c_int32)]
+
+
+class BlockInfo(ctypes.Structure):
+    _fields_ = [("row0", ctypes.c_int64), ("row1", ctypes.c_int64), ("col0", ctypes.c_int64),
+                ("col1", ctypes.c_int64), ("fft_len", ctypes.c_int64), ("groups", ctypes.c_int32),
+                ("terms", ctypes.c_int32), ("zmin", ctypes.c_double)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("work", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("task", ctypes.c_int32), ("precision", ctypes.c_int32), ("N", ctypes.c_int64),
+                ("nrhs", ctypes.c_int64), ("ldc", ctypes.c_int64), ("ldo", ctypes.c_int64),
+                ("eps", ctypes.c_double), ("c", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libhank.so is missing: build it with "
+                                   "paper_1501_01652_amd.build.build()")
+            L = ctypes.CDLL(LIB_PATH)
+            i32, i64, d, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+            for name in ("hank_schlomilch", "hank_fourier_bessel", "hank_dht0"):
+                f = getattr(L, name)
+                f.restype = i32
+                f.argtypes = [p, i64, d, p, p]
+            L.hank_transform.restype = i32
+            L.hank_transform.argtypes = [i32, p, i64, i64, i64, d, p, i64, ctypes.POINTER(Options), p]
+            L.hank_batch.restype = i32
+            L.hank_batch.argtypes = [ctypes.POINTER(Request), i64, p]
+            L.hank_last_error.restype = ctypes.c_char_p
+            L.hank_last_error.argtypes = []
+            L.hank_cache_clear.restype = i32
+            L.hank_cache_bytes.restype = i64
+            for name in ("hank_param_s", "hank_param_t"):
+                f = getattr(L, name)
+                f.restype = d
+                f.argtypes = [i32, i32, d]
+            for name in ("hank_param_neumann", "hank_param_pK", "hank_param_qT"):
+                f = getattr(L, name)
+                f.restype = d
+                f.argtypes = [i32, d]
+            L.hank_plan_info.restype = i32
+            L.hank_plan_info.argtypes = [i32, i64, d, ctypes.POINTER(Options), ctypes.POINTER(PlanSummary)]
+            L.hank_plan_block.restype = i32
+            L.hank_plan_block.argtypes = [i32, i64, d, ctypes.POINTER(Options), i32,
+                                          ctypes.POINTER(BlockInfo)]
+            L.hank_root_offsets.restype = i32
+            L.hank_root_offsets.argtypes = [i64, p, p]
+            L.hank_j0.restype = i32
+            L.hank_j0.argtypes = [p, i64, p, p]
+            L.hank_profile.restype = i32
+            L.hank_profile.argtypes = [i32]
+            L.hank_profile_report.restype = i32
+            L.hank_profile_report.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
+            _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise HankError(status, lib().hank_last_error().decode(errors="replace"))
+
+
+def last_error() -> str:
+    return lib().hank_last_error().decode(errors="replace")
+
+
+def _task(task) -> int:
+    return TASKS[task] if isinstance(task, str) else int(task)
+
+
+def _options(plan_mode=0, precision=0, direct=0, prefer_far=0) -> Options:
+    return Options(int(plan_mode), int(precision), int(direct), int(prefer_far))
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _dev_f64(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("%s must be a float64 GPU tensor" % name)
+    if not t.is_contiguous():
+        raise TypeError("%s must be contiguous" % name)
+    return t
+
+
+def transform(task, c, eps: float, out=None, plan_mode: int = 0, precision: int = 0,
+              direct: int = 0, prefer_far: int = 0, stream=None):
+    """f = J_0(r w^T) c for c of shape (N,) or (nrhs, N) (one right-hand side per row)."""
+    import torch
+    c = _dev_f64(c, "c")
+    if out is None:
+        out = torch.empty_like(c)
+    out = _dev_f64(out, "out")
+    if out.shape != c.shape:
+        raise ValueError("out must have the shape of c")
+    N = c.shape[-1]
+    nrhs = 1 if c.dim() == 1 else c.shape[0]
+    opts = _options(plan_mode, precision, direct, prefer_far)
+    _check(lib().hank_transform(_task(task), ctypes.c_void_p(c.data_ptr()), N, nrhs, N, float(eps),
+                                ctypes.c_void_p(out.data_ptr()), N, ctypes.byref(opts), _stream(stream)))
+    return out
+
+
+def schlomilch(c, eps: float, out=None, stream=None):
+    """f_k = sum_n c_n J_0((k-1)/(N-1) * n pi)  (Sec. 4)."""
+    import torch
+    c = _dev_f64(c, "c")
+    out = _dev_f64(torch.empty_like(c) if out is None else out, "out")
+    _check(lib().hank_schlomilch(ctypes.c_void_p(c.data_ptr()), c.numel(), float(eps),
+                                 ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def fourier_bessel(c, eps: float, out=None, stream=None):
+    """f_k = sum_n c_n J_0((k-1)/(N-1) * j_{0,n})  (Sec. 5)."""
+    import torch
+    c = _dev_f64(c, "c")
+    out = _dev_f64(torch.empty_like(c) if out is None else out, "out")
+    _check(lib().hank_fourier_bessel(ctypes.c_void_p(c.data_ptr()), c.numel(), float(eps),
+                                     ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def dht0(c, eps: float, out=None, stream=None):
+    """f_k = sum_n c_n J_0(j_{0,k} j_{0,n} / j_{0,N+1})  (Sec. 6, eq. (DHT))."""
+    import torch
+    c = _dev_f64(c, "c")
+    out = _dev_f64(torch.empty_like(c) if out is None else out, "out")
+    _check(lib().hank_dht0(ctypes.c_void_p(c.data_ptr()), c.numel(), float(eps),
+                           ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def batch(requests, stream=None):
+    """Submit many transforms at once.  requests: iterable of dicts with keys
+    task, c, out, eps and optionally precision (c, out of shape (N,) or (nrhs, N))."""
+    reqs = list(requests)
+    arr = (Request * max(1, len(reqs)))()
+    for i, r in enumerate(reqs):
+        c = _dev_f64(r["c"], "c")
+        o = _dev_f64(r["out"], "out")
+        N = c.shape[-1]
+        nrhs = 1 if c.dim() == 1 else c.shape[0]
+        arr[i] = Request(_task(r["task"]), int(r.get("precision", 0)), N, nrhs, N, N, float(r["eps"]),
+                         c.data_ptr(), o.data_ptr())
+    _check(lib().hank_batch(arr, len(reqs), _stream(stream)))
+
+
+def plan_info(task, N: int, eps: float, plan_mode: int = 0, precision: int = 0, direct: int = 0,
+              prefer_far: int = 0) -> dict:
+    """Parameters and costs of the plan the library would use (host only)."""
+    s = PlanSummary()
+    opts = _options(plan_mode, precision, direct, prefer_far)
+    _check(lib().hank_plan_info(_task(task), int(N), float(eps), ctypes.byref(opts), ctypes.byref(s)))
+    return {name: getattr(s, name) for name, _ in PlanSummary._fields_}
+
+
+def plan_block(task, N: int, eps: float, k: int, plan_mode: int = 0, precision: int = 0,
+               prefer_far: int = 0) -> dict:
+    b = BlockInfo()
+    opts = _options(plan_mode, precision, 0, prefer_far)
+    _check(lib().hank_plan_block(_task(task), int(N), float(eps), ctypes.byref(opts), int(k), ctypes.byref(b)))
+    return {name: getattr(b, name) for name, _ in BlockInfo._fields_}
+
+
+def plan_blocks(task, N: int, eps: float, plan_mode: int = 0, precision: int = 0,
+                prefer_far: int = 0) -> list:
+    n = plan_info(task, N, eps, plan_mode, precision, prefer_far=prefer_far)["nblocks"]
+    return [plan_block(task, N, eps, k, plan_mode, precision, prefer_far) for k in range(n)]
+
+
+def param_s(nu: int, M: int, eps: float) -> float:
+    return lib().hank_param_s(int(nu), int(M), float(eps))
+
+
+def param_t(nu: int, T: int, eps: float) -> float:
+    return lib().hank_param_t(int(nu), int(T), float(eps))
+
+
+def param_neumann(K: int, eps: float) -> float:
+    return lib().hank_param_neumann(int(K), float(eps))
+
+
+def param_pK(K: int, eps: float) -> float:
+    return lib().hank_param_pK(int(K), float(eps))
+
+
+def param_qT(T: int, eps: float) -> float:
+    return lib().hank_param_qT(int(T), float(eps))
+
+
+def root_offsets(nmax: int, out=None, stream=None):
+    """b_n = j_{0,n} - (n - 1/4) pi for n = 1..nmax, computed on the GPU."""
+    import torch
+    if out is None:
+        out = torch.empty(int(nmax), dtype=torch.float64, device="cuda")
+    out = _dev_f64(out, "out")
+    _check(lib().hank_root_offsets(int(nmax), ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def j0(z, out=None, stream=None):
+    """J_0 by the library's device evaluator."""
+    import torch
+    z = _dev_f64(z, "z")
+    out = _dev_f64(torch.empty_like(z) if out is None else out, "out")
+    _check(lib().hank_j0(ctypes.c_void_p(z.data_ptr()), z.numel(), ctypes.c_void_p(out.data_ptr()),
+                         _stream(stream)))
+    return out
+
+
+def cache_clear():
+    _check(lib().hank_cache_clear())
+
+
+def cache_bytes() -> int:
+    return int(lib().hank_cache_bytes())
+
+
+def profile(enable: bool = True):
+    """Start (and reset) or stop per-kernel event timing."""
+    _check(lib().hank_profile(1 if enable else 0))
+
+
+def profile_report() -> list:
+    """[{name, launches, total_ms, bytes, work}] for the kernels timed since profile(True)."""
+    arr = (KernelStat * 16)()
+    n = ctypes.c_int32(0)
+    _check(lib().hank_profile_report(arr, 16, ctypes.byref(n)))
+    return [{"name": arr[i].name.decode(), "launches": arr[i].launches, "total_ms": arr[i].total_ms,
+             "bytes": arr[i].bytes, "work": arr[i].work} for i in range(min(n.value, 16))]

@@ -1,0 +1,126 @@
+// fft_device.h -- power-of-two complex FFTs held in registers and exchanged
+// through LDS (Stockham autosort, radix 8 with one radix-2/4 stage).
+//
+// A transform of length LEN is computed by NT = LEN/R threads; thread tt
+// holds the R points x[tt + r*NT], r < R, before and after the call (natural
+// order both ways).  SIGN = -1 is the forward DFT X_m = sum_j x_j e^{-2 pi i jm/LEN},
+// SIGN = +1 the unnormalised inverse.  Every stage is one radix butterfly per
+// register group, one LDS write and one LDS read; `sh` must hold
+// LEN + LEN/8 elements for this transform and every thread of the workgroup
+// must call the function (it synchronises the workgroup).
+#pragma once
+
+#include "device_common.h"
+
+namespace hank {
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
+
+template <typename F, int SIGN>
+__device__ __forceinline__ cx<F> mul_si(cx<F> a) { // a * (SIGN i)
+    return SIGN < 0 ? mk(a.y, -a.x) : mk(-a.y, a.x);
+}
+
+template <typename F, int RS, int SIGN>
+__device__ __forceinline__ void dft_small(cx<F> (&a)[RS]) {
+    if constexpr (RS == 2) {
+        cx<F> t = a[0];
+        a[0] = t + a[1];
+        a[1] = t - a[1];
+    } else if constexpr (RS == 4) {
+        cx<F> t0 = a[0] + a[2], t1 = a[0] - a[2], t2 = a[1] + a[3], t3 = mul_si<F, SIGN>(a[1] - a[3]);
+        a[0] = t0 + t2;
+        a[1] = t1 + t3;
+        a[2] = t0 - t2;
+        a[3] = t1 - t3;
+    } else { // RS == 8: two DFT4 and the W8 twiddles
+        const F c = F(0.70710678118654752440);
+        cx<F> e[4] = {a[0], a[2], a[4], a[6]}, o[4] = {a[1], a[3], a[5], a[7]};
+        dft_small<F, 4, SIGN>(e);
+        dft_small<F, 4, SIGN>(o);
+        cx<F> o1 = mk(c * (o[1].x - F(SIGN) * o[1].y), c * (F(SIGN) * o[1].x + o[1].y));
+        cx<F> o2 = mul_si<F, SIGN>(o[2]);
+        cx<F> o3 = mk(c * (-o[3].x - F(SIGN) * o[3].y), c * (F(SIGN) * o[3].x - o[3].y));
+        a[0] = e[0] + o[0];
+        a[4] = e[0] - o[0];
+        a[1] = e[1] + o1;
+        a[5] = e[1] - o1;
+        a[2] = e[2] + o2;
+        a[6] = e[2] - o2;
+        a[3] = e[3] + o3;
+        a[7] = e[3] - o3;
+    }
+}
+
+// twiddle e^{SIGN 2 pi i t / TW_SMALL}
+template <typename F, int SIGN>
+__device__ __forceinline__ cx<F> tw_small(int t) {
+    double c = g_tab.tw_small[t][0], s = g_tab.tw_small[t][1];
+    return mk(F(c), F(SIGN < 0 ? s : -s));
+}
+
+template <typename F, int LEN, int R, int RS, int SIGN>
+__device__ __forceinline__ void fft_stage(cx<F> (&v)[R], cx<F>* sh, int tt, int Ns) {
+    constexpr int NT = LEN / R;
+    constexpr int NB = R / RS;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int j = tt + q * NT;
+        cx<F> a[RS];
+#pragma unroll
+        for (int s = 0; s < RS; ++s) a[s] = v[q + s * NB];
+        const int kk = j & (Ns - 1);
+        if (Ns > 1) {
+            cx<F> w1 = tw_small<F, SIGN>(kk * (TW_SMALL / (Ns * RS)));
+            cx<F> w = w1;
+#pragma unroll
+            for (int s = 1; s < RS; ++s) {
+                a[s] = cmul(a[s], w);
+                if (s + 1 < RS) w = cmul(w, w1);
+            }
+        }
+        dft_small<F, RS, SIGN>(a);
+        const int base = (j - kk) * RS + kk;
+#pragma unroll
+        for (int s = 0; s < RS; ++s) sh[lds_pad(base + s * Ns)] = a[s];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = sh[lds_pad(tt + r * NT)];
+    __syncthreads();
+}
+
+template <int N>
+struct ilog2 {
+    static constexpr int v = 1 + ilog2<N / 2>::v;
+};
+template <>
+struct ilog2<1> {
+    static constexpr int v = 0;
+};
+
+template <typename F, int LEN, int R, int SIGN>
+__device__ __forceinline__ void fft_reg(cx<F> (&v)[R], cx<F>* sh, int tt) {
+    constexpr int LG = ilog2<LEN>::v, LR = ilog2<R>::v;
+    static_assert((1 << LG) == LEN && (1 << LR) == R && LEN >= R, "power-of-two sizes");
+    int Ns = 1;
+#pragma unroll
+    for (int st = 0; st < LG / LR; ++st) {
+        fft_stage<F, LEN, R, R, SIGN>(v, sh, tt, Ns);
+        Ns *= R;
+    }
+    if constexpr (LG % LR != 0) fft_stage<F, LEN, R, (1 << (LG % LR)), SIGN>(v, sh, tt, Ns);
+}
+
+// e^{-2 pi i e / L} for 0 <= e < L, L = 2^lg <= 2^23, from the two-level table
+template <typename F>
+__device__ __forceinline__ cx<F> tw_big(int64_t e, int shift /* 23 - lg */) {
+    int64_t E = e << shift;
+    int hi = (int)(E >> 12), lo = (int)(E & (TW_LO - 1));
+    cx<double> a = mk(g_tab.tw_hi[hi][0], g_tab.tw_hi[hi][1]);
+    cx<double> b = mk(g_tab.tw_lo[lo][0], g_tab.tw_lo[lo][1]);
+    cx<double> p = cmul(a, b);
+    return mk(F(p.x), F(p.y));
+}
+
+} // namespace hank

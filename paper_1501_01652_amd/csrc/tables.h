@@ -1,0 +1,29 @@
+// tables.h -- layout of the constant tables shared by host and device code.
+#pragma once
+
+namespace hank {
+
+constexpr int J0_SERIES_TERMS = 14;     // sum_t (-1)^t (z^2/4)^t/(t!)^2 for z < 2
+constexpr int J0_TAYLOR_INTERVALS = 36; // [2, 20) in steps of 1/2
+constexpr int J0_TAYLOR_DEG = 14;       // coefficients per interval (degree 13)
+constexpr double J0_TAYLOR_Z0 = 2.0;
+constexpr double J0_TAYLOR_H = 0.5;
+constexpr double J0_ASY_Z = 20.0;       // Hankel branch from here on
+constexpr int HANKEL_TERMS = 26;        // a_0 .. a_25 for nu = 0, 1
+constexpr int TW_SMALL = 8192;          // twiddles inside one LDS-resident FFT
+constexpr int TW_BIG = 1 << 23;         // largest four-step FFT length
+constexpr int TW_LO = 4096;
+constexpr int TW_HI = TW_BIG / TW_LO;   // 2048
+
+struct DeviceTables {
+    double ser[J0_SERIES_TERMS];
+    double tay[J0_TAYLOR_INTERVALS][J0_TAYLOR_DEG];
+    double hank[2][HANKEL_TERMS];
+    double tw_small[TW_SMALL][2];
+    double tw_hi[TW_HI][2];
+    double tw_lo[TW_LO][2];
+};
+
+void build_tables(DeviceTables& t);
+
+} // namespace hank

@@ -1,0 +1,165 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerance (the paper's accuracy statement, Sec. 1 and Figs. 6-7): every result
+must satisfy |f_gpu - f_oracle|_inf <= C * eps * sum_n |c_n| with C = 10; the
+measured C is printed for every case.  One-hot coefficient vectors make the
+bound per matrix entry (sum |c| = 1)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1501_01652_amd as hank
+from paper_1501_01652_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+C_TOL = 10.0
+
+TASKS = ["schlomilch", "fourier_bessel", "dht0", "schlomilch_paper_grid", "fourier_bessel_paper_grid"]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+_oracle_cache = {}
+
+
+def oracle_full(task, N, seed):
+    key = (task, N, seed)
+    if key not in _oracle_cache:
+        c = inputs.coefficients("gauss", N, seed)
+        _oracle_cache[key] = (c, oracle.eval_rows(task, c))
+    return _oracle_cache[key]
+
+
+def measured_C(f, ref, eps, c):
+    return float(np.max(np.abs(f - ref)) / (eps * np.sum(np.abs(c))))
+
+
+def test_device_j0_matches_oracle():
+    rng = np.random.default_rng(7)
+    z = np.concatenate([np.linspace(0, 25, 20001), rng.uniform(0, 60, 20000),
+                        10 ** rng.uniform(1.5, 6.5, 20000)])
+    got = host(hank.j0(dev(z)))
+    ref = oracle.j0(z)
+    # large plain arguments carry the rounding of z itself: allow ulp(z)
+    tol = 4e-16 + 2.3e-16 * z * (z >= 20)
+    assert np.all(np.abs(got - ref) <= tol), float(np.max(np.abs(got - ref) - tol))
+
+
+def test_device_roots_match_oracle():
+    nmax = (1 << 20) + 1
+    got = host(hank.root_offsets(nmax))
+    ref = oracle.root_offsets(nmax)
+    err = np.abs(got - ref)
+    # b_n for the first roots comes from z - (n - 1/4) pi and carries ulp(z)
+    assert np.all(err <= 4e-16 + 1e-14 * np.abs(ref)), float(np.max(err))
+    n = np.arange(1, nmax + 1)
+    assert np.all(got >= 0) and np.all(got <= 1.0 / (8 * (n - 0.25) * np.pi) * (1 + 1e-13))
+
+
+@pytest.mark.parametrize("task", TASKS)
+@pytest.mark.parametrize("N", [2, 17, 100, 700, 2500])
+@pytest.mark.parametrize("eps", [1e-4, 1e-8, 1e-14])
+@pytest.mark.parametrize("mode", ["tuned", "far", "paper"])
+def test_parity_all_rows(task, N, eps, mode):
+    if N == 2 and task == "dht0":
+        N = 1
+    c, ref = oracle_full(task, N, 1000 + N)
+    kw = {"tuned": {}, "far": {"prefer_far": 1}, "paper": {"plan_mode": 1}}[mode]
+    f = host(hank.transform(task, dev(c), eps, **kw))
+    Cm = measured_C(f, ref, eps, c)
+    nb = hank.plan_info(task, N, eps, **kw)["nblocks"]
+    print("%s N=%d eps=%g mode=%s blocks=%d measured C=%.3g" % (task, N, eps, mode, nb, Cm))
+    assert Cm <= C_TOL
+
+
+@pytest.mark.parametrize("task,N,eps", [("schlomilch", 3000, 1e-14), ("fourier_bessel", 3000, 1e-8),
+                                        ("dht0", 3000, 1e-14), ("dht0", 3000, 1e-4),
+                                        ("fourier_bessel_paper_grid", 1500, 1e-14)])
+@pytest.mark.parametrize("mode", ["far", "paper"])
+def test_one_hot_every_column_class(task, N, eps, mode):
+    """c = e_n gives f_k = J_0(r_k w_n) for every k: a per-entry check in the
+    first columns, at both edges of every block's column range and at n = N."""
+    kw = {"far": {"prefer_far": 1}, "paper": {"plan_mode": 1}}[mode]
+    cols = {1, 2, N}
+    info = hank.plan_info(task, N, eps, **kw)
+    cols.add(max(1, info["first_direct"]))
+    cols.add(min(N, info["first_direct"] + 1))
+    for b in hank.plan_blocks(task, N, eps, **kw):
+        for n in (b["col0"] - 1, b["col0"], b["col0"] + 1, b["col1"]):
+            if 1 <= n <= N:
+                cols.add(n)
+    assert len(cols) > 5
+    worst = 0.0
+    for n in sorted(cols):
+        c = np.zeros(N)
+        c[n - 1] = 1.0
+        f = host(hank.transform(task, dev(c), eps, **kw))
+        ref = oracle.eval_rows(task, c)
+        worst = max(worst, float(np.max(np.abs(f - ref))))
+    print("%s N=%d eps=%g %s columns=%d worst entry error %.3g (%.3g eps)" %
+          (task, N, eps, mode, len(cols), worst, worst / eps))
+    assert worst <= C_TOL * eps
+
+
+@pytest.mark.parametrize("task", ["schlomilch", "fourier_bessel", "dht0"])
+def test_direct_mode_is_the_plain_sum(task):
+    N = 1500
+    c, ref = oracle_full(task, N, 77)
+    f = host(hank.transform(task, dev(c), 1e-14, direct=1))
+    assert np.max(np.abs(f - ref)) <= 1e-15 * np.sum(np.abs(c))
+
+
+def test_deterministic_and_linear():
+    N = 4000
+    rng = np.random.default_rng(11)
+    a, b = rng.standard_normal(N), rng.standard_normal(N)
+    for task in ("fourier_bessel", "dht0"):
+        fa = host(hank.transform(task, dev(a), 1e-8, prefer_far=1))
+        fa2 = host(hank.transform(task, dev(a), 1e-8, prefer_far=1))
+        assert np.array_equal(fa, fa2)
+        fb = host(hank.transform(task, dev(b), 1e-8, prefer_far=1))
+        fab = host(hank.transform(task, dev(2.0 * a - 3.0 * b), 1e-8, prefer_far=1))
+        assert np.max(np.abs(fab - (2.0 * fa - 3.0 * fb))) <= 1e-12 * np.sum(np.abs(a) + np.abs(b))
+
+
+def test_multiple_right_hand_sides():
+    N, nrhs = 3000, 5
+    rng = np.random.default_rng(12)
+    C = rng.standard_normal((nrhs, N))
+    F = host(hank.transform("dht0", dev(C), 1e-8))
+    for j in range(nrhs):
+        fj = host(hank.transform("dht0", dev(C[j]), 1e-8))
+        assert np.array_equal(F[j], fj)
+
+
+def test_named_entry_points_match_generic():
+    rng = np.random.default_rng(13)
+    for name, fn in (("schlomilch", hank.schlomilch), ("fourier_bessel", hank.fourier_bessel),
+                     ("dht0", hank.dht0)):
+        c = rng.standard_normal(2048)
+        assert np.array_equal(host(fn(dev(c), 1e-8)), host(hank.transform(name, dev(c), 1e-8)))
+
+
+def test_errors_leave_output_untouched():
+    c = dev(np.ones(100))
+    out = dev(np.full(100, 7.0))
+    for bad in [dict(eps=0.0), dict(eps=1.5), dict(eps=1e-16), dict(eps=float("inf"))]:
+        with pytest.raises(hank.HankError) as e:
+            hank.transform("dht0", c, bad["eps"], out=out)
+        assert e.value.status == 1
+    with pytest.raises(hank.HankError):
+        hank.transform("schlomilch", dev(np.ones(1)), 1e-8)
+    with pytest.raises(hank.HankError):  # out overlapping c
+        hank.transform("dht0", c, 1e-8, out=c)
+    assert np.all(host(out) == 7.0)

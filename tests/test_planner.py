@@ -1,0 +1,175 @@
+"""Host logic of the GPU library (no GPU needed): the parameter formulas against
+the numbers the paper prints, the partition's structure, and the C ABI's
+exported symbols."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1501_01652_amd as hank
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _rows(name):
+    out = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.split("#")[0].split()
+        if line:
+            out.append(line)
+    return out
+
+
+def _worked():
+    return {r[0]: float(r[1]) for r in _rows("worked_numbers.txt")}
+
+
+def test_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "hank.h")).read()
+    declared = sorted(set(re.findall(r"\b(hank_[A-Za-z0-9_]+)\s*\(", header)))
+    assert declared, "no declarations found"
+    L = hank.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(hank.EXPORTS) == declared
+
+
+def test_table1_s():
+    """Table 1 (Sec. 3.1): s_{nu,M}(1e-15) to every printed digit."""
+    for row in _rows("table1_s_nuM_1e-15.txt"):
+        nu = int(row[0])
+        for M, printed in zip(range(3, 13), row[1:]):
+            assert round(hank.param_s(nu, M, 1e-15), 1) == float(printed), (nu, M)
+
+
+def _round_like(value, printed):
+    if "e" in printed:
+        return float("%.0e" % value) == float(printed)
+    return round(value, 3) == float(printed)
+
+
+def test_table2_t():
+    """Table 2 (Sec. 3.2): t_{nu,T}(1e-15) as printed."""
+    for row in _rows("table2_t_nuT_1e-15.txt"):
+        nu = int(row[0])
+        for T, printed in zip(range(1, 10), row[1:]):
+            assert _round_like(hank.param_t(nu, T, 1e-15), printed), (nu, T)
+
+
+def test_table3_neumann():
+    """Table 3 (Sec. 3.3): 2 (eps/5.2)^(1/K)/e at 1e-15 as printed."""
+    for K, printed in _rows("table3_neumann_1e-15.txt"):
+        assert _round_like(hank.param_neumann(int(K), 1e-15), printed), K
+
+
+def test_worked_numbers():
+    w = _worked()
+    # the text truncates to one decimal: p_6 = 22.76.. reads "22.7", q_3 = 3.71.. reads "3.7"
+    assert math.floor(hank.param_pK(6, 1e-15) * 10) / 10 == w["pK_6_1e-15"]
+    assert math.floor(hank.param_qT(3, 1e-15) * 10) / 10 == w["qT_3_1e-15"]
+    info = hank.plan_info("fourier_bessel", 4096, 1e-15, plan_mode=1)
+    assert info["K"] == w["K_at_1e-15"] and info["T"] == w["T_at_1e-15"]
+    K, T = info["K"], info["T"]
+    assert (2 * K - 1) * T == w["terms_unrearranged"] and 2 * T + K - 2 == w["terms_rearranged"]
+    assert info["M"] == w["M_at_1e-15"]
+    # the first floor(max(p_K, q_T)) columns are summed directly (Sec. 5.1)
+    assert info["first_direct"] == math.floor(max(hank.param_pK(6, 1e-15), hank.param_qT(3, 1e-15)))
+
+
+def test_partitions_vanish_up_to_158():
+    """Sec. 4.3: at eps = 1e-15 the paper's rule gives P = 0 exactly for N <= 158."""
+    nmax = int(_worked()["P_zero_up_to_N"])
+    for N in (100, 150, nmax):
+        assert hank.plan_info("schlomilch_paper_grid", N, 1e-15, plan_mode=1)["P"] == 0, N
+    assert hank.plan_info("schlomilch_paper_grid", nmax + 1, 1e-15, plan_mode=1)["P"] == 1
+
+
+def test_table4_rules():
+    for eps in (1e-3, 1e-4, 1e-8, 1e-14, 1e-15):
+        info = hank.plan_info("schlomilch", 5000, eps, plan_mode=1)
+        assert info["M"] == max(math.floor(0.3 * math.log(1 / eps)), 3)
+        assert info["alpha"] == pytest.approx(math.sqrt(info["s"] / math.pi))
+        assert info["beta"] == pytest.approx(min(3 / math.log(5000), 1.0))
+    # log base: natural log reproduces M = 10 at 1e-15 (a base-10 log would give 3)
+    assert hank.plan_info("schlomilch", 5000, 1e-15, plan_mode=1)["M"] == 10
+
+
+def test_dht_truncation_rule():
+    """Sec. 6: smallest K, T with 1.01 max(p_K, q_T) <= 30; first floor(1.01 max) rows direct."""
+    for eps in (1e-4, 1e-8, 1e-14):
+        info = hank.plan_info("dht0", 1 << 20, eps, plan_mode=1)
+        K, T = info["K"], info["T"]
+        assert 1.01 * hank.param_pK(K, eps) <= 30 and (K == 1 or 1.01 * hank.param_pK(K - 1, eps) > 30)
+        assert 1.01 * hank.param_qT(T, eps) <= 30 and (T == 1 or 1.01 * hank.param_qT(T - 1, eps) > 30)
+        assert info["first_direct"] == math.floor(1.01 * max(hank.param_pK(K, eps), hank.param_qT(T, eps)))
+
+
+def _ztilde(task, N, k, n):
+    if task == "dht0":
+        return math.pi * (4 * k - 1) * (4 * n - 1) / (4 * (4 * N + 3))
+    if task == "fourier_bessel":
+        return math.pi * (k - 1) * (4 * n - 1) / (4 * (N - 1))
+    return math.pi * (k - 1) * n / (N - 1)
+
+
+@pytest.mark.parametrize("task,N,eps", [("schlomilch", 4096, 1e-14), ("fourier_bessel", 65536, 1e-8),
+                                        ("dht0", 1 << 20, 1e-8), ("dht0", 3000, 1e-4),
+                                        ("fourier_bessel", 777, 1e-14)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_partition_structure(task, N, eps, mode):
+    """Blocks are disjoint rectangles, their far columns form a suffix of every
+    row (so the rest is a staircase near field), every block corner lies in the
+    region where the expansion is used, and far + near covers all N^2 entries."""
+    info = hank.plan_info(task, N, eps, plan_mode=mode)
+    blocks = hank.plan_blocks(task, N, eps, plan_mode=mode)
+    far = 0
+    for b in blocks:
+        assert 1 <= b["row0"] <= b["row1"] <= N and 1 <= b["col0"] <= b["col1"] <= N
+        assert b["col1"] == N or b["row1"] == N
+        far += (b["row1"] - b["row0"] + 1) * (b["col1"] - b["col0"] + 1)
+        assert b["fft_len"] >= (b["row1"] - b["row0"] + 1) + (b["col1"] - b["col0"] + 1) - 1
+        z = _ztilde(task, N, b["row0"], b["col0"])
+        assert z == pytest.approx(b["zmin"], rel=1e-12)
+        if mode == 1:
+            assert z >= info["s"] * (1 - 1e-12)
+            if task == "fourier_bessel":
+                assert b["col0"] > info["first_direct"]
+            if task == "dht0":
+                assert b["row0"] > info["first_direct"]
+    for i, a in enumerate(blocks):
+        for b in blocks[i + 1:]:
+            overlap = (a["row0"] <= b["row1"] and b["row0"] <= a["row1"] and
+                       a["col0"] <= b["col1"] and b["col0"] <= a["col1"])
+            assert not overlap
+    assert far + info["near_entries"] == N * N
+
+
+def test_paper_plan_matches_survey_counts():
+    """Paper mode, DHT at N = 2^20 and eps = 1e-8: K = 4, T = 2, so 2T+K-2 = 6
+    perturbation degrees per level and (2T+K-2)^2 = 36 combined kernels; grouped by
+    output power this is 6 x 15 = 90 complex transforms per block."""
+    info = hank.plan_info("dht0", 1 << 20, 1e-8, plan_mode=1)
+    assert (info["K"], info["T"], info["M"]) == (4, 2, 5)
+    for b in hank.plan_blocks("dht0", 1 << 20, 1e-8, plan_mode=1):
+        assert b["groups"] == 6 * (2 * info["M"] + 2 * info["T"] + info["K"] - 3)
+
+
+def test_direct_option_has_no_blocks():
+    info = hank.plan_info("dht0", 5000, 1e-8, direct=1)
+    assert info["nblocks"] == 0 and info["near_entries"] == 5000 * 5000
+
+
+def test_invalid_plan_arguments():
+    with pytest.raises(hank.HankError):
+        hank.plan_info("schlomilch", 1, 1e-8)
+    with pytest.raises(hank.HankError):
+        hank.plan_info("dht0", 100, 0.0)
+    with pytest.raises(hank.HankError):
+        hank.plan_info("dht0", 100, 1e-16)
+    with pytest.raises(hank.HankError):
+        hank.plan_info("dht0", 100, float("nan"))
+    with pytest.raises(hank.HankError):
+        hank.plan_info(9, 100, 1e-8)
