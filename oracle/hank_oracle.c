@@ -376,6 +376,8 @@ typedef struct {
     const double* c;
     const double* b; /* root offsets b_1..b_{N+1} (tasks 1, 2, 4) */
     const int64_t* rows;
+    const int64_t* nz; /* 1-based columns with c_n != 0, ascending */
+    int64_t nnz;
     double* out;
     int64_t nrows;
     int64_t next; /* shared work counter */
@@ -424,9 +426,9 @@ static arg_t make_arg(const job_t* J, int64_t k, int64_t n) {
 
 static double row_sum(const job_t* J, int64_t k) {
     double s = 0.0, comp = 0.0; /* Neumaier */
-    for (int64_t n = 1; n <= J->N; ++n) {
+    for (int64_t i = 0; i < J->nnz; ++i) { /* columns with c_n = 0 add nothing */
+        int64_t n = J->nz[i];
         double cn = J->c[n - 1];
-        if (cn == 0.0) continue;
         arg_t a = make_arg(J, k, n);
         double t = cn * j0_arg(&a);
         double u = s + t;
@@ -468,6 +470,13 @@ int or_eval_rows(int task, int64_t N, const double* c, const double* b, int64_t 
     for (int64_t i = 0; i < nrows; ++i)
         if (rows[i] < 1 || rows[i] > N) return -1;
     job_t J;
+    int64_t* nz = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
+    if (!nz) return -1;
+    int64_t nnz = 0;
+    for (int64_t n = 1; n <= N; ++n)
+        if (c[n - 1] != 0.0) nz[nnz++] = n;
+    J.nz = nz;
+    J.nnz = nnz;
     J.task = task;
     J.N = N;
     J.c = c;
@@ -483,6 +492,7 @@ int or_eval_rows(int task, int64_t N, const double* c, const double* b, int64_t 
     for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, worker, &J);
     for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
     pthread_mutex_destroy(&J.mu);
+    free(nz);
     return 0;
 }
 

@@ -24,14 +24,16 @@ __device__ DeviceTables g_tab;
 // ---------------------------------------------------------------------------
 // Roots
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double j0_taylor_deriv(double z) { // J_0'(z), 2 <= z < 20
-    int i = (int)((z - J0_TAYLOR_Z0) * (1.0 / J0_TAYLOR_H));
-    i = i < 0 ? 0 : (i >= J0_TAYLOR_INTERVALS ? J0_TAYLOR_INTERVALS - 1 : i);
-    double dz = z - (J0_TAYLOR_Z0 + (i + 0.5) * J0_TAYLOR_H);
+// J_0 and J_0' from Taylor piece i at offset dz from its centre
+__device__ __forceinline__ void j0_taylor_piece(int i, double dz, double* J, double* dJ) {
     const double* t = g_tab.tay[i];
-    double p = (J0_TAYLOR_DEG - 1) * t[J0_TAYLOR_DEG - 1];
-    for (int u = J0_TAYLOR_DEG - 2; u >= 1; --u) p = fma(p, dz, u * t[u]);
-    return p;
+    double p = t[J0_TAYLOR_DEG - 1], d = (J0_TAYLOR_DEG - 1) * t[J0_TAYLOR_DEG - 1];
+    for (int u = J0_TAYLOR_DEG - 2; u >= 1; --u) {
+        p = fma(p, dz, t[u]);
+        d = fma(d, dz, u * t[u]);
+    }
+    *J = fma(p, dz, t[0]);
+    *dJ = d;
 }
 
 __global__ void k_roots(int64_t nmax, double* b) {
@@ -42,9 +44,21 @@ __global__ void k_roots(int64_t nmax, double* b) {
     double bi = 1.0 / beta;
     double x = bi * (0.125 - (31.0 / 384.0) * bi * bi);
     if (beta < 21.0) {
-        double z = beta + x;
-        for (int it = 0; it < 8; ++it) z -= j0_small(z) / j0_taylor_deriv(z);
-        x = z - beta;
+        // Newton on b itself with (n - 1/4) pi = beta + beta_lo carried exactly, so
+        // the Taylor offset dz = (beta - z_c) + (beta_lo + b) keeps b's precision
+        const double pi_lo = 1.2246467991473532e-16;
+        const double nq = (double)n - 0.25;
+        const double beta_lo = fma(nq, M_PI, -beta) + nq * pi_lo;
+        for (int it = 0; it < 10; ++it) {
+            double z = beta + x;
+            int i = (int)((z - J0_TAYLOR_Z0) * (1.0 / J0_TAYLOR_H));
+            i = i < 0 ? 0 : (i >= J0_TAYLOR_INTERVALS ? J0_TAYLOR_INTERVALS - 1 : i);
+            const double zc = J0_TAYLOR_Z0 + (i + 0.5) * J0_TAYLOR_H;
+            const double dz = (beta - zc) + (beta_lo + x);
+            double J, dJ;
+            j0_taylor_piece(i, dz, &J, &dJ);
+            x -= J / dJ;
+        }
     } else {
         // J_0 ~ A(-1)^n (P0 sin b + Q0 cos b), J_1 ~ A(-1)^n (-P1 cos b + Q1 sin b)
         // (eq. (HankelExpansion) at z = (n-1/2)pi + b + pi/4); Newton: b += J_0/J_1
