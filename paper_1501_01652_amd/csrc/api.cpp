@@ -140,9 +140,23 @@ GridArgs grid_args(const Grid& g) {
     long double pd = PI / (long double)g.D;
     a.piD_hi = double(pd);
     a.piD_lo = double(pd - (long double)a.piD_hi);
+    a.invD = double(1.0L / (long double)g.D);
     a.row_pert = g.row_pert;
     a.col_pert = g.col_pert;
     return a;
+}
+
+// Branches and Hankel term count of a near-field tile from bounds on z over it:
+// z >= z~ (the perturbations e_k, b_n are non-negative) and z <= z~ + 0.25.
+int32_t near_flags(const Grid& g, const NearTile& t) {
+    const double zlo = g.ztilde(t.k0, t.n0);
+    const double zhi = g.ztilde(t.k0 + t.nk - 1, t.n1 - 1) + 0.25;
+    int32_t f = 0;
+    if (zlo < J0_ASY_Z) f |= 1;
+    if (zhi >= J0_ASY_Z) f |= 2;
+    const double za = std::max(zlo, J0_ASY_Z);
+    const int M = za < 28.0 ? 12 : za < 44.0 ? 8 : za < 65.0 ? 6 : za < 123.0 ? 5 : za < 376.0 ? 4 : 3;
+    return f | (M << 8);
 }
 
 hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
@@ -174,6 +188,7 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
                 t.nk = r.nk;
                 t.n0 = n;
                 t.n1 = std::min(seg.ncut, n + NEAR_CHUNK);
+                t.flags = near_flags(g, t);
                 tiles.push_back(t);
             }
             r.ntiles = int64_t(tiles.size()) - r.tile0;

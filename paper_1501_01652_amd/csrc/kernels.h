@@ -12,14 +12,16 @@ namespace hank {
 // w^_n = pi N_n / Qc.  pi/D is carried as hi + lo.
 struct GridArgs {
     int64_t ar, br, ac, bc, D, Dr, Qc;
-    double pi_Qc, piD_hi, piD_lo;
+    double pi_Qc, piD_hi, piD_lo, invD;
     int32_t row_pert, col_pert;
 };
 
-// near-field work item: rows [k0, k0+nk) x columns [n0, n1)
+// near-field work item: rows [k0, k0+nk) x columns [n0, n1); flags: bit 0 some
+// entry has z < 20, bit 1 some entry has z >= 20, bits 8.. Hankel pairs needed
+// for the smallest z >= 20 of the tile (remainder below 1e-17)
 struct NearTile {
     int64_t k0, n0, n1;
-    int32_t nk, pad;
+    int32_t nk, flags;
 };
 
 // rows [k0, k0+nk) own partials of tiles [tile0, tile0+ntiles)

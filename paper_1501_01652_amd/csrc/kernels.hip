@@ -90,8 +90,81 @@ __global__ void k_j0(const double* z, int64_t n, double* out) {
 // ---------------------------------------------------------------------------
 // Near field
 // ---------------------------------------------------------------------------
+// Hankel coefficients of J_0 (Sec. 3.1) folded with their signs:
+// P = sum_m HP[m] z^-2m, Q = z^-1 sum_m HQ[m] z^-2m, HP[m] = (-1)^m a_2m(0), HQ[m] = (-1)^m a_2m+1(0).
+struct Hankel0 {
+    double p[12], q[12];
+};
+constexpr Hankel0 make_hankel0() {
+    Hankel0 h{};
+    double a = 1.0;
+    for (int m = 0; m < 24; ++m) {
+        if (m > 0) a *= -double(2 * m - 1) * double(2 * m - 1) / (8.0 * m);
+        const double sg = ((m / 2) & 1) ? -1.0 : 1.0;
+        if (m & 1)
+            h.q[m / 2] = sg * a;
+        else
+            h.p[m / 2] = sg * a;
+    }
+    return h;
+}
+
+// z^{-1/2} to full precision: hardware estimate and two Newton steps
+__device__ __forceinline__ double rsqrt_full(double z) {
+    double y = __builtin_amdgcn_rsq(z);
+    double h = 0.5 * z;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+// Near-field sweep of one tile for a fixed number M of Hankel pairs.  SMALL:
+// some entry may have z < 20 (Taylor tables); ASY: some entry has z >= 20.
+template <int M, bool SMALL, bool ASY>
+__device__ __forceinline__ double near_sweep(const GridArgs& G, const double* __restrict__ c,
+                                             const double* __restrict__ bvec, int64_t n, int64_t n1,
+                                             double Kd, double rk, double ek, int64_t ir, int64_t step) {
+    constexpr Hankel0 H = make_hankel0();
+    const int64_t D2 = 2 * G.D;
+    double acc = 0.0;
+    for (; n < n1; n += 4) {
+        const double cn = c[n - 1];
+        const double bn = G.col_pert ? bvec[n - 1] : 0.0;
+        const double Nd = (double)(G.ac * n + G.bc);
+        const double lam = fma(Nd, G.pi_Qc, bn);
+        const double delta = fma(ek, lam, rk * bn);
+        const double I = Kd * Nd; // exact: K_k N_n < 2^53
+        const double pz = I * G.piD_hi;
+        const double z = (pz + (fma(I, G.piD_hi, -pz) + I * G.piD_lo)) + delta;
+        double J = 0.0;
+        if (ASY) {
+            // phase/pi = ir/D - 1/4 + delta/pi with ir = K_k N_n mod 2D exact
+            const double phi = fma((double)ir, G.invD, -0.25) + delta * 0.31830988618379067154;
+            double sn, cs;
+            sincospi(phi, &sn, &cs);
+            const double y = rsqrt_full(z), zi = y * y, zi2 = zi * zi;
+            double P = H.p[M - 1], Q = H.q[M - 1];
+#pragma unroll
+            for (int m = M - 2; m >= 0; --m) {
+                P = fma(P, zi2, H.p[m]);
+                Q = fma(Q, zi2, H.q[m]);
+            }
+            J = 0.79788456080286535588 * y * fma(cs, P, -sn * (Q * zi));
+        }
+        if (SMALL) {
+            if (!ASY || z < J0_ASY_Z) J = j0_small(z);
+        }
+        acc = fma(cn, J, acc);
+        ir += step;
+        if (ir >= D2) ir -= D2;
+    }
+    return acc;
+}
+
 // One workgroup = 64 rows (one per lane) x a column range; its 4 waves take
-// every 4th column and their sums are added in a fixed order.
+// every 4th column (wave-uniform, so the column data are scalar loads) and
+// their sums are added in a fixed order.  The tile's flags (host-computed
+// bounds on z over the tile) select the Hankel term count and the branches.
 __global__ __launch_bounds__(256) void k_near(GridArgs G, const double* __restrict__ c,
                                               const double* __restrict__ bvec,
                                               const double* __restrict__ evec,
@@ -99,48 +172,56 @@ __global__ __launch_bounds__(256) void k_near(GridArgs G, const double* __restri
                                               double* __restrict__ partial) {
     __shared__ double red[4][64];
     const NearTile T = tiles[blockIdx.x];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t k = T.k0 + lane;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool active = lane < T.nk;
+    const int64_t k = T.k0 + (active ? lane : 0);
     const int64_t K = G.ar * k + G.br;
     const double rk = (double)K / (double)G.Dr;
-    const double ek = (G.row_pert && active) ? evec[k - 1] : 0.0;
+    const double ek = G.row_pert ? evec[k - 1] : 0.0;
     const int64_t D2 = 2 * G.D;
-    int64_t n = T.n0 + wave;
+    const int64_t n = T.n0 + wave;
     int64_t ir = 0, step = 0;
     if (n < T.n1) {
         ir = (K * (G.ac * n + G.bc)) % D2;
         step = (K * 4 * G.ac) % D2;
     }
+    const double Kd = (double)K;
+    const bool small = T.flags & 1, asy = T.flags & 2;
+    const int M = T.flags >> 8;
     double acc = 0.0;
-    for (; n < T.n1; n += 4) {
-        const double cn = c[n - 1];
-        const double bn = G.col_pert ? bvec[n - 1] : 0.0;
-        const int64_t Nn = G.ac * n + G.bc;
-        const double lam = (double)Nn * G.pi_Qc + bn;
-        const double delta = ek * lam + rk * bn;
-        const double I = (double)(K * Nn); // exact below 2^53
-        const double p = I * G.piD_hi;
-        const double zt = p + (fma(I, G.piD_hi, -p) + I * G.piD_lo);
-        const double z = zt + delta;
-        double J = (z < J0_ASY_Z) ? j0_small(z) : j0_asy(ir, G.D, delta, z);
-        if (active) acc = fma(cn, J, acc);
-        ir += step;
-        if (ir >= D2) ir -= D2;
+    if (!asy) {
+        acc = near_sweep<3, true, false>(G, c, bvec, n, T.n1, Kd, rk, ek, ir, step);
+    } else if (small) {
+        acc = near_sweep<12, true, true>(G, c, bvec, n, T.n1, Kd, rk, ek, ir, step);
+    } else {
+        switch (M) {
+        case 3: acc = near_sweep<3, false, true>(G, c, bvec, n, T.n1, Kd, rk, ek, ir, step); break;
+        case 4: acc = near_sweep<4, false, true>(G, c, bvec, n, T.n1, Kd, rk, ek, ir, step); break;
+        case 5: acc = near_sweep<5, false, true>(G, c, bvec, n, T.n1, Kd, rk, ek, ir, step); break;
+        case 6: acc = near_sweep<6, false, true>(G, c, bvec, n, T.n1, Kd, rk, ek, ir, step); break;
+        case 8: acc = near_sweep<8, false, true>(G, c, bvec, n, T.n1, Kd, rk, ek, ir, step); break;
+        default: acc = near_sweep<12, false, true>(G, c, bvec, n, T.n1, Kd, rk, ek, ir, step); break;
+        }
     }
-    red[wave][lane] = acc;
+    red[wave][lane] = active ? acc : 0.0;
     __syncthreads();
-    if (wave == 0) partial[(int64_t)blockIdx.x * 64 + lane] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    if (wave == 0)
+        partial[(int64_t)blockIdx.x * 64 + lane] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
-__global__ __launch_bounds__(64) void k_near_reduce(const RowTile* __restrict__ rt,
-                                                    const double* __restrict__ partial, double* __restrict__ f) {
+// f_k = sum of the row's tile partials; 4 waves take every 4th tile and their
+// sums are combined in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_near_reduce(const RowTile* __restrict__ rt,
+                                                     const double* __restrict__ partial, double* __restrict__ f) {
+    __shared__ double red[4][64];
     const RowTile R = rt[blockIdx.x];
-    const int lane = threadIdx.x;
-    if (lane >= R.nk) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double s = 0.0;
-    for (int64_t t = 0; t < R.ntiles; ++t) s += partial[(R.tile0 + t) * 64 + lane];
-    f[R.k0 + lane - 1] = s;
+    for (int64_t t = wave; t < R.ntiles; t += 4) s += partial[(R.tile0 + t) * 64 + lane];
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && lane < R.nk) f[R.k0 + lane - 1] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // ---------------------------------------------------------------------------
@@ -405,7 +486,7 @@ hipError_t launch_near(const GridArgs& G, const double* c, const double* b, cons
 }
 
 hipError_t launch_near_reduce(const RowTile* rt, int64_t nrt, const double* partial, double* f, hipStream_t s) {
-    if (nrt > 0) hipLaunchKernelGGL(k_near_reduce, dim3((unsigned)nrt), dim3(64), 0, s, rt, partial, f);
+    if (nrt > 0) hipLaunchKernelGGL(k_near_reduce, dim3((unsigned)nrt), dim3(256), 0, s, rt, partial, f);
     return hipGetLastError();
 }
 

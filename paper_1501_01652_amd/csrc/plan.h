@@ -87,10 +87,10 @@ struct Plan {
 // Cost-model constants (seconds); refined from measurements through the
 // environment (HANK_COST_FFT, HANK_COST_NEAR, HANK_COST_BLOCK).
 struct CostModel {
-    double fft_pt_group64 = 1.6e-11; // per FFT point per group, FP64 bulk
-    double fft_pt_group32 = 0.9e-11; // same, FP32 bulk
-    double near_entry = 2.0e-12;     // per directly summed entry
-    double block = 12e-6;            // fixed cost per block
+    double fft_pt_group64 = 3.0e-11; // per FFT point per group, FP64 bulk (measured)
+    double fft_pt_group32 = 1.7e-11; // same, FP32 bulk
+    double near_entry = 4.6e-12;     // per directly summed entry (measured)
+    double block = 20e-6;            // fixed cost per block (three launches)
 };
 
 // ---- parameter formulas ----
