@@ -17,7 +17,7 @@ import os
 import threading
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhank.so")
+LIB_PATH = os.environ.get("HANK_LIB") or os.path.join(_HERE, "libhank.so")
 
 TASKS = {"schlomilch": 0, "fourier_bessel": 1, "dht0": 2,
          "schlomilch_paper_grid": 3, "fourier_bessel_paper_grid": 4}

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -146,6 +147,21 @@ GridArgs grid_args(const Grid& g) {
     return a;
 }
 
+// Groups per launch of passes A-C.  A bounded batch keeps the work buffer
+// (groups x L complex) small enough to stay in the Infinity Cache between the
+// passes, but every launch repeats pass A's per-column set-up; measured on
+// MI355X the single launch is faster, so the budget defaults to unlimited
+// (HANK_GROUP_BATCH_MB caps it).
+size_t group_batch(size_t bytes_per_group, size_t ngroups) {
+    static const double budget = [] {
+        const char* v = std::getenv("HANK_GROUP_BATCH_MB");
+        return (v ? std::atof(v) : 1e12) * 1048576.0;
+    }();
+    size_t gb = size_t(budget / double(bytes_per_group));
+    if (gb < 1) gb = 1;
+    return std::min(gb, std::max<size_t>(1, ngroups));
+}
+
 // Branches and Hankel term count of a near-field tile from bounds on z over it:
 // z >= z~ (the perturbations e_k, b_n are non-negative) and z <= z~ + 0.25.
 int32_t near_flags(const Grid& g, const NearTile& t) {
@@ -207,7 +223,10 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
     // far-field blocks
     const size_t esz = p.fp32 ? 8 : 16;
     size_t work_elems = 0;
-    for (auto& hb : p.blocks) work_elems = std::max(work_elems, size_t(hb.L) * std::max<size_t>(1, hb.groups.size()));
+    for (auto& hb : p.blocks) {
+        const size_t gb = group_batch(size_t(hb.L) * esz, hb.groups.size());
+        work_elems = std::max(work_elems, size_t(hb.L) * std::max<size_t>(1, gb));
+    }
     if (!p.blocks.empty())
         if ((st = dev_alloc(reinterpret_cast<char*&>(dp.work), work_elems * esz, dp.bytes))) return st;
     std::vector<std::vector<GroupDev>> hg(p.blocks.size());
@@ -236,6 +255,8 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
         while ((int64_t(1) << lg) < hb.L) ++lg;
         A.twshift = 23 - lg;
         A.ngroups = int32_t(hb.groups.size());
+        A.g0 = 0;
+        A.g1 = A.ngroups;
         A.ar = g.ar;
         A.br = g.br;
         A.ac = g.ac;
@@ -352,15 +373,21 @@ hank_status run_plan(DevPlan& dp, const double* c, double* f, hipStream_t s) {
     if ((st = prof_end(K_NEAR_REDUCE, ev, 64.0 * 8.0 * double(dp.ntiles) + 8.0 * double(dp.plan.g.N), 0.0, s)))
         return st;
     for (auto& d : dp.blocks) {
-        const double G = double(d.args.ngroups), L = double(d.args.L);
-        const double pert = (d.args.col_pert ? 8.0 : 0.0);
-        const double bytes[3] = {G * L * esz + double(d.args.ncols) * (8.0 + pert),
-                                 2.0 * G * L * esz + L * esz,
-                                 G * L * esz + double(d.args.nrows) * (16.0 + (d.args.row_pert ? 8.0 : 0.0))};
-        for (int w = 0; w < 3; ++w) {
-            if ((st = prof_begin(ev, s))) return st;
-            HIP_TRY(launch_far_pass(w, d.args, dp.plan.fp32, c, dp.b, dp.e, dp.work, d.H, f, s));
-            if ((st = prof_end(K_PASS_A + w, ev, bytes[w], G * L, s))) return st;
+        const size_t gb = group_batch(size_t(d.args.L) * size_t(esz), size_t(d.args.ngroups));
+        FarArgs A = d.args;
+        for (int32_t g0 = 0; g0 < d.args.ngroups; g0 += int32_t(gb)) {
+            A.g0 = g0;
+            A.g1 = std::min(d.args.ngroups, g0 + int32_t(gb));
+            const double G = double(A.g1 - A.g0), L = double(A.L);
+            const double pert = (A.col_pert ? 8.0 : 0.0);
+            const double bytes[3] = {G * L * esz + double(A.ncols) * (8.0 + pert),
+                                     2.0 * G * L * esz + L * esz,
+                                     G * L * esz + double(A.nrows) * (16.0 + (A.row_pert ? 8.0 : 0.0))};
+            for (int w = 0; w < 3; ++w) {
+                if ((st = prof_begin(ev, s))) return st;
+                HIP_TRY(launch_far_pass(w, A, dp.plan.fp32, c, dp.b, dp.e, dp.work, d.H, f, s));
+                if ((st = prof_end(K_PASS_A + w, ev, bytes[w], G * L, s))) return st;
+            }
         }
     }
     return HANK_OK;

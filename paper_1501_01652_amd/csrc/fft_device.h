@@ -12,6 +12,20 @@
 
 #include "device_common.h"
 
+// Build knobs (measured variants):
+//   HANK_TW_DIRECT  1: each stage twiddle W^{kk s} is its own table load;
+//                   0: one load and powers by complex multiplication
+//   HANK_TW_OPAQUE  1: twiddle tables reached through an opaque pointer, so
+//                   they are reloaded per group instead of hoisted into registers;
+//                   2: only the base twiddle of each stage may be hoisted, its
+//                   powers are formed at every use (pinned by an empty asm)
+#ifndef HANK_TW_DIRECT
+#define HANK_TW_DIRECT 0
+#endif
+#ifndef HANK_TW_OPAQUE
+#define HANK_TW_OPAQUE 2
+#endif
+
 namespace hank {
 
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
@@ -52,15 +66,26 @@ __device__ __forceinline__ void dft_small(cx<F> (&a)[RS]) {
     }
 }
 
-// twiddle e^{SIGN 2 pi i t / TW_SMALL}
+// twiddle e^{SIGN 2 pi i t / TW_SMALL} from table `tw`
 template <typename F, int SIGN>
-__device__ __forceinline__ cx<F> tw_small(int t) {
-    double c = g_tab.tw_small[t][0], s = g_tab.tw_small[t][1];
+__device__ __forceinline__ cx<F> tw_small(const double (*tw)[2], int t) {
+    double c = tw[t][0], s = tw[t][1];
     return mk(F(c), F(SIGN < 0 ? s : -s));
 }
 
+// The twiddle table pointer passed through an empty asm statement: inside a
+// loop over groups this stops the compiler from hoisting every stage's
+// twiddles out of the loop (which would keep ~28 registers per stage alive).
+__device__ __forceinline__ const double (*opaque_tw())[2] {
+    const double(*p)[2] = g_tab.tw_small;
+#if HANK_TW_OPAQUE == 1
+    asm volatile("" : "+s"(p));
+#endif
+    return p;
+}
+
 template <typename F, int LEN, int R, int RS, int SIGN>
-__device__ __forceinline__ void fft_stage(cx<F> (&v)[R], cx<F>* sh, int tt, int Ns) {
+__device__ __forceinline__ void fft_stage(cx<F> (&v)[R], cx<F>* sh, int tt, int Ns, const double (*tw)[2]) {
     constexpr int NT = LEN / R;
     constexpr int NB = R / RS;
 #pragma unroll
@@ -71,13 +96,22 @@ __device__ __forceinline__ void fft_stage(cx<F> (&v)[R], cx<F>* sh, int tt, int 
         for (int s = 0; s < RS; ++s) a[s] = v[q + s * NB];
         const int kk = j & (Ns - 1);
         if (Ns > 1) {
-            cx<F> w1 = tw_small<F, SIGN>(kk * (TW_SMALL / (Ns * RS)));
+            const int step = kk * (TW_SMALL / (Ns * RS));
+#if HANK_TW_DIRECT
+#pragma unroll
+            for (int s = 1; s < RS; ++s) a[s] = cmul(a[s], tw_small<F, SIGN>(tw, s * step));
+#else
+            cx<F> w1 = tw_small<F, SIGN>(tw, step);
+#if HANK_TW_OPAQUE == 2
+            asm volatile("" : "+v"(w1.x), "+v"(w1.y));
+#endif
             cx<F> w = w1;
 #pragma unroll
             for (int s = 1; s < RS; ++s) {
                 a[s] = cmul(a[s], w);
                 if (s + 1 < RS) w = cmul(w, w1);
             }
+#endif
         }
         dft_small<F, RS, SIGN>(a);
         const int base = (j - kk) * RS + kk;
@@ -106,19 +140,24 @@ __device__ __forceinline__ void fft_reg(cx<F> (&v)[R], cx<F>* sh, int tt) {
     int Ns = 1;
 #pragma unroll
     for (int st = 0; st < LG / LR; ++st) {
-        fft_stage<F, LEN, R, R, SIGN>(v, sh, tt, Ns);
+        fft_stage<F, LEN, R, R, SIGN>(v, sh, tt, Ns, opaque_tw());
         Ns *= R;
     }
-    if constexpr (LG % LR != 0) fft_stage<F, LEN, R, (1 << (LG % LR)), SIGN>(v, sh, tt, Ns);
+    if constexpr (LG % LR != 0) fft_stage<F, LEN, R, (1 << (LG % LR)), SIGN>(v, sh, tt, Ns, opaque_tw());
 }
 
 // e^{-2 pi i e / L} for 0 <= e < L, L = 2^lg <= 2^23, from the two-level table
+// (its base passed through an empty asm statement, as for opaque_tw)
 template <typename F>
 __device__ __forceinline__ cx<F> tw_big(int64_t e, int shift /* 23 - lg */) {
     int64_t E = e << shift;
     int hi = (int)(E >> 12), lo = (int)(E & (TW_LO - 1));
-    cx<double> a = mk(g_tab.tw_hi[hi][0], g_tab.tw_hi[hi][1]);
-    cx<double> b = mk(g_tab.tw_lo[lo][0], g_tab.tw_lo[lo][1]);
+    const DeviceTables* T = &g_tab;
+#if HANK_TW_OPAQUE == 1
+    asm volatile("" : "+s"(T));
+#endif
+    cx<double> a = mk(T->tw_hi[hi][0], T->tw_hi[hi][1]);
+    cx<double> b = mk(T->tw_lo[lo][0], T->tw_lo[lo][1]);
     cx<double> p = cmul(a, b);
     return mk(F(p.x), F(p.y));
 }

@@ -44,6 +44,7 @@ struct TermDev {
 struct FarArgs {
     int64_t ka, na, nrows, ncols, L;
     int32_t L1, L2, twshift, ngroups;
+    int32_t g0, g1; // groups [g0, g1) of this launch; group g lives at buf + (g - g0) * L
     int64_t ar, br, ac, bc, D, Dr, Qc, Kka, Nna;
     double pi_Qc, r0, w0, eref, lref, bref;
     int32_t row_pert, col_pert;

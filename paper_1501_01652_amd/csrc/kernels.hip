@@ -241,6 +241,10 @@ __device__ __forceinline__ double ipow_d(double x, int e) {
 }
 
 // Pass A on the block's data: y_n' = q(n') c_n X_g(n), column FFTs over j2.
+// Per column position the group-independent factors are kept:
+//   base = c_n q(n') (w^_n/w0)^(-1/2),  iw = w0/w^_n,  x = (b_n/bref) iw,  la = lambda_n/lref
+// and X_g = la^a (w^_n/w0)^e sum_b K_{g,b} x^b, with (w^_n/w0)^e updated
+// incrementally over the groups (sorted by a, then e).
 template <typename F, int L2, int W>
 __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(FarArgs A, const double* __restrict__ c,
                                                        const double* __restrict__ bvec,
@@ -251,61 +255,74 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(FarArgs A, const double* 
     const int64_t j1 = (int64_t)blockIdx.x * W + w;
     cx<F>* my = sh + w * (L2 + L2 / 8);
 
-    double vp[R], vph[R], la[R], bb[R];
-    cx<double> cq[R];
-    cx<F> tw[R];
-    bool ok[R];
+    double vw[R], xb[R], la[R], pw[R];
+    cx<double> base[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t j2 = tt + r * NTC;
         const int64_t np = j1 + (int64_t)A.L1 * j2;
-        ok[r] = np < A.ncols;
-        tw[r] = tw_big<F>(j1 * j2, A.twshift); // m2 = j2 after the FFT
-        vp[r] = vph[r] = la[r] = bb[r] = 0.0;
-        cq[r] = mk(0.0, 0.0);
-        if (ok[r]) {
+        vw[r] = 1.0;
+        xb[r] = la[r] = 0.0;
+        base[r] = mk(0.0, 0.0);
+        if (np < A.ncols) {
             const int64_t n = A.na + np;
             const int64_t Nn = A.ac * n + A.bc;
             const double wn = (double)Nn * A.pi_Qc;
             const double bn = A.col_pert ? bvec[n - 1] : 0.0;
-            vp[r] = wn / A.w0;
-            vph[r] = 1.0 / sqrt(vp[r]);
+            vw[r] = wn / A.w0;
+            const double iw = 1.0 / vw[r];
+            xb[r] = (bn / A.bref) * iw;
             la[r] = (wn + bn) / A.lref;
-            bb[r] = bn / A.bref;
             const cx<double> q = expi_ratio(2 * A.Kka * A.ac * np + A.ar * A.ac * np * np, 2 * A.D);
-            cq[r] = cscale(q, c[n - 1]);
+            base[r] = cscale(q, c[n - 1] * sqrt(iw));
         }
     }
-    for (int g = 0; g < A.ngroups; ++g) {
+    int ecur = 0, acur = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) pw[r] = 1.0; // (w^_n/w0)^ecur * la^acur
+    for (int g = A.g0; g < A.g1; ++g) {
         const GroupDev Gd = A.groups[g];
+        if (Gd.a != acur || g == A.g0) { // restart the powers
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                pw[r] = ipow_d<double>(vw[r], Gd.e) * (Gd.a ? ipow_d<double>(la[r], Gd.a) : 1.0);
+        } else {
+            for (; ecur < Gd.e; ++ecur) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) pw[r] *= vw[r];
+            }
+            for (; ecur > Gd.e; --ecur) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) pw[r] /= vw[r];
+            }
+        }
+        ecur = Gd.e;
+        acur = Gd.a;
         cx<F> v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            cx<double> X = mk(0.0, 0.0);
-            if (ok[r]) {
-                const double x = bb[r] / vp[r];
-                double xp = 1.0;
-                int bcur = 0;
+            double xp = 1.0, Xr = 0.0, Xi = 0.0;
+            int bcur = 0;
+            const bool live = (j1 + (int64_t)A.L1 * (tt + r * NTC)) < A.ncols; // zero padding otherwise
+            if (live)
                 for (int ti = Gd.t0; ti < Gd.t1; ++ti) {
-                    const TermDev Td = A.terms[ti];
-                    while (bcur < Td.b) {
-                        xp *= x;
-                        ++bcur;
-                    }
-                    X.x = fma(Td.kre, xp, X.x);
-                    X.y = fma(Td.kim, xp, X.y);
+                const TermDev Td = A.terms[ti];
+                while (bcur < Td.b) {
+                    xp *= xb[r];
+                    ++bcur;
                 }
-                const double amp = vph[r] * ipow_d<double>(vp[r], Gd.e) * (Gd.a ? ipow_d<double>(la[r], Gd.a) : 1.0);
-                X = cmul(cscale(X, amp), cq[r]);
+                Xr = fma(Td.kre, xp, Xr);
+                Xi = fma(Td.kim, xp, Xi);
             }
-            v[r] = mk(F(X.x), F(X.y));
+            const cx<double> y = cmul(mk(Xr * pw[r], Xi * pw[r]), base[r]);
+            v[r] = mk(F(y.x), F(y.y));
         }
         fft_reg<F, L2, R, -1>(v, my, tt);
-        cx<F>* out = buf + (int64_t)g * A.L;
+        cx<F>* out = buf + (int64_t)(g - A.g0) * A.L;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t m2 = tt + r * NTC;
-            out[m2 * A.L1 + j1] = cmul(v[r], tw[r]);
+            out[m2 * A.L1 + j1] = cmul(v[r], tw_big<F>(j1 * m2, A.twshift));
         }
     }
 }
@@ -367,6 +384,11 @@ __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b_fwd(FarArgs A, const c
 }
 
 // Pass B: row FFT, product with H^, inverse row FFT, inverse twiddle; in place.
+// HANK_PASSB_HREG 1: H^ and the inverse twiddles of the row are held in
+// registers across the groups; 0: re-read per group (L2 hits), fewer registers.
+#ifndef HANK_PASSB_HREG
+#define HANK_PASSB_HREG 1
+#endif
 template <typename F, int L1, int ROWS>
 __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(FarArgs A, cx<F>* __restrict__ buf,
                                                            const cx<F>* __restrict__ H) {
@@ -375,32 +397,50 @@ __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(FarArgs A, cx<F>* __re
     const int t = threadIdx.x, rl = t / NTR, tt = t % NTR;
     const int64_t row = (int64_t)blockIdx.x * ROWS + rl;
     const bool okrow = row < A.L2;
+    const int64_t rowc = okrow ? row : 0;
+    cx<F>* my = sh + rl * (L1 + L1 / 8);
+    const cx<F>* hrow = H + rowc * L1;
+#if HANK_PASSB_HREG
     cx<F> hv[R], tw[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int64_t j1 = tt + r * NTR;
-        hv[r] = okrow ? H[row * L1 + j1] : mk(F(0), F(0));
-        cx<F> w = tw_big<F>(j1 * (okrow ? row : 0), A.twshift);
-        tw[r] = mk(w.x, -w.y); // e^{+2 pi i j1 m2 / L}
+        hv[r] = hrow[tt + r * NTR];
+        const cx<F> w = tw_big<F>((int64_t)(tt + r * NTR) * rowc, A.twshift);
+        tw[r] = mk(w.x, -w.y);
     }
-    cx<F>* my = sh + rl * (L1 + L1 / 8);
-    for (int g = 0; g < A.ngroups; ++g) {
-        cx<F>* p = buf + (int64_t)g * A.L + row * L1;
+#endif
+    for (int g = A.g0; g < A.g1; ++g) {
+        cx<F>* p = buf + (int64_t)(g - A.g0) * A.L + rowc * L1;
         cx<F> v[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = okrow ? p[tt + r * NTR] : mk(F(0), F(0));
+        for (int r = 0; r < R; ++r) v[r] = p[tt + r * NTR];
         fft_reg<F, L1, R, -1>(v, my, tt);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = cmul(v[r], hv[r]);
+        for (int r = 0; r < R; ++r) {
+#if HANK_PASSB_HREG
+            v[r] = cmul(v[r], hv[r]);
+#else
+            v[r] = cmul(v[r], hrow[tt + r * NTR]);
+#endif
+        }
         fft_reg<F, L1, R, 1>(v, my, tt);
         if (okrow) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) p[tt + r * NTR] = cmul(v[r], tw[r]);
+            for (int r = 0; r < R; ++r) {
+#if HANK_PASSB_HREG
+                p[tt + r * NTR] = cmul(v[r], tw[r]);
+#else
+                const cx<F> w = tw_big<F>((int64_t)(tt + r * NTR) * row, A.twshift);
+                p[tt + r * NTR] = cmul(v[r], mk(w.x, -w.y)); // e^{+2 pi i j1 m2 / L}
+#endif
+            }
         }
     }
 }
 
-// Pass C: inverse column FFTs, then f_k += sum_g A_g(k) Re(p(k') conv_g(k')).
+// Pass C: inverse column FFTs, then f_k += sum_g A_g(k) Re(p(k') conv_g(k')),
+// A_g(k) = scale_g (e_k/eref)^a (r^_k/r0)^(e - 1/2) with the power of r^_k/r0
+// updated incrementally over the groups.
 template <typename F, int L2, int W>
 __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(FarArgs A, const cx<F>* __restrict__ buf,
                                                        const double* __restrict__ evec,
@@ -410,48 +450,59 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(FarArgs A, const cx<F>* _
     const int t = threadIdx.x, w = t % W, tt = t / W;
     const int64_t j1 = (int64_t)blockIdx.x * W + w;
     cx<F>* my = sh + w * (L2 + L2 / 8);
-    double rho[R], rhoh[R], ek[R], acc[R];
+    double rho[R], ek[R], acc[R], pw[R];
     cx<double> pk[R];
-    bool ok[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t kp = j1 + (int64_t)A.L1 * (tt + r * NTC);
-        ok[r] = kp < A.nrows;
-        rho[r] = rhoh[r] = 1.0;
+        rho[r] = 1.0;
         ek[r] = 0.0;
         acc[r] = 0.0;
         pk[r] = mk(0.0, 0.0);
-        if (ok[r]) {
+        if (kp < A.nrows) {
             const int64_t k = A.ka + kp;
             rho[r] = ((double)(A.ar * k + A.br) / (double)A.Dr) / A.r0;
-            rhoh[r] = 1.0 / sqrt(rho[r]);
             ek[r] = A.row_pert ? evec[k - 1] / A.eref : 0.0;
-            pk[r] = expi_ratio(2 * A.Kka * A.Nna + 2 * A.ar * A.Nna * kp + A.ar * A.ac * kp * kp, 2 * A.D);
+            pk[r] = cscale(expi_ratio(2 * A.Kka * A.Nna + 2 * A.ar * A.Nna * kp + A.ar * A.ac * kp * kp, 2 * A.D),
+                           1.0 / sqrt(rho[r]));
         }
     }
-    for (int g = 0; g < A.ngroups; ++g) {
+    int ecur = 0, acur = 0;
+    for (int g = A.g0; g < A.g1; ++g) {
         const GroupDev Gd = A.groups[g];
-        const cx<F>* p = buf + (int64_t)g * A.L;
+        if (Gd.a != acur || g == A.g0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                pw[r] = ipow_d<double>(rho[r], Gd.e) * (Gd.a ? ipow_d<double>(ek[r], Gd.a) : 1.0);
+        } else {
+            for (; ecur < Gd.e; ++ecur) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) pw[r] *= rho[r];
+            }
+            for (; ecur > Gd.e; --ecur) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) pw[r] /= rho[r];
+            }
+        }
+        ecur = Gd.e;
+        acur = Gd.a;
+        const cx<F>* p = buf + (int64_t)(g - A.g0) * A.L;
         cx<F> v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = p[(int64_t)(tt + r * NTC) * A.L1 + j1];
         fft_reg<F, L2, R, 1>(v, my, tt);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if (ok[r]) {
+            if (j1 + (int64_t)A.L1 * (tt + r * NTC) < A.nrows) { // rows past the block are discarded
                 const double re = pk[r].x * (double)v[r].x - pk[r].y * (double)v[r].y;
-                const double wgt = Gd.scale * rhoh[r] * ipow_d<double>(rho[r], Gd.e) *
-                                   (Gd.a ? ipow_d<double>(ek[r], Gd.a) : 1.0);
-                acc[r] = fma(wgt, re, acc[r]);
+                acc[r] = fma(Gd.scale * pw[r], re, acc[r]);
             }
         }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        if (ok[r]) {
-            const int64_t k = A.ka + j1 + (int64_t)A.L1 * (tt + r * NTC);
-            f[k - 1] += acc[r];
-        }
+        const int64_t kp = j1 + (int64_t)A.L1 * (tt + r * NTC);
+        if (kp < A.nrows) f[A.ka + kp - 1] += acc[r];
     }
 }
 
