@@ -36,7 +36,90 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=1024, help="requests of the batched workload (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving run (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--only", choices=["all", "headline", "batched", "serve"], default="all")
     return ap.parse_args()
+
+
+def run_batched(hank, inputs, torch, count):
+    """1024 uneven transforms in one hank_batch call against the same requests
+    one call at a time; throughput and per-request completion latency (all
+    submitted at t = 0)."""
+    specs = inputs.batch_specs(count)
+    reqs = []
+    for sp in specs:
+        g = torch.Generator(device="cuda").manual_seed(sp["seed"])
+        shape = (sp["nrhs"], sp["N"]) if sp["nrhs"] > 1 else (sp["N"],)
+        c = torch.rand(shape, generator=g, dtype=torch.float64, device="cuda") * 2.0 - 1.0
+        reqs.append({"task": sp["task"], "c": c, "out": torch.empty_like(c), "eps": sp["eps"]})
+    t0 = time.perf_counter()
+    hank.batch(reqs)  # builds every plan, then runs
+    torch.cuda.synchronize()
+    warm_s = time.perf_counter() - t0
+    reps = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        hank.batch(reqs)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    # one request at a time, same stream, completion stamped by events
+    for r in reqs:
+        hank.transform(r["task"], r["c"], r["eps"], out=r["out"])
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in reqs]
+    start.record()
+    for r, e in zip(reqs, evs):
+        hank.transform(r["task"], r["c"], r["eps"], out=r["out"])
+        e.record()
+    torch.cuda.synchronize()
+    lat = sorted(start.elapsed_time(e) for e in evs)
+    ts = lat[-1] / 1e3
+    pct = lambda q: lat[min(len(lat) - 1, int(q * (len(lat) - 1) + 0.5))]
+    return {"requests": count, "rhs_total": int(sum(sp["nrhs"] for sp in specs)),
+            "workload": "task 40/40/20, N log-uniform [2^8, 2^16], 1-64 rhs, eps {1e-4,1e-8,1e-14}, "
+                        "c ~ U[-1,1], seed %d" % inputs.SEED_BATCH,
+            "batched_transforms_per_s": count / tb, "batched_ms": tb * 1e3,
+            "batched_latency_p50_ms": tb * 1e3, "batched_latency_p99_ms": tb * 1e3,
+            "sequential_transforms_per_s": count / ts, "sequential_ms": ts * 1e3,
+            "sequential_latency_p50_ms": pct(0.5), "sequential_latency_p99_ms": pct(0.99),
+            "speedup": ts / tb, "first_call_incl_planning_s": warm_s}
+
+
+def run_serve(hank, inputs, torch, seconds, rate, max_batch):
+    """Open-loop Poisson arrivals through the continuous-batching server."""
+    trace = inputs.serve_trace(rate=rate, seconds=seconds)
+    sizes = sorted({t["N"] for t in trace})
+    cin = {}
+    pool = {}
+    for N in sizes:
+        g = torch.Generator(device="cuda").manual_seed(inputs.SEED_SERVE + N)
+        cin[N] = torch.randn(N, generator=g, dtype=torch.float64, device="cuda")
+        pool[N] = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in range(max_batch + 1)]
+    srv = hank.Server(budget_bytes=32 << 30, max_batch=max_batch, max_pending=256)
+    seen = {}
+    for t in trace:  # plans on the device before the clock starts
+        key = (t["task"], t["N"], t["eps"])
+        if key not in seen:
+            seen[key] = True
+            srv.warm({"task": t["task"], "c": cin[t["N"]], "out": pool[t["N"]][0], "eps": t["eps"]})
+    count = {}
+    for t in trace:
+        i = count.get(t["N"], 0)
+        count[t["N"]] = i + 1
+        srv.submit({"task": t["task"], "c": cin[t["N"]], "out": pool[t["N"]][i % (max_batch + 1)],
+                    "eps": t["eps"]}, arrival_s=t["arrival"])
+    srv.start()
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    st["offered_rate"] = rate
+    st["window_s"] = seconds
+    st["max_batch"] = max_batch
+    return st
 
 
 def main():
@@ -50,6 +133,24 @@ def main():
 
     import paper_1501_01652_amd as hank
     from paper_1501_01652_amd import inputs
+
+    extra = {}
+
+    def run_extra():
+        if args.only in ("all", "batched") and args.batch_count > 0:
+            extra["batched"] = run_batched(hank, inputs, torch, args.batch_count)
+        if args.only in ("all", "serve") and args.serve_seconds > 0:
+            extra["serving"] = {
+                "workload": "Poisson %g req/s for %g s, task 40/40/20, N in {2^10..2^22} log-uniform, 1 rhs, "
+                            "eps {1e-4,1e-8,1e-14}, seed %d" % (args.serve_rate, args.serve_seconds,
+                                                                inputs.SEED_SERVE),
+                "continuous_batching": run_serve(hank, inputs, torch, args.serve_seconds, args.serve_rate, 64),
+                "one_at_a_time": run_serve(hank, inputs, torch, args.serve_seconds, args.serve_rate, 1)}
+
+    if args.only in ("batched", "serve"):
+        run_extra()
+        print(json.dumps(extra))
+        return
 
     task, N, eps = args.task, args.N, args.eps
     c_host = inputs.workload(task, N)
@@ -146,6 +247,8 @@ def main():
             "plan_build_s": plan_s},
         "roofline": roofline, "cpu_baseline": cpu, "direct_gpu": direct, "kernels": kernels,
     }
+    run_extra()
+    line.update(extra)
     print(json.dumps(line))
 
 

@@ -110,6 +110,41 @@ typedef struct {
 
 hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t stream);
 
+/* ---- Serving: continuous batching ---------------------------------------------
+ * A server owns a worker thread and a stream.  Submitted requests become
+ * eligible at their arrival time (seconds after hank_server_start; a negative
+ * arrival means "now"), wait in a queue, and are admitted in arrival order into
+ * batches while (a) the device bytes of the admitted, unfinished requests stay
+ * within budget_bytes and (b) a batch holds at most max_batch requests.  Up to
+ * two batches are in flight on the stream, so a new batch is enqueued while
+ * the previous one runs.  A request that arrives while max_pending requests
+ * are already waiting is rejected (state 3) and never run.  Latency is
+ * completion minus arrival (host clock).  max_batch = 1 gives the plain
+ * one-request-at-a-time form on the same path.  Requests follow the
+ * conventions of hank_transform; their buffers must stay valid until done.
+ * Plans are built (and cached) by the worker on first use; hank_server_warm
+ * builds a request's plan in advance. */
+typedef struct hank_server hank_server;
+
+typedef struct {
+    int64_t submitted, completed, rejected, batches;
+    double mean_batch;                 /* requests per batch                      */
+    double p50_ms, p90_ms, p99_ms, max_ms, mean_ms; /* latency of completed requests */
+    double wall_s;                     /* first arrival to last completion        */
+    double throughput;                 /* completed requests per second of wall_s */
+} hank_server_summary;
+
+hank_status hank_server_create(int64_t budget_bytes, int32_t max_batch, int64_t max_pending,
+                               hank_stream_t stream, hank_server** out);
+hank_status hank_server_warm(hank_server* srv, const hank_request* req);
+hank_status hank_server_submit(hank_server* srv, const hank_request* req, double arrival_s, int64_t* ticket);
+hank_status hank_server_start(hank_server* srv);
+hank_status hank_server_drain(hank_server* srv);
+/* state: 0 waiting, 1 admitted, 2 done, 3 rejected */
+hank_status hank_server_status(hank_server* srv, int64_t ticket, int32_t* state, double* latency_ms);
+hank_status hank_server_stats(hank_server* srv, hank_server_summary* out);
+hank_status hank_server_destroy(hank_server* srv);
+
 /* ---- Library state --------------------------------------------------------- */
 const char* hank_last_error(void);   /* message of the calling thread's last error */
 hank_status hank_cache_clear(void);  /* drop every cached plan (device sync first)  */

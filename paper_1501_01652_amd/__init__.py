@@ -27,7 +27,9 @@ STATUS = {0: "HANK_OK", 1: "HANK_EINVAL", 2: "HANK_ENOMEM", 3: "HANK_EDEVICE", 4
 EXPORTS = ["hank_schlomilch", "hank_fourier_bessel", "hank_dht0", "hank_transform", "hank_batch",
            "hank_last_error", "hank_cache_clear", "hank_cache_bytes", "hank_param_s", "hank_param_t",
            "hank_param_neumann", "hank_param_pK", "hank_param_qT", "hank_plan_info",
-           "hank_plan_block", "hank_root_offsets", "hank_j0", "hank_profile", "hank_profile_report"]
+           "hank_plan_block", "hank_root_offsets", "hank_j0", "hank_profile", "hank_profile_report",
+           "hank_server_create", "hank_server_warm", "hank_server_submit", "hank_server_start",
+           "hank_server_drain", "hank_server_status", "hank_server_stats", "hank_server_destroy"]
 
 
 class HankError(RuntimeError):
@@ -299,3 +301,96 @@ def profile_report() -> list:
     _check(lib().hank_profile_report(arr, 16, ctypes.byref(n)))
     return [{"name": arr[i].name.decode(), "launches": arr[i].launches, "total_ms": arr[i].total_ms,
              "bytes": arr[i].bytes, "work": arr[i].work} for i in range(min(n.value, 16))]
+
+
+class ServerSummary(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("mean_batch", ctypes.c_double), ("p50_ms", ctypes.c_double),
+                ("p90_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("wall_s", ctypes.c_double), ("throughput", ctypes.c_double)]
+
+
+def _server_fns():
+    L = lib()
+    if not getattr(L, "_server_typed", False):
+        p, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.hank_server_create.restype = i32
+        L.hank_server_create.argtypes = [i64, i32, i64, p, ctypes.POINTER(p)]
+        L.hank_server_warm.restype = i32
+        L.hank_server_warm.argtypes = [p, ctypes.POINTER(Request)]
+        L.hank_server_submit.restype = i32
+        L.hank_server_submit.argtypes = [p, ctypes.POINTER(Request), d, ctypes.POINTER(i64)]
+        for name in ("hank_server_start", "hank_server_drain", "hank_server_destroy"):
+            f = getattr(L, name)
+            f.restype = i32
+            f.argtypes = [p]
+        L.hank_server_status.restype = i32
+        L.hank_server_status.argtypes = [p, i64, ctypes.POINTER(i32), ctypes.POINTER(d)]
+        L.hank_server_stats.restype = i32
+        L.hank_server_stats.argtypes = [p, ctypes.POINTER(ServerSummary)]
+        L._server_typed = True
+    return L
+
+
+def _request(r) -> Request:
+    c = _dev_f64(r["c"], "c")
+    o = _dev_f64(r["out"], "out")
+    N = c.shape[-1]
+    nrhs = 1 if c.dim() == 1 else c.shape[0]
+    return Request(_task(r["task"]), int(r.get("precision", 0)), N, nrhs, N, N, float(r["eps"]),
+                   c.data_ptr(), o.data_ptr())
+
+
+class Server:
+    """Continuous-batching server of the C library (hank_server_*).
+
+    Requests are dicts like those of batch(); their tensors are kept alive by
+    this object until close()."""
+
+    STATES = {0: "waiting", 1: "admitted", 2: "done", 3: "rejected"}
+
+    def __init__(self, budget_bytes: int, max_batch: int = 64, max_pending: int = 256, stream=None):
+        L = _server_fns()
+        h = ctypes.c_void_p()
+        _check(L.hank_server_create(int(budget_bytes), int(max_batch), int(max_pending), _stream(stream),
+                                    ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+
+    def warm(self, req):
+        _check(_server_fns().hank_server_warm(self._h, ctypes.byref(_request(req))))
+
+    def submit(self, req, arrival_s: float = -1.0) -> int:
+        t = ctypes.c_int64()
+        _check(_server_fns().hank_server_submit(self._h, ctypes.byref(_request(req)), float(arrival_s),
+                                                ctypes.byref(t)))
+        self._keep.append(req)
+        return t.value
+
+    def start(self):
+        _check(_server_fns().hank_server_start(self._h))
+
+    def drain(self):
+        _check(_server_fns().hank_server_drain(self._h))
+
+    def status(self, ticket: int):
+        s, lat = ctypes.c_int32(), ctypes.c_double()
+        _check(_server_fns().hank_server_status(self._h, int(ticket), ctypes.byref(s), ctypes.byref(lat)))
+        return self.STATES[s.value], lat.value
+
+    def stats(self) -> dict:
+        s = ServerSummary()
+        _check(_server_fns().hank_server_stats(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in ServerSummary._fields_}
+
+    def close(self):
+        if self._h:
+            _check(_server_fns().hank_server_destroy(self._h))
+            self._h = None
+            self._keep = []
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

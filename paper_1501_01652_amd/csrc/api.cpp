@@ -7,6 +7,12 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <atomic>
+#include <thread>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -55,13 +61,10 @@ struct DevPlan {
     int device = 0;
     double* b = nullptr; // root offsets b_1..b_{N+1}
     double* e = nullptr; // DHT row perturbations e_1..e_N
-    NearTile* tiles = nullptr;
-    int64_t ntiles = 0;
-    RowTile* rt = nullptr;
-    int64_t nrt = 0;
-    double* partial = nullptr;
+    std::vector<NearTile> tiles; // geometry and flags; prob/pbase filled per call
+    std::vector<RowTile> rts;    // geometry; f/pbase/nrhs filled per call
     std::vector<DevBlock> blocks;
-    void* work = nullptr;
+    void* work = nullptr; // chirp-spectrum scratch during the build
     size_t bytes = 0;
     GridArgs G{};
 
@@ -74,9 +77,6 @@ struct DevPlan {
         };
         fr(b);
         fr(e);
-        fr(tiles);
-        fr(rt);
-        fr(partial);
         fr(work);
         for (auto& d : blocks) {
             fr(d.H);
@@ -189,9 +189,9 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
         if ((st = dev_alloc(dp.e, size_t(N), dp.bytes))) return st;
         HIP_TRY(launch_dht_e(N, dp.b, dp.e, s));
     }
-    // near-field work items
-    std::vector<NearTile> tiles;
-    std::vector<RowTile> rts;
+    // near-field work items (host copies; device descriptors are built per call)
+    std::vector<NearTile>& tiles = dp.tiles;
+    std::vector<RowTile>& rts = dp.rts;
     for (auto& seg : p.near)
         for (int64_t k = seg.k0; k < seg.k1; k += 64) {
             RowTile r{};
@@ -210,23 +210,11 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
             r.ntiles = int64_t(tiles.size()) - r.tile0;
             rts.push_back(r);
         }
-    dp.ntiles = int64_t(tiles.size());
-    dp.nrt = int64_t(rts.size());
-    if ((st = dev_alloc(dp.tiles, tiles.size(), dp.bytes))) return st;
-    if ((st = dev_alloc(dp.rt, rts.size(), dp.bytes))) return st;
-    if ((st = dev_alloc(dp.partial, size_t(dp.ntiles) * 64, dp.bytes))) return st;
-    if (!tiles.empty())
-        HIP_TRY(hipMemcpyAsync(dp.tiles, tiles.data(), tiles.size() * sizeof(NearTile), hipMemcpyHostToDevice, s));
-    if (!rts.empty())
-        HIP_TRY(hipMemcpyAsync(dp.rt, rts.data(), rts.size() * sizeof(RowTile), hipMemcpyHostToDevice, s));
 
-    // far-field blocks
+    // far-field blocks (the scratch only holds one chirp kernel at a time)
     const size_t esz = p.fp32 ? 8 : 16;
     size_t work_elems = 0;
-    for (auto& hb : p.blocks) {
-        const size_t gb = group_batch(size_t(hb.L) * esz, hb.groups.size());
-        work_elems = std::max(work_elems, size_t(hb.L) * std::max<size_t>(1, gb));
-    }
+    for (auto& hb : p.blocks) work_elems = std::max(work_elems, size_t(hb.L));
     if (!p.blocks.empty())
         if ((st = dev_alloc(reinterpret_cast<char*&>(dp.work), work_elems * esz, dp.bytes))) return st;
     std::vector<std::vector<GroupDev>> hg(p.blocks.size());
@@ -283,16 +271,22 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
     return HANK_OK;
 }
 
-hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hipStream_t s, DevPlan*& out) {
+Key plan_key(int task, int64_t N, double eps, const hank_options* o, int dev) {
+    int mode = o ? o->plan_mode : 0, prec = o ? o->precision : 0, direct = o ? o->direct : 0;
+    int far = o ? o->prefer_far : 0;
+    uint64_t eb;
+    std::memcpy(&eb, &eps, 8);
+    return Key{task, N, eb, mode, prec, direct * 2 + far, dev};
+}
+
+hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hipStream_t s, DevPlan*& out,
+                     const Plan* prebuilt = nullptr) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     hank_status st = ensure_tables(dev);
     if (st) return st;
     int mode = o ? o->plan_mode : 0, prec = o ? o->precision : 0, direct = o ? o->direct : 0;
-    int far = o ? o->prefer_far : 0;
-    uint64_t eb;
-    std::memcpy(&eb, &eps, 8);
-    Key key{task, N, eb, mode, prec, direct * 2 + far, dev};
+    Key key = plan_key(task, N, eps, o, dev);
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
         out = it->second.get();
@@ -301,7 +295,7 @@ hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hip
     std::unique_ptr<DevPlan> dp(new DevPlan);
     dp->device = dev;
     try {
-        dp->plan = make_plan(task, N, eps, mode, prec, direct != 0, cost_model_for(o));
+        dp->plan = prebuilt ? *prebuilt : make_plan(task, N, eps, mode, prec, direct != 0, cost_model_for(o));
     } catch (const std::exception& ex) {
         return fail(HANK_EINVAL, std::string("planning failed: ") + ex.what());
     }
@@ -313,8 +307,8 @@ hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hip
 }
 
 // ---- optional per-kernel timing (hank_profile) ----
-enum { K_NEAR = 0, K_NEAR_REDUCE, K_PASS_A, K_PASS_B, K_PASS_C, K_COUNT };
-const char* const k_names[K_COUNT] = {"near", "near_reduce", "pass_a", "pass_b", "pass_c"};
+enum { K_NEAR = 0, K_NEAR_MULTI, K_NEAR_REDUCE, K_PASS_A, K_PASS_B, K_PASS_C, K_COUNT };
+const char* const k_names[K_COUNT] = {"near", "near_multi", "near_reduce", "pass_a", "pass_b", "pass_c"};
 struct Pending {
     int kind;
     hipEvent_t a, b;
@@ -361,35 +355,283 @@ hank_status prof_collect() {
     return HANK_OK;
 }
 
-hank_status run_plan(DevPlan& dp, const double* c, double* f, hipStream_t s) {
+// ---- execution of a list of jobs ----
+// A job is a plan applied to nrhs coefficient columns.  All jobs of one call
+// share its launches: one near-field launch per kind over every job's tiles,
+// one reduce, and the far field in waves by block index (blocks of one job
+// overlap in rows, blocks of different jobs never share output), each wave
+// split by FFT shape into one launch per pass.
+struct Job {
+    DevPlan* dp;
+    const double* c;
+    int64_t ldc;
+    double* f;
+    int64_t ldo;
+    int64_t nrhs;
+};
+
+// Device buffers shared by all calls (grow-only), ordered across streams by
+// an event recorded at the end of every call.
+struct Scratch {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+struct Executor {
+    Scratch probs, tiles1, tilesm, rts, partial, descs, maps, work;
+    hipEvent_t done = nullptr;
+    hipStream_t last = nullptr;
+    bool used = false;
+    // the last upload, so that a repeated identical call skips it
+    std::vector<char> sig;
+} g_ex;
+
+hank_status ensure(Scratch& b, size_t bytes, hipStream_t s) {
+    if (bytes <= b.bytes) return HANK_OK;
+    if (b.p) {
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipFree(b.p));
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = std::max(bytes, size_t(4096));
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? HANK_ENOMEM : HANK_EDEVICE,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    b.bytes = want;
+    g_ex.sig.clear(); // contents are gone
+    return HANK_OK;
+}
+
+template <typename T>
+hank_status upload(Scratch& b, const std::vector<T>& v, hipStream_t s) {
+    hank_status st = ensure(b, v.size() * sizeof(T), s);
+    if (st) return st;
+    if (!v.empty()) HIP_TRY(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return HANK_OK;
+}
+
+// Workspace budget of one far-field wave (HANK_WAVE_MB, default 4096 MB).
+size_t wave_budget() {
+    static const size_t b = [] {
+        const char* v = std::getenv("HANK_WAVE_MB");
+        return size_t((v ? std::atof(v) : 4096.0) * 1048576.0);
+    }();
+    return b;
+}
+
+hank_status run_jobs(std::vector<Job>& jobs, hipStream_t s) {
     hank_status st;
-    hipEvent_t ev;
-    const double esz = dp.plan.fp32 ? 8.0 : 16.0;
-    if ((st = prof_begin(ev, s))) return st;
-    HIP_TRY(launch_near(dp.G, c, dp.b, dp.e, dp.tiles, dp.ntiles, dp.partial, s));
-    if ((st = prof_end(K_NEAR, ev, 64.0 * 8.0 * double(dp.ntiles), double(dp.plan.near_entries), s))) return st;
-    if ((st = prof_begin(ev, s))) return st;
-    HIP_TRY(launch_near_reduce(dp.rt, dp.nrt, dp.partial, f, s));
-    if ((st = prof_end(K_NEAR_REDUCE, ev, 64.0 * 8.0 * double(dp.ntiles) + 8.0 * double(dp.plan.g.N), 0.0, s)))
-        return st;
-    for (auto& d : dp.blocks) {
-        const size_t gb = group_batch(size_t(d.args.L) * size_t(esz), size_t(d.args.ngroups));
-        FarArgs A = d.args;
-        for (int32_t g0 = 0; g0 < d.args.ngroups; g0 += int32_t(gb)) {
-            A.g0 = g0;
-            A.g1 = std::min(d.args.ngroups, g0 + int32_t(gb));
-            const double G = double(A.g1 - A.g0), L = double(A.L);
-            const double pert = (A.col_pert ? 8.0 : 0.0);
-            const double bytes[3] = {G * L * esz + double(A.ncols) * (8.0 + pert),
-                                     2.0 * G * L * esz + L * esz,
-                                     G * L * esz + double(A.nrows) * (16.0 + (A.row_pert ? 8.0 : 0.0))};
-            for (int w = 0; w < 3; ++w) {
-                if ((st = prof_begin(ev, s))) return st;
-                HIP_TRY(launch_far_pass(w, A, dp.plan.fp32, c, dp.b, dp.e, dp.work, d.H, f, s));
-                if ((st = prof_end(K_PASS_A + w, ev, bytes[w], G * L, s))) return st;
+    if (!g_ex.done) HIP_TRY(hipEventCreateWithFlags(&g_ex.done, hipEventDisableTiming));
+    if (g_ex.used && g_ex.last != s) HIP_TRY(hipStreamWaitEvent(s, g_ex.done, 0));
+
+    // ---------- near field descriptors ----------
+    std::vector<NearProb> probs;
+    std::vector<NearTile> t1, tm;
+    std::vector<RowTile> rts;
+    int64_t pbase = 0;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        Job& J = jobs[i];
+        NearProb P{};
+        P.G = J.dp->G;
+        P.c = J.c;
+        P.b = J.dp->b;
+        P.e = J.dp->e;
+        P.ldc = J.ldc;
+        P.nrhs = int32_t(J.nrhs);
+        probs.push_back(P);
+        for (const RowTile& r0 : J.dp->rts) {
+            RowTile r = r0;
+            r.f = J.f;
+            r.ldo = J.ldo;
+            r.nrhs = int32_t(J.nrhs);
+            r.pbase = pbase;
+            for (int64_t t = 0; t < r0.ntiles; ++t) {
+                NearTile T = J.dp->tiles[size_t(r0.tile0 + t)];
+                T.prob = int32_t(i);
+                T.pbase = pbase;
+                pbase += J.nrhs * 64;
+                (J.nrhs == 1 ? t1 : tm).push_back(T);
             }
+            rts.push_back(r);
         }
     }
+    // multi right-hand-side tiles: MFMA ones first
+    std::stable_partition(tm.begin(), tm.end(), [&](const NearTile& T) { return probs[size_t(T.prob)].nrhs >= 16; });
+    int64_t nmfma = 0;
+    for (auto& T : tm) nmfma += probs[size_t(T.prob)].nrhs >= 16;
+
+    // ---------- far field descriptors, by wave ----------
+    struct Launch {
+        bool fp32;
+        int32_t L1, L2;
+        size_t d0, d1;           // descriptors [d0, d1)
+        size_t a0, a1, b0, b1;   // workgroup maps of the column passes and of pass B
+        double bytesA, bytesB, bytesC, work;
+    };
+    std::vector<FarDesc> descs;
+    std::vector<WgMap> maps;
+    std::vector<Launch> launches;
+    size_t maxblocks = 0;
+    for (auto& J : jobs) maxblocks = std::max(maxblocks, J.dp->blocks.size());
+    const size_t budget = wave_budget();
+    size_t work_need = 0;
+    for (size_t bi = 0; bi < maxblocks; ++bi) {
+        // (job, group range) items of this wave
+        struct Item {
+            size_t job;
+            int32_t g0, g1;
+        };
+        std::vector<std::vector<Item>> sub(1);
+        std::vector<size_t> subbytes(1, 0);
+        for (size_t ji = 0; ji < jobs.size(); ++ji) {
+            Job& J = jobs[ji];
+            if (bi >= J.dp->blocks.size()) continue;
+            const DevBlock& d = J.dp->blocks[bi];
+            const size_t per_group = size_t(d.args.L) * (J.dp->plan.fp32 ? 8 : 16) * size_t(J.nrhs);
+            size_t gb = std::max<size_t>(1, std::min<size_t>(size_t(d.args.ngroups), budget / per_group));
+            gb = std::min(gb, group_batch(size_t(d.args.L) * (J.dp->plan.fp32 ? 8 : 16), size_t(d.args.ngroups)));
+            int si = 0;
+            for (int32_t g0 = 0; g0 < d.args.ngroups; g0 += int32_t(gb), ++si) {
+                const int32_t g1 = std::min(d.args.ngroups, g0 + int32_t(gb));
+                const size_t need = per_group * size_t(g1 - g0);
+                // group batches of one block go to successive sub-waves
+                size_t k = size_t(si);
+                while (k < sub.size() && subbytes[k] + need > budget && subbytes[k] > 0) ++k;
+                if (k >= sub.size()) {
+                    sub.emplace_back();
+                    subbytes.push_back(0);
+                    k = sub.size() - 1;
+                }
+                sub[k].push_back(Item{ji, g0, g1});
+                subbytes[k] += need;
+                si = int(k);
+            }
+        }
+        for (size_t k = 0; k < sub.size(); ++k) {
+            if (sub[k].empty()) continue;
+            // one launch set per FFT shape and precision
+            std::map<std::tuple<bool, int32_t, int32_t>, std::vector<Item>> shapes;
+            for (auto& it : sub[k]) {
+                const Job& J = jobs[it.job];
+                const DevBlock& d = J.dp->blocks[bi];
+                shapes[{J.dp->plan.fp32, d.args.L1, d.args.L2}].push_back(it);
+            }
+            size_t off = 0; // bytes within the work buffer for this sub-wave
+            for (auto& kv : shapes) {
+                Launch Ln{};
+                Ln.fp32 = std::get<0>(kv.first);
+                Ln.L1 = std::get<1>(kv.first);
+                Ln.L2 = std::get<2>(kv.first);
+                const double esz = Ln.fp32 ? 8.0 : 16.0;
+                Ln.d0 = descs.size();
+                Ln.a0 = maps.size();
+                for (auto& it : kv.second) {
+                    const Job& J = jobs[it.job];
+                    const DevBlock& d = J.dp->blocks[bi];
+                    FarDesc D{};
+                    D.A = d.args;
+                    D.A.g0 = it.g0;
+                    D.A.g1 = it.g1;
+                    D.c = J.c;
+                    D.b = J.dp->b;
+                    D.e = J.dp->e;
+                    D.f = J.f;
+                    D.H = d.H;
+                    D.ldc = J.ldc;
+                    D.ldo = J.ldo;
+                    D.nrhs = int32_t(J.nrhs);
+                    D.buf = reinterpret_cast<void*>(off); // offset, made absolute below
+                    const double GL = double(it.g1 - it.g0) * double(J.nrhs) * double(d.args.L);
+                    off += size_t(GL * esz);
+                    Ln.bytesA += GL * esz + double(d.args.ncols) * (8.0 * double(J.nrhs) + (d.args.col_pert ? 8.0 : 0.0));
+                    Ln.bytesB += 2.0 * GL * esz + double(d.args.L) * esz;
+                    Ln.bytesC += GL * esz + double(d.args.nrows) * (16.0 * double(J.nrhs) + (d.args.row_pert ? 8.0 : 0.0));
+                    Ln.work += GL;
+                    const int32_t di = int32_t(descs.size());
+                    descs.push_back(D);
+                    for (int32_t w = 0; w < d.args.L1 / 8; ++w) maps.push_back(WgMap{di, w});
+                }
+                Ln.d1 = descs.size();
+                Ln.a1 = maps.size();
+                Ln.b0 = maps.size();
+                const int32_t rows = far_rows_per_wg(Ln.L1);
+                for (size_t di = Ln.d0; di < Ln.d1; ++di) {
+                    const int32_t nb = (descs[di].A.L2 + rows - 1) / rows;
+                    for (int32_t w = 0; w < nb; ++w) maps.push_back(WgMap{int32_t(di), w});
+                }
+                Ln.b1 = maps.size();
+                launches.push_back(Ln);
+            }
+            work_need = std::max(work_need, off);
+            launches.push_back(Launch{false, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}); // sub-wave boundary
+        }
+    }
+
+    // ---------- uploads (skipped when identical to the previous call) ----------
+    if ((st = ensure(g_ex.work, work_need, s))) return st;
+    for (auto& D : descs) D.buf = static_cast<char*>(g_ex.work.p) + reinterpret_cast<size_t>(D.buf);
+    if ((st = ensure(g_ex.partial, size_t(std::max<int64_t>(pbase, 1)) * sizeof(double), s))) return st;
+    std::vector<char> sig;
+    auto add = [&](const void* p, size_t n) {
+        const char* q = static_cast<const char*>(p);
+        sig.insert(sig.end(), q, q + n);
+    };
+    add(probs.data(), probs.size() * sizeof(NearProb));
+    add(t1.data(), t1.size() * sizeof(NearTile));
+    add(tm.data(), tm.size() * sizeof(NearTile));
+    add(rts.data(), rts.size() * sizeof(RowTile));
+    add(descs.data(), descs.size() * sizeof(FarDesc));
+    add(maps.data(), maps.size() * sizeof(WgMap));
+    if (sig != g_ex.sig) {
+        if ((st = upload(g_ex.probs, probs, s))) return st;
+        if ((st = upload(g_ex.tiles1, t1, s))) return st;
+        if ((st = upload(g_ex.tilesm, tm, s))) return st;
+        if ((st = upload(g_ex.rts, rts, s))) return st;
+        if ((st = upload(g_ex.descs, descs, s))) return st;
+        if ((st = upload(g_ex.maps, maps, s))) return st;
+        g_ex.sig.swap(sig);
+    }
+    const NearProb* dprobs = static_cast<const NearProb*>(g_ex.probs.p);
+    double* dpart = static_cast<double*>(g_ex.partial.p);
+
+    // ---------- launches ----------
+    hipEvent_t ev;
+    double near_entries = 0, multi_entries = 0;
+    for (auto& J : jobs) (J.nrhs == 1 ? near_entries : multi_entries) += double(J.dp->plan.near_entries) * double(J.nrhs);
+    if (!t1.empty()) {
+        if ((st = prof_begin(ev, s))) return st;
+        HIP_TRY(launch_near(dprobs, static_cast<const NearTile*>(g_ex.tiles1.p), int64_t(t1.size()), dpart, s));
+        if ((st = prof_end(K_NEAR, ev, 8.0 * 64.0 * double(t1.size()), near_entries, s))) return st;
+    }
+    if (!tm.empty()) {
+        if ((st = prof_begin(ev, s))) return st;
+        const NearTile* dtm = static_cast<const NearTile*>(g_ex.tilesm.p);
+        HIP_TRY(launch_near_multi(dprobs, dtm, nmfma, true, dpart, s));
+        HIP_TRY(launch_near_multi(dprobs, dtm + nmfma, int64_t(tm.size()) - nmfma, false, dpart, s));
+        if ((st = prof_end(K_NEAR_MULTI, ev, 0.0, multi_entries, s))) return st;
+    }
+    if ((st = prof_begin(ev, s))) return st;
+    HIP_TRY(launch_near_reduce(static_cast<const RowTile*>(g_ex.rts.p), int64_t(rts.size()), dpart, s));
+    if ((st = prof_end(K_NEAR_REDUCE, ev, 8.0 * double(pbase), 0.0, s))) return st;
+
+    const FarDesc* ddesc = static_cast<const FarDesc*>(g_ex.descs.p);
+    const WgMap* dmap = static_cast<const WgMap*>(g_ex.maps.p);
+    for (auto& Ln : launches) {
+        if (Ln.L1 == 0) continue; // sub-wave boundary: the stream orders the waves
+        const double bytes[3] = {Ln.bytesA, Ln.bytesB, Ln.bytesC};
+        for (int w = 0; w < 3; ++w) {
+            if ((st = prof_begin(ev, s))) return st;
+            const size_t m0 = (w == 1) ? Ln.b0 : Ln.a0, m1 = (w == 1) ? Ln.b1 : Ln.a1;
+            HIP_TRY(launch_far_pass(w, Ln.fp32, Ln.L1, Ln.L2, ddesc, dmap + m0, int64_t(m1 - m0), s));
+            if ((st = prof_end(K_PASS_A + w, ev, bytes[w], Ln.work, s))) return st;
+        }
+    }
+    HIP_TRY(hipEventRecord(g_ex.done, s));
+    g_ex.last = s;
+    g_ex.used = true;
     return HANK_OK;
 }
 
@@ -417,12 +659,289 @@ hank_status transform(int32_t task, const double* c, int64_t N, int64_t nrhs, in
     hipStream_t s = (hipStream_t)stream;
     DevPlan* dp = nullptr;
     if ((st = get_plan(task, N, eps, o, s, dp))) return st;
-    for (int64_t j = 0; j < nrhs; ++j)
-        if ((st = run_plan(*dp, c + j * ldc, out + j * ldo, s))) return st;
-    return HANK_OK;
+    std::vector<Job> jobs{Job{dp, c, ldc, out, ldo, nrhs}};
+    return run_jobs(jobs, s);
+}
+
+// Device bytes a request occupies while in flight: the far-field workspace
+// of its largest block plus its near-field partials.
+int64_t request_bytes(const DevPlan& dp, int64_t nrhs) {
+    const double esz = dp.plan.fp32 ? 8.0 : 16.0;
+    double far = 0;
+    for (auto& b : dp.blocks) far = std::max(far, double(b.args.L) * double(b.args.ngroups) * esz * double(nrhs));
+    return int64_t(far + double(dp.tiles.size()) * 64.0 * 8.0 * double(nrhs));
 }
 
 } // namespace
+
+// ---------------------------------------------------------------------------
+// Continuous-batching server
+// ---------------------------------------------------------------------------
+struct hank_server {
+    using clock = std::chrono::steady_clock;
+    struct Rec {
+        hank_request req;
+        double arrival = 0; // seconds after start
+        double done = -1;
+        int32_t state = 0;
+        int64_t bytes = 0;
+    };
+    struct Batch {
+        std::vector<int64_t> tickets;
+        hipEvent_t ev = nullptr;
+        int64_t bytes = 0;
+    };
+    int64_t budget = 0, max_pending = 0;
+    int32_t max_batch = 1;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<Rec> recs;
+    std::vector<int64_t> order; // tickets sorted by arrival (built at start)
+    size_t next_arrival = 0;    // index into order of the next not-yet-arrived request
+    std::deque<int64_t> waiting;
+    std::deque<Batch> inflight;
+    int64_t inflight_bytes = 0;
+    int64_t batches = 0, batched = 0;
+    bool started = false, stop = false;
+    clock::time_point t0;
+    std::thread worker;
+    hank_status error = HANK_OK;
+    std::string error_msg;
+
+    double now() const { return std::chrono::duration<double>(clock::now() - t0).count(); }
+
+    void run() {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        while (true) {
+            if (!started) {
+                if (stop) break;
+                cv.wait(lk);
+                continue;
+            }
+            const double t = now();
+            // arrivals: into the queue, or rejected when the queue is full
+            while (next_arrival < order.size() && recs[size_t(order[next_arrival])].arrival <= t) {
+                Rec& r = recs[size_t(order[next_arrival])];
+                if (int64_t(waiting.size()) >= max_pending || r.bytes > budget)
+                    r.state = 3;
+                else
+                    waiting.push_back(order[next_arrival]);
+                ++next_arrival;
+            }
+            // retire finished batches
+            while (!inflight.empty() && hipEventQuery(inflight.front().ev) == hipSuccess) {
+                const double td = now();
+                for (int64_t tk : inflight.front().tickets) {
+                    recs[size_t(tk)].state = 2;
+                    recs[size_t(tk)].done = td;
+                }
+                inflight_bytes -= inflight.front().bytes;
+                (void)hipEventDestroy(inflight.front().ev);
+                inflight.pop_front();
+                cv.notify_all();
+            }
+            // admit a batch
+            if (inflight.size() < 2 && !waiting.empty()) {
+                Batch b;
+                std::vector<hank_request> reqs;
+                while (!waiting.empty() && int32_t(b.tickets.size()) < max_batch) {
+                    Rec& r = recs[size_t(waiting.front())];
+                    if (!b.tickets.empty() && inflight_bytes + b.bytes + r.bytes > budget) break;
+                    if (b.tickets.empty() && inflight_bytes > 0 && inflight_bytes + r.bytes > budget) break;
+                    b.tickets.push_back(waiting.front());
+                    b.bytes += r.bytes;
+                    r.state = 1;
+                    reqs.push_back(r.req);
+                    waiting.pop_front();
+                }
+                if (!b.tickets.empty()) {
+                    lk.unlock();
+                    hank_status st = hank_batch(reqs.data(), int64_t(reqs.size()), stream);
+                    if (st == HANK_OK && hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) == hipSuccess &&
+                        hipEventRecord(b.ev, stream) == hipSuccess) {
+                        lk.lock();
+                        inflight_bytes += b.bytes;
+                        inflight.push_back(b);
+                        ++batches;
+                        batched += int64_t(b.tickets.size());
+                    } else {
+                        lk.lock();
+                        error = st ? st : HANK_EDEVICE;
+                        error_msg = hank_last_error();
+                        for (int64_t tk : b.tickets) recs[size_t(tk)].state = 3;
+                        cv.notify_all();
+                    }
+                    continue;
+                }
+            }
+            const bool all_arrived = next_arrival >= order.size();
+            if (stop && all_arrived && waiting.empty() && inflight.empty()) break;
+            if (all_arrived && waiting.empty() && inflight.empty()) {
+                cv.notify_all();
+                cv.wait_for(lk, std::chrono::milliseconds(1));
+                continue;
+            }
+            // short wait: the next arrival or a batch completing
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        }
+        (void)hipSetDevice(cur);
+    }
+};
+
+extern "C" {
+
+hank_status hank_server_create(int64_t budget_bytes, int32_t max_batch, int64_t max_pending, hank_stream_t stream,
+                               hank_server** out) {
+    if (!out || budget_bytes <= 0 || max_batch < 1 || max_pending < 1) return fail(HANK_EINVAL, "bad server arguments");
+    hank_server* s = new hank_server;
+    s->budget = budget_bytes;
+    s->max_batch = max_batch;
+    s->max_pending = max_pending;
+    s->stream = (hipStream_t)stream;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(HANK_EDEVICE, "hipGetDevice failed");
+    }
+    s->worker = std::thread([s] { s->run(); });
+    *out = s;
+    return HANK_OK;
+}
+
+hank_status hank_server_warm(hank_server* srv, const hank_request* r) {
+    if (!srv || !r) return fail(HANK_EINVAL, "null pointer");
+    hank_status st = check_args(r->task, r->c, r->N, r->nrhs, r->ldc, r->eps, r->out, r->ldo);
+    if (st) return st;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    hank_options o{};
+    o.precision = r->precision;
+    DevPlan* dp = nullptr;
+    return get_plan(r->task, r->N, r->eps, &o, srv->stream, dp);
+}
+
+hank_status hank_server_submit(hank_server* srv, const hank_request* r, double arrival_s, int64_t* ticket) {
+    if (!srv || !r || !ticket) return fail(HANK_EINVAL, "null pointer");
+    hank_status st = check_args(r->task, r->c, r->N, r->nrhs, r->ldc, r->eps, r->out, r->ldo);
+    if (st) return st;
+    int64_t bytes = 0;
+    {
+        std::lock_guard<std::recursive_mutex> lk(g_mu);
+        hank_options o{};
+        o.precision = r->precision;
+        DevPlan* dp = nullptr;
+        if ((st = get_plan(r->task, r->N, r->eps, &o, srv->stream, dp))) return st;
+        bytes = request_bytes(*dp, r->nrhs);
+    }
+    std::lock_guard<std::mutex> lk(srv->mu);
+    hank_server::Rec rec;
+    rec.req = *r;
+    rec.bytes = bytes;
+    rec.arrival = (arrival_s < 0 && srv->started) ? srv->now() : std::max(0.0, arrival_s);
+    *ticket = int64_t(srv->recs.size());
+    srv->recs.push_back(rec);
+    if (srv->started) { // keep `order` sorted by arrival for the not-yet-arrived part
+        auto pos = std::upper_bound(srv->order.begin() + long(srv->next_arrival), srv->order.end(), rec.arrival,
+                                    [&](double a, int64_t t) { return a < srv->recs[size_t(t)].arrival; });
+        srv->order.insert(pos, *ticket);
+    }
+    srv->cv.notify_all();
+    return HANK_OK;
+}
+
+hank_status hank_server_start(hank_server* srv) {
+    if (!srv) return fail(HANK_EINVAL, "null pointer");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->started) return HANK_OK;
+    srv->order.resize(srv->recs.size());
+    for (size_t i = 0; i < srv->order.size(); ++i) srv->order[i] = int64_t(i);
+    std::stable_sort(srv->order.begin(), srv->order.end(),
+                     [&](int64_t a, int64_t b) { return srv->recs[size_t(a)].arrival < srv->recs[size_t(b)].arrival; });
+    srv->t0 = hank_server::clock::now();
+    srv->started = true;
+    srv->cv.notify_all();
+    return HANK_OK;
+}
+
+hank_status hank_server_drain(hank_server* srv) {
+    if (!srv) return fail(HANK_EINVAL, "null pointer");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (!srv->started) return fail(HANK_EINVAL, "server not started");
+    srv->cv.wait(lk, [&] {
+        if (srv->next_arrival < srv->order.size() || !srv->waiting.empty() || !srv->inflight.empty()) return false;
+        return true;
+    });
+    if (srv->error) return fail(srv->error, srv->error_msg);
+    return HANK_OK;
+}
+
+hank_status hank_server_status(hank_server* srv, int64_t ticket, int32_t* state, double* latency_ms) {
+    if (!srv || !state) return fail(HANK_EINVAL, "null pointer");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (ticket < 0 || ticket >= int64_t(srv->recs.size())) return fail(HANK_EINVAL, "unknown ticket");
+    const hank_server::Rec& r = srv->recs[size_t(ticket)];
+    *state = r.state;
+    if (latency_ms) *latency_ms = r.state == 2 ? 1e3 * (r.done - r.arrival) : -1.0;
+    return HANK_OK;
+}
+
+hank_status hank_server_stats(hank_server* srv, hank_server_summary* out) {
+    if (!srv || !out) return fail(HANK_EINVAL, "null pointer");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    hank_server_summary st{};
+    std::vector<double> lat;
+    double first = 1e300, last = 0;
+    for (auto& r : srv->recs) {
+        ++st.submitted;
+        first = std::min(first, r.arrival);
+        if (r.state == 3) ++st.rejected;
+        if (r.state == 2) {
+            lat.push_back(1e3 * (r.done - r.arrival));
+            last = std::max(last, r.done);
+        }
+    }
+    st.completed = int64_t(lat.size());
+    st.batches = srv->batches;
+    st.mean_batch = srv->batches ? double(srv->batched) / double(srv->batches) : 0.0;
+    if (!lat.empty()) {
+        std::sort(lat.begin(), lat.end());
+        auto pct = [&](double q) { return lat[std::min(lat.size() - 1, size_t(q * double(lat.size() - 1) + 0.5))]; };
+        st.p50_ms = pct(0.50);
+        st.p90_ms = pct(0.90);
+        st.p99_ms = pct(0.99);
+        st.max_ms = lat.back();
+        double sum = 0;
+        for (double v : lat) sum += v;
+        st.mean_ms = sum / double(lat.size());
+        st.wall_s = last - first;
+        st.throughput = st.wall_s > 0 ? double(st.completed) / st.wall_s : 0.0;
+    }
+    *out = st;
+    return HANK_OK;
+}
+
+hank_status hank_server_destroy(hank_server* srv) {
+    if (!srv) return fail(HANK_EINVAL, "null pointer");
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        if (!srv->started) {
+            srv->started = true; // let the worker drain nothing and exit
+            srv->t0 = hank_server::clock::now();
+        }
+        srv->cv.notify_all();
+    }
+    srv->worker.join();
+    delete srv;
+    return HANK_OK;
+}
+
+} // extern "C"
 
 extern "C" {
 
@@ -449,15 +968,66 @@ hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t st
         const hank_request& r = reqs[i];
         hank_status st = check_args(r.task, r.c, r.N, r.nrhs, r.ldc, r.eps, r.out, r.ldo);
         if (st) return fail(st, "request " + std::to_string(i) + ": " + t_err);
+        for (int64_t j = 0; j < i; ++j) { // outputs must not overlap each other
+            const hank_request& q = reqs[j];
+            uintptr_t a0 = uintptr_t(r.out), a1 = uintptr_t(r.out + (r.nrhs - 1) * r.ldo + r.N);
+            uintptr_t b0 = uintptr_t(q.out), b1 = uintptr_t(q.out + (q.nrhs - 1) * q.ldo + q.N);
+            if (a0 < b1 && b0 < a1) return fail(HANK_EINVAL, "request " + std::to_string(i) + ": output overlaps request " + std::to_string(j));
+            uintptr_t c0 = uintptr_t(q.c), c1 = uintptr_t(q.c + (q.nrhs - 1) * q.ldc + q.N);
+            uintptr_t d0 = uintptr_t(r.c), d1 = uintptr_t(r.c + (r.nrhs - 1) * r.ldc + r.N);
+            if ((a0 < c1 && c0 < a1) || (b0 < d1 && d0 < b1))
+                return fail(HANK_EINVAL, "requests " + std::to_string(j) + " and " + std::to_string(i) + ": an output overlaps an input");
+        }
     }
+    if (count == 0) return HANK_OK;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    // host planning of the keys not cached yet, in parallel threads
+    std::map<Key, std::pair<int64_t, Plan>> fresh;
+    for (int64_t i = 0; i < count; ++i) {
+        hank_options o{};
+        o.precision = reqs[i].precision;
+        Key k = plan_key(reqs[i].task, reqs[i].N, reqs[i].eps, &o, dev);
+        if (!g_cache.count(k) && !fresh.count(k)) fresh[k] = {i, Plan()};
+    }
+    if (fresh.size() > 1) {
+        std::vector<std::pair<const Key, std::pair<int64_t, Plan>>*> todo;
+        for (auto& kv : fresh) todo.push_back(&kv);
+        std::atomic<size_t> next{0};
+        std::atomic<bool> bad{false};
+        auto worker = [&]() {
+            for (size_t t; (t = next++) < todo.size();) {
+                const hank_request& r = reqs[todo[t]->second.first];
+                hank_options o{};
+                o.precision = r.precision;
+                try {
+                    todo[t]->second.second = make_plan(r.task, r.N, r.eps, 0, r.precision, false, cost_model_for(&o));
+                } catch (...) {
+                    bad = true;
+                }
+            }
+        };
+        unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> th;
+        for (unsigned i = 0; i < nt; ++i) th.emplace_back(worker);
+        for (auto& t : th) t.join();
+        if (bad) return fail(HANK_EINVAL, "planning failed for a request");
+    }
+    std::vector<Job> jobs;
     for (int64_t i = 0; i < count; ++i) {
         const hank_request& r = reqs[i];
         hank_options o{};
         o.precision = r.precision;
-        hank_status st = transform(r.task, r.c, r.N, r.nrhs, r.ldc, r.eps, r.out, r.ldo, &o, stream);
+        DevPlan* dp = nullptr;
+        auto it = fresh.find(plan_key(r.task, r.N, r.eps, &o, dev));
+        const Plan* pre = (fresh.size() > 1 && it != fresh.end()) ? &it->second.second : nullptr;
+        hank_status st = get_plan(r.task, r.N, r.eps, &o, s, dp, pre);
         if (st) return st;
+        jobs.push_back(Job{dp, r.c, r.ldc, r.out, r.ldo, r.nrhs});
     }
-    return HANK_OK;
+    return run_jobs(jobs, s);
 }
 
 const char* hank_last_error(void) { return t_err.c_str(); }

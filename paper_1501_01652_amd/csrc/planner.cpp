@@ -64,17 +64,18 @@ Grid make_grid(int task, int64_t N) {
 double hankel_a(int m, int nu) {
     // a_m(nu) for the orders and term counts the planner uses, tabulated once
     static const int NUS = 48, MS = 64;
-    static double tab[NUS][MS];
-    static bool init = false;
-    if (!init) {
-        for (int n = 0; n < NUS; ++n) {
-            tab[n][0] = 1.0;
-            for (int i = 1; i < MS; ++i)
-                tab[n][i] = tab[n][i - 1] * (4.0 * n * n - double(2 * i - 1) * double(2 * i - 1)) / (8.0 * i);
+    struct Tab {
+        double v[NUS][MS];
+        Tab() {
+            for (int n = 0; n < NUS; ++n) {
+                v[n][0] = 1.0;
+                for (int i = 1; i < MS; ++i)
+                    v[n][i] = v[n][i - 1] * (4.0 * n * n - double(2 * i - 1) * double(2 * i - 1)) / (8.0 * i);
+            }
         }
-        init = true;
-    }
-    if (nu >= 0 && nu < NUS && m >= 0 && m < MS) return tab[nu][m];
+    };
+    static const Tab tab; // thread-safe one-time initialisation
+    if (nu >= 0 && nu < NUS && m >= 0 && m < MS) return tab.v[nu][m];
     double v = 1.0;
     for (int i = 1; i <= m; ++i) v *= (4.0 * nu * nu - double(2 * i - 1) * double(2 * i - 1)) / (8.0 * i);
     return v;

@@ -58,3 +58,44 @@ def sampled_rows(N: int, count: int, boundaries=(), seed: int = SEED_SAMPLED_ROW
     while len(rows) < min(count, N):
         rows.add(int(rng.integers(1, N + 1)))
     return np.array(sorted(rows), dtype=np.int64)
+
+
+TASK_MIX = (("schlomilch", 0.4), ("fourier_bessel", 0.4), ("dht0", 0.2))
+EPS_SET = (1e-4, 1e-8, 1e-14)
+
+
+def batch_specs(count: int = 1024, seed: int = SEED_BATCH, nlo: int = 2 ** 8, nhi: int = 2 ** 16,
+                rhs_max: int = 64):
+    """Request specs of the batched workload: task 40/40/20 (Schlomilch,
+    Fourier-Bessel, DHT), N log-uniform in [nlo, nhi], 1..rhs_max right-hand
+    sides, eps from {1e-4, 1e-8, 1e-14}, and a per-request seed for c ~ U[-1, 1]."""
+    rng = np.random.default_rng(seed)
+    names = [t for t, _ in TASK_MIX]
+    probs = [p for _, p in TASK_MIX]
+    specs = []
+    for i in range(count):
+        specs.append({"task": names[int(rng.choice(3, p=probs))],
+                      "N": int(np.exp(rng.uniform(np.log(nlo), np.log(nhi)))),
+                      "nrhs": int(rng.integers(1, rhs_max + 1)),
+                      "eps": float(EPS_SET[int(rng.integers(0, 3))]),
+                      "seed": int(seed * 10007 + i)})
+    return specs
+
+
+def serve_trace(rate: float = 2000.0, seconds: float = 60.0, seed: int = SEED_SERVE,
+                lg_lo: int = 10, lg_hi: int = 22):
+    """Open-loop Poisson arrivals at `rate` per second for `seconds`: the same
+    task and eps mix, one right-hand side, N log-uniform over the sizes
+    2^lg_lo .. 2^lg_hi (a grid, so that plans can be kept on the device)."""
+    rng = np.random.default_rng(seed)
+    names = [t for t, _ in TASK_MIX]
+    probs = [p for _, p in TASK_MIX]
+    t, out = 0.0, []
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= seconds:
+            break
+        out.append({"arrival": t, "task": names[int(rng.choice(3, p=probs))],
+                    "N": int(2 ** int(rng.integers(lg_lo, lg_hi + 1))),
+                    "eps": float(EPS_SET[int(rng.integers(0, 3))])})
+    return out

@@ -133,14 +133,21 @@ def test_deterministic_and_linear():
         assert np.max(np.abs(fab - (2.0 * fa - 3.0 * fb))) <= 1e-12 * np.sum(np.abs(a) + np.abs(b))
 
 
-def test_multiple_right_hand_sides():
-    N, nrhs = 3000, 5
-    rng = np.random.default_rng(12)
+@pytest.mark.parametrize("nrhs", [2, 5, 16, 23, 64])
+@pytest.mark.parametrize("task", ["fourier_bessel", "dht0"])
+def test_multiple_right_hand_sides(task, nrhs):
+    """nrhs columns in one call (near field: J_0 once per entry, FMA below 16
+    columns, FP64 MFMA from 16): every column against the oracle, and against
+    the single-column call to rounding."""
+    N, eps = 1500, 1e-8
+    rng = np.random.default_rng(12 + nrhs)
     C = rng.standard_normal((nrhs, N))
-    F = host(hank.transform("dht0", dev(C), 1e-8))
-    for j in range(nrhs):
-        fj = host(hank.transform("dht0", dev(C[j]), 1e-8))
-        assert np.array_equal(F[j], fj)
+    F = host(hank.transform(task, dev(C), eps, prefer_far=1))
+    for j in (0, nrhs // 2, nrhs - 1):
+        ref = oracle.eval_rows(task, C[j])
+        assert np.max(np.abs(F[j] - ref)) <= C_TOL * eps * np.sum(np.abs(C[j]))
+        fj = host(hank.transform(task, dev(C[j]), eps, prefer_far=1))
+        assert np.max(np.abs(F[j] - fj)) <= 1e-14 * np.sum(np.abs(C[j]))
 
 
 def test_named_entry_points_match_generic():
@@ -163,3 +170,53 @@ def test_errors_leave_output_untouched():
     with pytest.raises(hank.HankError):  # out overlapping c
         hank.transform("dht0", c, 1e-8, out=c)
     assert np.all(host(out) == 7.0)
+
+
+def _mixed_requests(seed, count, nmax=3000):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        task = ["schlomilch", "fourier_bessel", "dht0"][int(rng.integers(0, 3))]
+        N = int(np.exp(rng.uniform(np.log(64), np.log(nmax))))
+        nrhs = int(rng.choice([1, 1, 2, 7, 16, 20]))
+        eps = float(rng.choice([1e-4, 1e-8, 1e-14]))
+        c = rng.uniform(-1, 1, (nrhs, N)) if nrhs > 1 else rng.uniform(-1, 1, N)
+        reqs.append({"task": task, "c": dev(c), "out": dev(np.zeros_like(c)), "eps": eps, "host": c})
+    return reqs
+
+
+def test_batch_matches_oracle():
+    reqs = _mixed_requests(21, 24)
+    hank.batch(reqs)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for r in reqs:
+        c = r["host"].reshape(-1, r["host"].shape[-1])
+        f = host(r["out"]).reshape(c.shape)
+        for j in range(c.shape[0]):
+            ref = oracle.eval_rows(r["task"], c[j])
+            Cm = np.max(np.abs(f[j] - ref)) / (r["eps"] * np.sum(np.abs(c[j])))
+            worst = max(worst, Cm)
+    print("batch of %d mixed requests: worst measured C = %.3g" % (len(reqs), worst))
+    assert worst <= C_TOL
+
+
+def test_batch_alone_equals_in_the_mix():
+    """A request gives bitwise the same result alone and inside a batch."""
+    reqs = _mixed_requests(22, 16)
+    hank.batch(reqs)
+    mixed = [host(r["out"]).copy() for r in reqs]
+    for r, m in zip(reqs, mixed):
+        alone = dict(r, out=dev(np.zeros_like(r["host"])))
+        hank.batch([alone])
+        assert np.array_equal(host(alone["out"]), m)
+
+
+def test_batch_rejects_overlap_and_writes_nothing():
+    c = dev(np.ones(500))
+    out = dev(np.full(500, 3.0))
+    r1 = {"task": "dht0", "c": c, "out": out, "eps": 1e-8}
+    r2 = {"task": "dht0", "c": out, "out": dev(np.zeros(500)), "eps": 1e-8}
+    with pytest.raises(hank.HankError):
+        hank.batch([r1, r2])
+    assert np.all(host(out) == 3.0)
