@@ -71,6 +71,11 @@ typedef struct {
                            O(N^2) direct-summation baseline of Sec. 2.1)             */
     int32_t prefer_far; /* 1: tuned mode prices direct entries 1000x higher, so the
                            fast method is used wherever it is valid (small N tests)  */
+    int32_t nrhs;       /* hank_plan_info / hank_plan_block only: right-hand sides to
+                           plan for (0 means 1).  The transform calls plan for their
+                           own nrhs (rounded up to a power of two, at most 64): with
+                           several right-hand sides J_0 is evaluated once per direct
+                           entry, so the tuned partition moves toward the near field */
 } hank_options;
 
 /* ---- The three transforms (Sec. 4, 5, 6) ---------------------------------

@@ -40,7 +40,7 @@ class HankError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("plan_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("direct", ctypes.c_int32), ("prefer_far", ctypes.c_int32)]
+                ("direct", ctypes.c_int32), ("prefer_far", ctypes.c_int32), ("nrhs", ctypes.c_int32)]
 
 
 class PlanSummary(ctypes.Structure):
@@ -133,8 +133,8 @@ def _task(task) -> int:
     return TASKS[task] if isinstance(task, str) else int(task)
 
 
-def _options(plan_mode=0, precision=0, direct=0, prefer_far=0) -> Options:
-    return Options(int(plan_mode), int(precision), int(direct), int(prefer_far))
+def _options(plan_mode=0, precision=0, direct=0, prefer_far=0, nrhs=0) -> Options:
+    return Options(int(plan_mode), int(precision), int(direct), int(prefer_far), int(nrhs))
 
 
 def _stream(stream):
@@ -219,26 +219,27 @@ def batch(requests, stream=None):
 
 
 def plan_info(task, N: int, eps: float, plan_mode: int = 0, precision: int = 0, direct: int = 0,
-              prefer_far: int = 0) -> dict:
-    """Parameters and costs of the plan the library would use (host only)."""
+              prefer_far: int = 0, nrhs: int = 1) -> dict:
+    """Parameters and costs of the plan the library would use for nrhs
+    right-hand sides (host only)."""
     s = PlanSummary()
-    opts = _options(plan_mode, precision, direct, prefer_far)
+    opts = _options(plan_mode, precision, direct, prefer_far, nrhs)
     _check(lib().hank_plan_info(_task(task), int(N), float(eps), ctypes.byref(opts), ctypes.byref(s)))
     return {name: getattr(s, name) for name, _ in PlanSummary._fields_}
 
 
 def plan_block(task, N: int, eps: float, k: int, plan_mode: int = 0, precision: int = 0,
-               prefer_far: int = 0) -> dict:
+               prefer_far: int = 0, nrhs: int = 1) -> dict:
     b = BlockInfo()
-    opts = _options(plan_mode, precision, 0, prefer_far)
+    opts = _options(plan_mode, precision, 0, prefer_far, nrhs)
     _check(lib().hank_plan_block(_task(task), int(N), float(eps), ctypes.byref(opts), int(k), ctypes.byref(b)))
     return {name: getattr(b, name) for name, _ in BlockInfo._fields_}
 
 
 def plan_blocks(task, N: int, eps: float, plan_mode: int = 0, precision: int = 0,
-                prefer_far: int = 0) -> list:
-    n = plan_info(task, N, eps, plan_mode, precision, prefer_far=prefer_far)["nblocks"]
-    return [plan_block(task, N, eps, k, plan_mode, precision, prefer_far) for k in range(n)]
+                prefer_far: int = 0, nrhs: int = 1) -> list:
+    n = plan_info(task, N, eps, plan_mode, precision, prefer_far=prefer_far, nrhs=nrhs)["nblocks"]
+    return [plan_block(task, N, eps, k, plan_mode, precision, prefer_far, nrhs) for k in range(n)]
 
 
 def param_s(nu: int, M: int, eps: float) -> float:

@@ -122,6 +122,8 @@ CostModel cost_model_for(const hank_options* o) {
     CostModel cm = cost_model_from_env();
     if (o && o->prefer_far) {
         cm.near_entry *= 1000.0;
+        cm.near_multi_entry *= 1000.0;
+        cm.near_rhs *= 1000.0;
         cm.block = 0.0;
     }
     return cm;
@@ -271,22 +273,30 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
     return HANK_OK;
 }
 
-Key plan_key(int task, int64_t N, double eps, const hank_options* o, int dev) {
+// Right-hand sides a plan is balanced for: nrhs rounded up to a power of two
+// (at most 64); plans are cached per bucket.
+int64_t rhs_bucket(int64_t nrhs) {
+    int64_t b = 1;
+    while (b < nrhs && b < 64) b *= 2;
+    return b;
+}
+
+Key plan_key(int task, int64_t N, double eps, const hank_options* o, int dev, int64_t nrhs) {
     int mode = o ? o->plan_mode : 0, prec = o ? o->precision : 0, direct = o ? o->direct : 0;
     int far = o ? o->prefer_far : 0;
     uint64_t eb;
     std::memcpy(&eb, &eps, 8);
-    return Key{task, N, eb, mode, prec, direct * 2 + far, dev};
+    return Key{task, N, eb, mode, prec, (direct * 2 + far) * 128 + int(rhs_bucket(nrhs)), dev};
 }
 
 hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hipStream_t s, DevPlan*& out,
-                     const Plan* prebuilt = nullptr) {
+                     int64_t nrhs = 1, const Plan* prebuilt = nullptr) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     hank_status st = ensure_tables(dev);
     if (st) return st;
     int mode = o ? o->plan_mode : 0, prec = o ? o->precision : 0, direct = o ? o->direct : 0;
-    Key key = plan_key(task, N, eps, o, dev);
+    Key key = plan_key(task, N, eps, o, dev, nrhs);
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
         out = it->second.get();
@@ -295,7 +305,8 @@ hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hip
     std::unique_ptr<DevPlan> dp(new DevPlan);
     dp->device = dev;
     try {
-        dp->plan = prebuilt ? *prebuilt : make_plan(task, N, eps, mode, prec, direct != 0, cost_model_for(o));
+        dp->plan = prebuilt ? *prebuilt
+                            : make_plan(task, N, eps, mode, prec, direct != 0, cost_model_for(o), rhs_bucket(nrhs));
     } catch (const std::exception& ex) {
         return fail(HANK_EINVAL, std::string("planning failed: ") + ex.what());
     }
@@ -307,8 +318,9 @@ hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hip
 }
 
 // ---- optional per-kernel timing (hank_profile) ----
-enum { K_NEAR = 0, K_NEAR_MULTI, K_NEAR_REDUCE, K_PASS_A, K_PASS_B, K_PASS_C, K_COUNT };
-const char* const k_names[K_COUNT] = {"near", "near_multi", "near_reduce", "pass_a", "pass_b", "pass_c"};
+enum { K_NEAR = 0, K_NEAR_MULTI, K_NEAR_REDUCE, K_PASS_A, K_PASS_B, K_PASS_C, K_FAR_REDUCE, K_COUNT };
+const char* const k_names[K_COUNT] = {"near",   "near_multi", "near_reduce", "pass_a",
+                                      "pass_b", "pass_c",     "far_reduce"};
 struct Pending {
     int kind;
     hipEvent_t a, b;
@@ -377,7 +389,7 @@ struct Scratch {
     size_t bytes = 0;
 };
 struct Executor {
-    Scratch probs, tiles1, tilesm, rts, partial, descs, maps, work;
+    Scratch probs, tiles1, tilesm, rts, partial, descs, maps, work, fpart;
     hipEvent_t done = nullptr;
     hipStream_t last = nullptr;
     bool used = false;
@@ -420,6 +432,20 @@ size_t wave_budget() {
         return size_t((v ? std::atof(v) : 4096.0) * 1048576.0);
     }();
     return b;
+}
+
+// Group chunks of a far-field block applied to nrhs right-hand sides: one
+// (rhs, chunk) item is L/8 threads per pass, and enough items run side by side
+// to give the chip about eight waves per compute unit (2048 waves).  A chunk
+// keeps at least two groups so that the per-column set-up is shared.  The
+// rule depends on the request alone, so a request sums in the same order
+// inside any batch.
+int32_t far_chunks(int64_t L, int32_t ngroups, int64_t nrhs) {
+    const double target_threads = 2048.0 * 64.0;
+    const double items = target_threads / (double(L) / 8.0);
+    int64_t want = int64_t(std::ceil(items / double(nrhs)));
+    want = std::min<int64_t>(want, (ngroups + 1) / 2);
+    return int32_t(std::max<int64_t>(1, want));
 }
 
 hank_status run_jobs(std::vector<Job>& jobs, hipStream_t s) {
@@ -467,10 +493,11 @@ hank_status run_jobs(std::vector<Job>& jobs, hipStream_t s) {
     struct Launch {
         bool fp32;
         int32_t L1, L2;
-        size_t d0, d1;           // descriptors [d0, d1)
-        size_t a0, a1, b0, b1;   // workgroup maps of the column passes and of pass B
-        double bytesA, bytesB, bytesC, work;
+        size_t d0, d1;                 // descriptors [d0, d1)
+        size_t a0, a1, b0, b1, r0, r1; // workgroup maps of the column passes, pass B and the chunk reduction
+        double bytesA, bytesB, bytesC, bytesR, work;
     };
+    size_t part_need = 0;
     std::vector<FarDesc> descs;
     std::vector<WgMap> maps;
     std::vector<Launch> launches;
@@ -543,36 +570,72 @@ hank_status run_jobs(std::vector<Job>& jobs, hipStream_t s) {
                     D.ldc = J.ldc;
                     D.ldo = J.ldo;
                     D.nrhs = int32_t(J.nrhs);
-                    D.buf = reinterpret_cast<void*>(off); // offset, made absolute below
-                    const double GL = double(it.g1 - it.g0) * double(J.nrhs) * double(d.args.L);
+                    const int32_t ng = it.g1 - it.g0;
+                    D.nchunk = far_chunks(d.args.L, ng, J.nrhs);
+                    D.gchunk = (ng + D.nchunk - 1) / D.nchunk;
+                    D.nchunk = (ng + D.gchunk - 1) / D.gchunk;
+                    D.buf = reinterpret_cast<void*>(off); // offsets, made absolute below
+                    D.part = nullptr;
+                    const double GL = double(ng) * double(J.nrhs) * double(d.args.L);
                     off += size_t(GL * esz);
-                    Ln.bytesA += GL * esz + double(d.args.ncols) * (8.0 * double(J.nrhs) + (d.args.col_pert ? 8.0 : 0.0));
+                    const double cols = double(d.args.ncols), rws = double(d.args.nrows), nr = double(J.nrhs);
+                    Ln.bytesA += GL * esz + cols * (8.0 * nr + (d.args.col_pert ? 8.0 : 0.0));
                     Ln.bytesB += 2.0 * GL * esz + double(d.args.L) * esz;
-                    Ln.bytesC += GL * esz + double(d.args.nrows) * (16.0 * double(J.nrhs) + (d.args.row_pert ? 8.0 : 0.0));
+                    Ln.bytesC += GL * esz + rws * (d.args.row_pert ? 8.0 : 0.0);
+                    if (D.nchunk > 1) {
+                        D.part = reinterpret_cast<double*>(part_need);
+                        part_need += size_t(D.nchunk) * size_t(J.nrhs) * size_t(d.args.nrows) * sizeof(double);
+                        Ln.bytesC += rws * nr * 8.0 * D.nchunk;
+                        Ln.bytesR += rws * nr * 8.0 * (D.nchunk + 2.0);
+                    } else {
+                        Ln.bytesC += rws * nr * 16.0;
+                    }
                     Ln.work += GL;
-                    const int32_t di = int32_t(descs.size());
                     descs.push_back(D);
-                    for (int32_t w = 0; w < d.args.L1 / 8; ++w) maps.push_back(WgMap{di, w});
                 }
                 Ln.d1 = descs.size();
+                Ln.a0 = maps.size();
+                for (size_t di = Ln.d0; di < Ln.d1; ++di) {
+                    const FarDesc& D = descs[di];
+                    for (int32_t j = 0; j < D.nrhs; ++j)
+                        for (int32_t q = 0; q < D.nchunk; ++q)
+                            for (int32_t w = 0; w < D.A.L1 / 8; ++w) maps.push_back(WgMap{int32_t(di), w, j, q});
+                }
                 Ln.a1 = maps.size();
                 Ln.b0 = maps.size();
                 const int32_t rows = far_rows_per_wg(Ln.L1);
                 for (size_t di = Ln.d0; di < Ln.d1; ++di) {
-                    const int32_t nb = (descs[di].A.L2 + rows - 1) / rows;
-                    for (int32_t w = 0; w < nb; ++w) maps.push_back(WgMap{int32_t(di), w});
+                    const FarDesc& D = descs[di];
+                    const int32_t nb = (D.A.L2 + rows - 1) / rows;
+                    for (int32_t j = 0; j < D.nrhs; ++j)
+                        for (int32_t q = 0; q < D.nchunk; ++q)
+                            for (int32_t w = 0; w < nb; ++w) maps.push_back(WgMap{int32_t(di), w, j, q});
                 }
                 Ln.b1 = maps.size();
+                Ln.r0 = maps.size();
+                for (size_t di = Ln.d0; di < Ln.d1; ++di) {
+                    const FarDesc& D = descs[di];
+                    if (D.nchunk == 1) continue;
+                    const int32_t nb = int32_t((D.A.nrows + 255) / 256);
+                    for (int32_t j = 0; j < D.nrhs; ++j)
+                        for (int32_t w = 0; w < nb; ++w) maps.push_back(WgMap{int32_t(di), w, j, 0});
+                }
+                Ln.r1 = maps.size();
                 launches.push_back(Ln);
             }
             work_need = std::max(work_need, off);
-            launches.push_back(Launch{false, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}); // sub-wave boundary
+            launches.push_back(Launch{}); // sub-wave boundary
         }
     }
 
     // ---------- uploads (skipped when identical to the previous call) ----------
     if ((st = ensure(g_ex.work, work_need, s))) return st;
-    for (auto& D : descs) D.buf = static_cast<char*>(g_ex.work.p) + reinterpret_cast<size_t>(D.buf);
+    if ((st = ensure(g_ex.fpart, std::max<size_t>(part_need, 8), s))) return st;
+    for (auto& D : descs) {
+        D.buf = static_cast<char*>(g_ex.work.p) + reinterpret_cast<size_t>(D.buf);
+        if (D.nchunk > 1)
+            D.part = reinterpret_cast<double*>(static_cast<char*>(g_ex.fpart.p) + reinterpret_cast<size_t>(D.part));
+    }
     if ((st = ensure(g_ex.partial, size_t(std::max<int64_t>(pbase, 1)) * sizeof(double), s))) return st;
     std::vector<char> sig;
     auto add = [&](const void* p, size_t n) {
@@ -628,6 +691,11 @@ hank_status run_jobs(std::vector<Job>& jobs, hipStream_t s) {
             HIP_TRY(launch_far_pass(w, Ln.fp32, Ln.L1, Ln.L2, ddesc, dmap + m0, int64_t(m1 - m0), s));
             if ((st = prof_end(K_PASS_A + w, ev, bytes[w], Ln.work, s))) return st;
         }
+        if (Ln.r1 > Ln.r0) {
+            if ((st = prof_begin(ev, s))) return st;
+            HIP_TRY(launch_far_reduce(ddesc, dmap + Ln.r0, int64_t(Ln.r1 - Ln.r0), s));
+            if ((st = prof_end(K_FAR_REDUCE, ev, Ln.bytesR, 0.0, s))) return st;
+        }
     }
     HIP_TRY(hipEventRecord(g_ex.done, s));
     g_ex.last = s;
@@ -658,7 +726,7 @@ hank_status transform(int32_t task, const double* c, int64_t N, int64_t nrhs, in
     std::lock_guard<std::recursive_mutex> lk(g_mu);
     hipStream_t s = (hipStream_t)stream;
     DevPlan* dp = nullptr;
-    if ((st = get_plan(task, N, eps, o, s, dp))) return st;
+    if ((st = get_plan(task, N, eps, o, s, dp, nrhs))) return st;
     std::vector<Job> jobs{Job{dp, c, ldc, out, ldo, nrhs}};
     return run_jobs(jobs, s);
 }
@@ -703,6 +771,7 @@ struct hank_server {
     std::deque<int64_t> waiting;
     std::deque<Batch> inflight;
     int64_t inflight_bytes = 0;
+    int admitting = 0; // batches taken from the queue but not yet in flight
     int64_t batches = 0, batched = 0;
     bool started = false, stop = false;
     clock::time_point t0;
@@ -760,17 +829,20 @@ struct hank_server {
                     waiting.pop_front();
                 }
                 if (!b.tickets.empty()) {
+                    ++admitting;
                     lk.unlock();
                     hank_status st = hank_batch(reqs.data(), int64_t(reqs.size()), stream);
                     if (st == HANK_OK && hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) == hipSuccess &&
                         hipEventRecord(b.ev, stream) == hipSuccess) {
                         lk.lock();
+                        --admitting;
                         inflight_bytes += b.bytes;
                         inflight.push_back(b);
                         ++batches;
                         batched += int64_t(b.tickets.size());
                     } else {
                         lk.lock();
+                        --admitting;
                         error = st ? st : HANK_EDEVICE;
                         error_msg = hank_last_error();
                         for (int64_t tk : b.tickets) recs[size_t(tk)].state = 3;
@@ -822,7 +894,7 @@ hank_status hank_server_warm(hank_server* srv, const hank_request* r) {
     hank_options o{};
     o.precision = r->precision;
     DevPlan* dp = nullptr;
-    return get_plan(r->task, r->N, r->eps, &o, srv->stream, dp);
+    return get_plan(r->task, r->N, r->eps, &o, srv->stream, dp, r->nrhs);
 }
 
 hank_status hank_server_submit(hank_server* srv, const hank_request* r, double arrival_s, int64_t* ticket) {
@@ -835,7 +907,7 @@ hank_status hank_server_submit(hank_server* srv, const hank_request* r, double a
         hank_options o{};
         o.precision = r->precision;
         DevPlan* dp = nullptr;
-        if ((st = get_plan(r->task, r->N, r->eps, &o, srv->stream, dp))) return st;
+        if ((st = get_plan(r->task, r->N, r->eps, &o, srv->stream, dp, r->nrhs))) return st;
         bytes = request_bytes(*dp, r->nrhs);
     }
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -873,8 +945,8 @@ hank_status hank_server_drain(hank_server* srv) {
     std::unique_lock<std::mutex> lk(srv->mu);
     if (!srv->started) return fail(HANK_EINVAL, "server not started");
     srv->cv.wait(lk, [&] {
-        if (srv->next_arrival < srv->order.size() || !srv->waiting.empty() || !srv->inflight.empty()) return false;
-        return true;
+        return srv->next_arrival >= srv->order.size() && srv->waiting.empty() && srv->inflight.empty() &&
+               srv->admitting == 0;
     });
     if (srv->error) return fail(srv->error, srv->error_msg);
     return HANK_OK;
@@ -989,7 +1061,7 @@ hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t st
     for (int64_t i = 0; i < count; ++i) {
         hank_options o{};
         o.precision = reqs[i].precision;
-        Key k = plan_key(reqs[i].task, reqs[i].N, reqs[i].eps, &o, dev);
+        Key k = plan_key(reqs[i].task, reqs[i].N, reqs[i].eps, &o, dev, reqs[i].nrhs);
         if (!g_cache.count(k) && !fresh.count(k)) fresh[k] = {i, Plan()};
     }
     if (fresh.size() > 1) {
@@ -1003,7 +1075,8 @@ hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t st
                 hank_options o{};
                 o.precision = r.precision;
                 try {
-                    todo[t]->second.second = make_plan(r.task, r.N, r.eps, 0, r.precision, false, cost_model_for(&o));
+                    todo[t]->second.second = make_plan(r.task, r.N, r.eps, 0, r.precision, false, cost_model_for(&o),
+                                                       rhs_bucket(r.nrhs));
                 } catch (...) {
                     bad = true;
                 }
@@ -1021,9 +1094,9 @@ hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t st
         hank_options o{};
         o.precision = r.precision;
         DevPlan* dp = nullptr;
-        auto it = fresh.find(plan_key(r.task, r.N, r.eps, &o, dev));
+        auto it = fresh.find(plan_key(r.task, r.N, r.eps, &o, dev, r.nrhs));
         const Plan* pre = (fresh.size() > 1 && it != fresh.end()) ? &it->second.second : nullptr;
-        hank_status st = get_plan(r.task, r.N, r.eps, &o, s, dp, pre);
+        hank_status st = get_plan(r.task, r.N, r.eps, &o, s, dp, r.nrhs, pre);
         if (st) return st;
         jobs.push_back(Job{dp, r.c, r.ldc, r.out, r.ldo, r.nrhs});
     }
@@ -1088,7 +1161,7 @@ static hank_status host_plan(int32_t task, int64_t N, double eps, const hank_opt
     if (!valid_task(task)) return fail(HANK_EINVAL, "unknown task");
     try {
         p = make_plan(task, N, eps, o ? o->plan_mode : 0, o ? o->precision : 0, o && o->direct,
-                      cost_model_for(o));
+                      cost_model_for(o), rhs_bucket(o && o->nrhs > 1 ? o->nrhs : 1));
     } catch (const std::exception& ex) {
         return fail(HANK_EINVAL, ex.what());
     }

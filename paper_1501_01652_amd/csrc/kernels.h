@@ -73,7 +73,11 @@ struct FarArgs {
 };
 
 // A block applied to nrhs right-hand sides: the work buffer holds
-// (j * (g1-g0) + (g - g0)) * L elements for rhs j and group g.
+// (j * (g1-g0) + (g - g0)) * L elements for rhs j and group g.  The groups
+// are cut into nchunk chunks of gchunk groups, one workgroup set per
+// (rhs, chunk).  With nchunk > 1 pass C leaves chunk sums in
+// part[(j * nchunk + chunk) * nrows + k'] and k_far_reduce adds them to f in
+// chunk order; with nchunk == 1 pass C adds into f itself.
 struct FarDesc {
     FarArgs A;
     const double* c;
@@ -82,13 +86,15 @@ struct FarDesc {
     double* f;
     void* buf;
     const void* H;
+    double* part;
     int64_t ldc, ldo;
-    int32_t nrhs, pad;
+    int32_t nrhs, nchunk, gchunk, pad;
 };
 
-// workgroup -> (descriptor, workgroup index within its block)
+// workgroup -> descriptor, workgroup index within its (rhs, chunk) set,
+// right-hand side and group chunk (for k_far_reduce: row block and rhs)
 struct WgMap {
-    int32_t desc, wg;
+    int32_t desc, wg, j, chunk;
 };
 
 hipError_t upload_tables(const DeviceTables& t);
@@ -109,5 +115,7 @@ hipError_t launch_chirp_spectrum(const FarArgs& A, bool fp32, void* work, void* 
 int32_t far_rows_per_wg(int32_t L1);
 hipError_t launch_far_pass(int which, bool fp32, int32_t L1, int32_t L2, const FarDesc* descs,
                            const WgMap* map, int64_t nwg, hipStream_t s);
+// f += sum over chunks of part, 256 rows per workgroup
+hipError_t launch_far_reduce(const FarDesc* descs, const WgMap* map, int64_t nwg, hipStream_t s);
 
 } // namespace hank

@@ -425,15 +425,17 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict
             nidx[r] = int32_t(n - 1);
         }
     }
-    for (int j = 0; j < D.nrhs; ++j) {
+    {
+        const int j = mp.j;
+        const int gs = A.g0 + mp.chunk * D.gchunk, ge = min(A.g1, gs + D.gchunk);
         const double* cj = D.c + (int64_t)j * D.ldc;
         double cv[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) cv[r] = nidx[r] >= 0 ? cj[nidx[r]] : 0.0;
         int ecur = 0, acur = 0;
-        for (int g = A.g0; g < A.g1; ++g) {
+        for (int g = gs; g < ge; ++g) {
             const GroupDev Gd = A.groups[g];
-            if (Gd.a != acur || g == A.g0) { // restart the powers
+            if (Gd.a != acur || g == gs) { // restart the powers
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     pw[r] = ipow_d<double>(vw[r], Gd.e) * (Gd.a ? ipow_d<double>(la[r], Gd.a) : 1.0);
@@ -566,8 +568,10 @@ __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(const FarDesc* __restr
         tw[r] = mk(w.x, -w.y);
     }
 #endif
-    const int64_t nt = (int64_t)D.nrhs * (A.g1 - A.g0);
-    for (int64_t q = 0; q < nt; ++q) {
+    const int ng = A.g1 - A.g0;
+    const int gs = mp.chunk * D.gchunk, ge = min(ng, gs + D.gchunk);
+    for (int gq = gs; gq < ge; ++gq) {
+        const int64_t q = (int64_t)mp.j * ng + gq;
         cx<F>* p = buf + q * A.L + rowc * L1;
         cx<F> v[R];
 #pragma unroll
@@ -628,13 +632,15 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict
                            1.0 / sqrt(rho[r]));
         }
     }
-    for (int j = 0; j < D.nrhs; ++j) {
+    {
+        const int j = mp.j;
+        const int gs = A.g0 + mp.chunk * D.gchunk, ge = min(A.g1, gs + D.gchunk);
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
         int ecur = 0, acur = 0;
-        for (int g = A.g0; g < A.g1; ++g) {
+        for (int g = gs; g < ge; ++g) {
             const GroupDev Gd = A.groups[g];
-            if (Gd.a != acur || g == A.g0) {
+            if (Gd.a != acur || g == gs) {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     pw[r] = ipow_d<double>(rho[r], Gd.e) * (Gd.a ? ipow_d<double>(ek[r], Gd.a) : 1.0);
@@ -663,13 +669,35 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict
                 }
             }
         }
-        double* fj = D.f + (int64_t)j * D.ldo;
+        if (D.nchunk == 1) {
+            double* fj = D.f + (int64_t)j * D.ldo;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t kp = j1 + (int64_t)A.L1 * (tt + r * NTC);
-            if (kp < A.nrows) fj[A.ka + kp - 1] += acc[r];
+            for (int r = 0; r < R; ++r) {
+                const int64_t kp = j1 + (int64_t)A.L1 * (tt + r * NTC);
+                if (kp < A.nrows) fj[A.ka + kp - 1] += acc[r];
+            }
+        } else {
+            double* pj = D.part + ((int64_t)j * D.nchunk + mp.chunk) * A.nrows;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t kp = j1 + (int64_t)A.L1 * (tt + r * NTC);
+                if (kp < A.nrows) pj[kp] = acc[r];
+            }
         }
     }
+}
+
+// f += sum of the pass-C chunk sums, in chunk order (deterministic)
+__global__ __launch_bounds__(256) void k_far_reduce(const FarDesc* __restrict__ descs,
+                                                    const WgMap* __restrict__ wmap) {
+    const WgMap mp = wmap[blockIdx.x];
+    const FarDesc& D = descs[mp.desc];
+    const int64_t kp = (int64_t)mp.wg * 256 + threadIdx.x;
+    if (kp >= D.A.nrows) return;
+    const double* pj = D.part + (int64_t)mp.j * D.nchunk * D.A.nrows + kp;
+    double s = 0.0;
+    for (int q = 0; q < D.nchunk; ++q) s += pj[(int64_t)q * D.A.nrows];
+    D.f[(int64_t)mp.j * D.ldo + D.A.ka + kp - 1] += s;
 }
 
 // ---------------------------------------------------------------------------
@@ -787,6 +815,11 @@ static hipError_t pass_b(bool fwd_only, int32_t L1, const FarArgs* A, const FarD
 }
 
 int32_t far_rows_per_wg(int32_t L1) { return L1 >= 2048 ? 1 : 2048 / L1; }
+
+hipError_t launch_far_reduce(const FarDesc* descs, const WgMap* map, int64_t nwg, hipStream_t s) {
+    if (nwg > 0) hipLaunchKernelGGL(k_far_reduce, dim3((unsigned)nwg), dim3(256), 0, s, descs, map);
+    return hipGetLastError();
+}
 
 hipError_t launch_chirp_spectrum(const FarArgs& A, bool fp32, void* work, void* H, hipStream_t s) {
     hipError_t e = fp32 ? pass_ac<float>(1, A.L2, &A, nullptr, nullptr, 0, work, s)

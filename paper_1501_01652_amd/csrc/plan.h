@@ -78,6 +78,7 @@ struct Plan {
     int M = 0, K = 0, T = 0, P = 0;
     double s = 0, alpha = 0, beta = 0;
     int first_direct = 0;
+    int64_t nrhs = 1; // right-hand sides the partition was balanced for
     std::vector<Block> blocks;
     std::vector<NearSeg> near;
     int64_t near_entries = 0;
@@ -87,9 +88,11 @@ struct Plan {
 // Cost-model constants (seconds); refined from measurements through the
 // environment (HANK_COST_FFT, HANK_COST_NEAR, HANK_COST_BLOCK).
 struct CostModel {
-    double fft_pt_group64 = 3.0e-11; // per FFT point per group, FP64 bulk (measured)
+    double fft_pt_group64 = 3.0e-11; // per FFT point per group per right-hand side, FP64 bulk (measured)
     double fft_pt_group32 = 1.7e-11; // same, FP32 bulk
-    double near_entry = 4.6e-12;     // per directly summed entry (measured)
+    double near_entry = 4.6e-12;     // per directly summed entry, one right-hand side (measured)
+    double near_multi_entry = 7.0e-12; // per entry with several right-hand sides (J_0 once, staged in LDS)
+    double near_rhs = 2.7e-13;       // per entry and right-hand side of the product (FP64 MFMA / FMA)
     double block = 20e-6;            // fixed cost per block (three launches)
 };
 
@@ -110,8 +113,9 @@ double bmax(int64_t n);
 double emax(int64_t k, int64_t N);
 
 // Build a plan.  Throws std::invalid_argument on bad input.
+// nrhs: the number of right-hand sides the tuned partition is balanced for.
 Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool direct,
-               const CostModel& cm);
+               const CostModel& cm, int64_t nrhs = 1);
 
 // Fill terms/groups of a block; returns false if the truncation would exceed
 // the supported term count.

@@ -148,6 +148,8 @@ CostModel cost_model_from_env() {
     if (const char* v = std::getenv("HANK_COST_FFT32")) cm.fft_pt_group32 = std::atof(v);
     if (const char* v = std::getenv("HANK_COST_NEAR")) cm.near_entry = std::atof(v);
     if (const char* v = std::getenv("HANK_COST_BLOCK")) cm.block = std::atof(v);
+    if (const char* v = std::getenv("HANK_COST_NEAR_MULTI")) cm.near_multi_entry = std::atof(v);
+    if (const char* v = std::getenv("HANK_COST_NEAR_RHS")) cm.near_rhs = std::atof(v);
     return cm;
 }
 
@@ -443,13 +445,15 @@ static bool near_segments(const Grid& g, const std::vector<Block>& blocks, std::
 }
 
 static double plan_cost(const Plan& p, const CostModel& cm) {
-    double c = double(p.near_entries) * cm.near_entry;
+    const double r = double(p.nrhs);
+    double c = double(p.near_entries) * (p.nrhs == 1 ? cm.near_entry : cm.near_multi_entry + r * cm.near_rhs);
     double per = p.fp32 ? cm.fft_pt_group32 : cm.fft_pt_group64;
-    for (auto& b : p.blocks) c += cm.block + double(b.groups.size()) * double(b.L) * per;
+    for (auto& b : p.blocks) c += cm.block + double(b.groups.size()) * double(b.L) * per * r;
     return c;
 }
 
-Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool direct, const CostModel& cm) {
+Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool direct, const CostModel& cm,
+               int64_t nrhs) {
     if (!(eps >= 1e-15 && eps < 1.0) || !std::isfinite(eps)) throw std::invalid_argument("eps out of range");
     int64_t Nmin = (task == T_SCHL || task == T_FB) ? 2 : 1;
     if (N < Nmin || N > (int64_t(1) << 24)) throw std::invalid_argument("N out of range");
@@ -459,6 +463,7 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
     p.mode = mode;
     p.direct = direct;
     p.fp32 = (precision == 2) || (precision == 0 && eps >= 1e-6);
+    p.nrhs = std::max<int64_t>(1, nrhs);
 
     // paper parameters (reported in both modes)
     p.M = paper_M(eps);
@@ -528,8 +533,9 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
         memo[key] = {ok, b};
         return ok;
     };
-    Plan best;
-    bool have = false;
+    // the plain direct sum is a candidate too
+    Plan best = p;
+    finish(best);
     const double betas[] = {0.06, 0.1, 0.15, 0.22, 0.3, 0.4, 0.55};
     for (int Mc = 2; Mc <= 14; ++Mc) {
         double s = param_s(0, Mc, eps / 8.0);
@@ -550,16 +556,9 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
                         break;
                     }
                 if (!valid || !finish(q)) continue;
-                if (!have || q.cost < best.cost) {
-                    best = q;
-                    have = true;
-                }
+                if (q.cost < best.cost) best = q;
                 if (P > 0 && q.blocks.size() <= size_t(1 + 2 * (P - 1))) break; // no new strip
             }
-    }
-    if (!have) { // nothing valid: plain direct summation
-        finish(p);
-        return p;
     }
     // keep the paper's reported M, K, T alongside the tuned partition
     best.M = p.M;

@@ -135,19 +135,24 @@ def test_deterministic_and_linear():
 
 @pytest.mark.parametrize("nrhs", [2, 5, 16, 23, 64])
 @pytest.mark.parametrize("task", ["fourier_bessel", "dht0"])
-def test_multiple_right_hand_sides(task, nrhs):
+@pytest.mark.parametrize("mode", ["tuned", "far"])
+def test_multiple_right_hand_sides(task, nrhs, mode):
     """nrhs columns in one call (near field: J_0 once per entry, FMA below 16
-    columns, FP64 MFMA from 16): every column against the oracle, and against
-    the single-column call to rounding."""
+    columns, FP64 MFMA from 16; far field: one workgroup set per column and
+    group chunk): sampled columns against the oracle, and each column is
+    bitwise independent of the other columns of the call."""
     N, eps = 1500, 1e-8
+    kw = {"tuned": {}, "far": {"prefer_far": 1}}[mode]
     rng = np.random.default_rng(12 + nrhs)
     C = rng.standard_normal((nrhs, N))
-    F = host(hank.transform(task, dev(C), eps, prefer_far=1))
+    F = host(hank.transform(task, dev(C), eps, **kw))
+    C2 = rng.standard_normal((nrhs, N))
     for j in (0, nrhs // 2, nrhs - 1):
         ref = oracle.eval_rows(task, C[j])
         assert np.max(np.abs(F[j] - ref)) <= C_TOL * eps * np.sum(np.abs(C[j]))
-        fj = host(hank.transform(task, dev(C[j]), eps, prefer_far=1))
-        assert np.max(np.abs(F[j] - fj)) <= 1e-14 * np.sum(np.abs(C[j]))
+        C2j = C2.copy()
+        C2j[j] = C[j]
+        assert np.array_equal(host(hank.transform(task, dev(C2j), eps, **kw))[j], F[j])
 
 
 def test_named_entry_points_match_generic():
