@@ -46,7 +46,24 @@ hank_status fail(hank_status s, const std::string& msg) {
                         std::string(#call) + ": " + hipGetErrorString(e_));                        \
     } while (0)
 
-constexpr int64_t NEAR_CHUNK = 2048; // columns per near-field work item
+// Columns per near-field work item: the widest of 2048, 1024, 512, 256 that
+// still gives at least 2048 tiles (two rounds of the chip at four
+// workgroups per compute unit), so that small problems fill the chip and
+// large ones keep the per-row reduction short.  HANK_NEAR_COLS fixes it.
+int64_t near_chunk(const std::vector<NearSeg>& segs) {
+    static const int64_t fixed = [] {
+        const char* e = std::getenv("HANK_NEAR_COLS");
+        return e ? std::max<int64_t>(64, std::min<int64_t>(NEAR_TILE_COLS, std::atoll(e))) : int64_t(0);
+    }();
+    if (fixed) return fixed;
+    int64_t chunk = NEAR_TILE_COLS;
+    for (; chunk > 256; chunk /= 2) {
+        int64_t tiles = 0;
+        for (auto& seg : segs) tiles += ((seg.k1 - seg.k0 + 63) / 64) * ((seg.ncut - 1 + chunk - 1) / chunk);
+        if (tiles >= 2048) break;
+    }
+    return chunk;
+}
 
 struct DevBlock {
     Block hb;
@@ -61,8 +78,10 @@ struct DevPlan {
     int device = 0;
     double* b = nullptr; // root offsets b_1..b_{N+1}
     double* e = nullptr; // DHT row perturbations e_1..e_N
-    std::vector<NearTile> tiles; // geometry and flags; prob/pbase filled per call
-    std::vector<RowTile> rts;    // geometry; f/pbase/nrhs filled per call
+    std::vector<NearTile> tiles; // host copies of the near-field tiles and row tiles
+    std::vector<RowTile> rts;
+    NearTile* d_tiles = nullptr; // the same on the device
+    RowTile* d_rts = nullptr;
     std::vector<DevBlock> blocks;
     void* work = nullptr; // chirp-spectrum scratch during the build
     size_t bytes = 0;
@@ -78,6 +97,8 @@ struct DevPlan {
         fr(b);
         fr(e);
         fr(work);
+        fr(d_tiles);
+        fr(d_rts);
         for (auto& d : blocks) {
             fr(d.H);
             fr(d.groups);
@@ -144,6 +165,7 @@ GridArgs grid_args(const Grid& g) {
     a.piD_hi = double(pd);
     a.piD_lo = double(pd - (long double)a.piD_hi);
     a.invD = double(1.0L / (long double)g.D);
+    a.invQc = double(1.0L / (long double)g.Qc);
     a.row_pert = g.row_pert;
     a.col_pert = g.col_pert;
     return a;
@@ -191,27 +213,43 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
         if ((st = dev_alloc(dp.e, size_t(N), dp.bytes))) return st;
         HIP_TRY(launch_dht_e(N, dp.b, dp.e, s));
     }
-    // near-field work items (host copies; device descriptors are built per call)
+    // near-field work items: partial slots in row order, so that a row
+    // tile's slots are consecutive; the tiles themselves run longest first,
+    // so that the short ones fill the tail of a launch
     std::vector<NearTile>& tiles = dp.tiles;
     std::vector<RowTile>& rts = dp.rts;
+    const int64_t chunk = near_chunk(p.near);
     for (auto& seg : p.near)
         for (int64_t k = seg.k0; k < seg.k1; k += 64) {
             RowTile r{};
             r.k0 = k;
             r.nk = int32_t(std::min<int64_t>(64, seg.k1 - k));
-            r.tile0 = int64_t(tiles.size());
-            for (int64_t n = 1; n < seg.ncut; n += NEAR_CHUNK) {
+            r.slot0 = int64_t(tiles.size());
+            for (int64_t n = 1; n < seg.ncut; n += chunk) {
                 NearTile t{};
                 t.k0 = k;
                 t.nk = r.nk;
                 t.n0 = n;
-                t.n1 = std::min(seg.ncut, n + NEAR_CHUNK);
+                t.n1 = std::min(seg.ncut, n + chunk);
                 t.flags = near_flags(g, t);
+                t.slot = int64_t(tiles.size());
                 tiles.push_back(t);
             }
-            r.ntiles = int64_t(tiles.size()) - r.tile0;
+            r.ntiles = int64_t(tiles.size()) - r.slot0;
             rts.push_back(r);
         }
+    auto tile_cost = [](const NearTile& T) {
+        static const double w[8] = {3.0, 3.0, 1.0, 1.05, 1.1, 1.15, 1.25, 1.45};
+        return double(T.n1 - T.n0) * w[near_variant(T.flags)];
+    };
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [&](const NearTile& a, const NearTile& b) { return tile_cost(a) > tile_cost(b); });
+    if ((st = dev_alloc(dp.d_tiles, tiles.size(), dp.bytes))) return st;
+    if ((st = dev_alloc(dp.d_rts, rts.size(), dp.bytes))) return st;
+    if (!tiles.empty())
+        HIP_TRY(hipMemcpyAsync(dp.d_tiles, tiles.data(), tiles.size() * sizeof(NearTile), hipMemcpyHostToDevice, s));
+    if (!rts.empty())
+        HIP_TRY(hipMemcpyAsync(dp.d_rts, rts.data(), rts.size() * sizeof(RowTile), hipMemcpyHostToDevice, s));
 
     // far-field blocks (the scratch only holds one chirp kernel at a time)
     const size_t esz = p.fp32 ? 8 : 16;
@@ -389,7 +427,7 @@ struct Scratch {
     size_t bytes = 0;
 };
 struct Executor {
-    Scratch probs, tiles1, tilesm, rts, partial, descs, maps, work, fpart;
+    Scratch probs, partial, descs, work, fpart;
     hipEvent_t done = nullptr;
     hipStream_t last = nullptr;
     bool used = false;
@@ -448,58 +486,63 @@ int32_t far_chunks(int64_t L, int32_t ngroups, int64_t nrhs) {
     return int32_t(std::max<int64_t>(1, want));
 }
 
-hank_status run_jobs(std::vector<Job>& jobs, hipStream_t s) {
+hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
     hank_status st;
+    // the near-field kernels take at most 64 right-hand sides: split wider jobs
+    std::vector<Job> jobs;
+    for (const Job& J : jobs_in)
+        for (int64_t j0 = 0; j0 < J.nrhs; j0 += 64) {
+            Job P = J;
+            P.c = J.c + j0 * J.ldc;
+            P.f = J.f + j0 * J.ldo;
+            P.nrhs = std::min<int64_t>(64, J.nrhs - j0);
+            jobs.push_back(P);
+        }
     if (!g_ex.done) HIP_TRY(hipEventCreateWithFlags(&g_ex.done, hipEventDisableTiming));
     if (g_ex.used && g_ex.last != s) HIP_TRY(hipStreamWaitEvent(s, g_ex.done, 0));
 
-    // ---------- near field descriptors ----------
+    // ---------- near field descriptors: single right-hand side jobs first ----------
+    std::stable_partition(jobs.begin(), jobs.end(), [](const Job& J) { return J.nrhs == 1; });
     std::vector<NearProb> probs;
-    std::vector<NearTile> t1, tm;
-    std::vector<RowTile> rts;
-    int64_t pbase = 0;
+    int32_t nsingle = 0;
+    int64_t pbase = 0, ntiles1 = 0, ntilesm = 0, nrts = 0;
+    double near_entries = 0, multi_entries = 0;
     for (size_t i = 0; i < jobs.size(); ++i) {
-        Job& J = jobs[i];
+        const Job& J = jobs[i];
         NearProb P{};
         P.G = J.dp->G;
         P.c = J.c;
         P.b = J.dp->b;
         P.e = J.dp->e;
+        P.f = J.f;
+        P.tiles = J.dp->d_tiles;
+        P.rts = J.dp->d_rts;
         P.ldc = J.ldc;
+        P.ldo = J.ldo;
         P.nrhs = int32_t(J.nrhs);
+        P.pbase = pbase;
+        const int64_t nt = int64_t(J.dp->tiles.size());
+        int64_t& count = J.nrhs == 1 ? ntiles1 : ntilesm;
+        P.tile_start = count;
+        count += nt;
+        P.rt_start = nrts;
+        nrts += int64_t(J.dp->rts.size());
+        pbase += nt * J.nrhs * 64;
+        nsingle += J.nrhs == 1;
+        (J.nrhs == 1 ? near_entries : multi_entries) += double(J.dp->plan.near_entries) * double(J.nrhs);
         probs.push_back(P);
-        for (const RowTile& r0 : J.dp->rts) {
-            RowTile r = r0;
-            r.f = J.f;
-            r.ldo = J.ldo;
-            r.nrhs = int32_t(J.nrhs);
-            r.pbase = pbase;
-            for (int64_t t = 0; t < r0.ntiles; ++t) {
-                NearTile T = J.dp->tiles[size_t(r0.tile0 + t)];
-                T.prob = int32_t(i);
-                T.pbase = pbase;
-                pbase += J.nrhs * 64;
-                (J.nrhs == 1 ? t1 : tm).push_back(T);
-            }
-            rts.push_back(r);
-        }
     }
-    // multi right-hand-side tiles: MFMA ones first
-    std::stable_partition(tm.begin(), tm.end(), [&](const NearTile& T) { return probs[size_t(T.prob)].nrhs >= 16; });
-    int64_t nmfma = 0;
-    for (auto& T : tm) nmfma += probs[size_t(T.prob)].nrhs >= 16;
 
     // ---------- far field descriptors, by wave ----------
     struct Launch {
         bool fp32;
         int32_t L1, L2;
-        size_t d0, d1;                 // descriptors [d0, d1)
-        size_t a0, a1, b0, b1, r0, r1; // workgroup maps of the column passes, pass B and the chunk reduction
+        size_t d0, d1;          // descriptors [d0, d1)
+        int64_t nac, nb, nr;    // grid sizes of the column passes, pass B and the chunk reduction
         double bytesA, bytesB, bytesC, bytesR, work;
     };
     size_t part_need = 0;
     std::vector<FarDesc> descs;
-    std::vector<WgMap> maps;
     std::vector<Launch> launches;
     size_t maxblocks = 0;
     for (auto& J : jobs) maxblocks = std::max(maxblocks, J.dp->blocks.size());
@@ -554,7 +597,6 @@ hank_status run_jobs(std::vector<Job>& jobs, hipStream_t s) {
                 Ln.L2 = std::get<2>(kv.first);
                 const double esz = Ln.fp32 ? 8.0 : 16.0;
                 Ln.d0 = descs.size();
-                Ln.a0 = maps.size();
                 for (auto& it : kv.second) {
                     const Job& J = jobs[it.job];
                     const DevBlock& d = J.dp->blocks[bi];
@@ -594,33 +636,17 @@ hank_status run_jobs(std::vector<Job>& jobs, hipStream_t s) {
                     descs.push_back(D);
                 }
                 Ln.d1 = descs.size();
-                Ln.a0 = maps.size();
-                for (size_t di = Ln.d0; di < Ln.d1; ++di) {
-                    const FarDesc& D = descs[di];
-                    for (int32_t j = 0; j < D.nrhs; ++j)
-                        for (int32_t q = 0; q < D.nchunk; ++q)
-                            for (int32_t w = 0; w < D.A.L1 / 8; ++w) maps.push_back(WgMap{int32_t(di), w, j, q});
-                }
-                Ln.a1 = maps.size();
-                Ln.b0 = maps.size();
                 const int32_t rows = far_rows_per_wg(Ln.L1);
                 for (size_t di = Ln.d0; di < Ln.d1; ++di) {
-                    const FarDesc& D = descs[di];
-                    const int32_t nb = (D.A.L2 + rows - 1) / rows;
-                    for (int32_t j = 0; j < D.nrhs; ++j)
-                        for (int32_t q = 0; q < D.nchunk; ++q)
-                            for (int32_t w = 0; w < nb; ++w) maps.push_back(WgMap{int32_t(di), w, j, q});
+                    FarDesc& D = descs[di];
+                    const int64_t items = int64_t(D.nrhs) * D.nchunk;
+                    D.wg_ac = Ln.nac;
+                    Ln.nac += items * (D.A.L1 / 8);
+                    D.wg_b = Ln.nb;
+                    Ln.nb += items * ((D.A.L2 + rows - 1) / rows);
+                    D.wg_r = Ln.nr;
+                    if (D.nchunk > 1) Ln.nr += int64_t(D.nrhs) * ((D.A.nrows + 255) / 256);
                 }
-                Ln.b1 = maps.size();
-                Ln.r0 = maps.size();
-                for (size_t di = Ln.d0; di < Ln.d1; ++di) {
-                    const FarDesc& D = descs[di];
-                    if (D.nchunk == 1) continue;
-                    const int32_t nb = int32_t((D.A.nrows + 255) / 256);
-                    for (int32_t j = 0; j < D.nrhs; ++j)
-                        for (int32_t w = 0; w < nb; ++w) maps.push_back(WgMap{int32_t(di), w, j, 0});
-                }
-                Ln.r1 = maps.size();
                 launches.push_back(Ln);
             }
             work_need = std::max(work_need, off);
@@ -643,18 +669,10 @@ hank_status run_jobs(std::vector<Job>& jobs, hipStream_t s) {
         sig.insert(sig.end(), q, q + n);
     };
     add(probs.data(), probs.size() * sizeof(NearProb));
-    add(t1.data(), t1.size() * sizeof(NearTile));
-    add(tm.data(), tm.size() * sizeof(NearTile));
-    add(rts.data(), rts.size() * sizeof(RowTile));
     add(descs.data(), descs.size() * sizeof(FarDesc));
-    add(maps.data(), maps.size() * sizeof(WgMap));
     if (sig != g_ex.sig) {
         if ((st = upload(g_ex.probs, probs, s))) return st;
-        if ((st = upload(g_ex.tiles1, t1, s))) return st;
-        if ((st = upload(g_ex.tilesm, tm, s))) return st;
-        if ((st = upload(g_ex.rts, rts, s))) return st;
         if ((st = upload(g_ex.descs, descs, s))) return st;
-        if ((st = upload(g_ex.maps, maps, s))) return st;
         g_ex.sig.swap(sig);
     }
     const NearProb* dprobs = static_cast<const NearProb*>(g_ex.probs.p);
@@ -662,38 +680,34 @@ hank_status run_jobs(std::vector<Job>& jobs, hipStream_t s) {
 
     // ---------- launches ----------
     hipEvent_t ev;
-    double near_entries = 0, multi_entries = 0;
-    for (auto& J : jobs) (J.nrhs == 1 ? near_entries : multi_entries) += double(J.dp->plan.near_entries) * double(J.nrhs);
-    if (!t1.empty()) {
+    if (ntiles1 > 0) {
         if ((st = prof_begin(ev, s))) return st;
-        HIP_TRY(launch_near(dprobs, static_cast<const NearTile*>(g_ex.tiles1.p), int64_t(t1.size()), dpart, s));
-        if ((st = prof_end(K_NEAR, ev, 8.0 * 64.0 * double(t1.size()), near_entries, s))) return st;
+        HIP_TRY(launch_near(dprobs, nsingle, ntiles1, dpart, s));
+        if ((st = prof_end(K_NEAR, ev, 8.0 * 64.0 * double(ntiles1), near_entries, s))) return st;
     }
-    if (!tm.empty()) {
+    if (ntilesm > 0) {
         if ((st = prof_begin(ev, s))) return st;
-        const NearTile* dtm = static_cast<const NearTile*>(g_ex.tilesm.p);
-        HIP_TRY(launch_near_multi(dprobs, dtm, nmfma, true, dpart, s));
-        HIP_TRY(launch_near_multi(dprobs, dtm + nmfma, int64_t(tm.size()) - nmfma, false, dpart, s));
+        HIP_TRY(launch_near_multi(dprobs + nsingle, int32_t(probs.size()) - nsingle, ntilesm, dpart, s));
         if ((st = prof_end(K_NEAR_MULTI, ev, 0.0, multi_entries, s))) return st;
     }
     if ((st = prof_begin(ev, s))) return st;
-    HIP_TRY(launch_near_reduce(static_cast<const RowTile*>(g_ex.rts.p), int64_t(rts.size()), dpart, s));
+    HIP_TRY(launch_near_reduce(dprobs, int32_t(probs.size()), nrts, dpart, s));
     if ((st = prof_end(K_NEAR_REDUCE, ev, 8.0 * double(pbase), 0.0, s))) return st;
 
     const FarDesc* ddesc = static_cast<const FarDesc*>(g_ex.descs.p);
-    const WgMap* dmap = static_cast<const WgMap*>(g_ex.maps.p);
     for (auto& Ln : launches) {
         if (Ln.L1 == 0) continue; // sub-wave boundary: the stream orders the waves
         const double bytes[3] = {Ln.bytesA, Ln.bytesB, Ln.bytesC};
+        const int64_t grid[3] = {Ln.nac, Ln.nb, Ln.nac};
+        const int32_t nd = int32_t(Ln.d1 - Ln.d0);
         for (int w = 0; w < 3; ++w) {
             if ((st = prof_begin(ev, s))) return st;
-            const size_t m0 = (w == 1) ? Ln.b0 : Ln.a0, m1 = (w == 1) ? Ln.b1 : Ln.a1;
-            HIP_TRY(launch_far_pass(w, Ln.fp32, Ln.L1, Ln.L2, ddesc, dmap + m0, int64_t(m1 - m0), s));
+            HIP_TRY(launch_far_pass(w, Ln.fp32, Ln.L1, Ln.L2, ddesc + Ln.d0, nd, grid[w], s));
             if ((st = prof_end(K_PASS_A + w, ev, bytes[w], Ln.work, s))) return st;
         }
-        if (Ln.r1 > Ln.r0) {
+        if (Ln.nr > 0) {
             if ((st = prof_begin(ev, s))) return st;
-            HIP_TRY(launch_far_reduce(ddesc, dmap + Ln.r0, int64_t(Ln.r1 - Ln.r0), s));
+            HIP_TRY(launch_far_reduce(ddesc + Ln.d0, nd, Ln.nr, s));
             if ((st = prof_end(K_FAR_REDUCE, ev, Ln.bytesR, 0.0, s))) return st;
         }
     }

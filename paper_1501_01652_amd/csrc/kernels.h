@@ -2,8 +2,11 @@
 //
 // Work is described by small device-resident descriptors so that one launch
 // can cover the same kind of work for many transforms (several right-hand
-// sides, several requests of a batch): near-field tiles name their problem,
-// far-field workgroups find their block through a workgroup map.
+// sides, several requests of a batch).  A launch gets one descriptor per
+// transform (or per far-field block of a transform) with the offset of its
+// first workgroup in the grid; a workgroup finds its descriptor by binary
+// search over those offsets, so the host work per call does not grow with
+// the number of workgroups.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,38 +20,61 @@ namespace hank {
 // w^_n = pi N_n / Qc.  pi/D is carried as hi + lo.
 struct GridArgs {
     int64_t ar, br, ac, bc, D, Dr, Qc;
-    double pi_Qc, piD_hi, piD_lo, invD;
+    double pi_Qc, piD_hi, piD_lo, invD, invQc;
     int32_t row_pert, col_pert;
 };
 
-// One transform's near field: grid, coefficient columns c + j*ldc (j < nrhs),
-// root offsets b and DHT row perturbations e.
+// columns of one near-field tile (its coefficients are staged in LDS)
+constexpr int NEAR_TILE_COLS = 2048;
+
+// near-field work item of a plan: rows [k0, k0+nk) x columns [n0, n1).  Its
+// partial sums (nrhs x 64) sit in slot `slot` of the transform's partial
+// area.  flags: bit 0 some entry has z < 20, bit 1 some entry has z >= 20,
+// bits 8.. Hankel pairs needed for the smallest z >= 20 of the tile
+// (remainder below 1e-17)
+struct NearTile {
+    int64_t k0, n0, n1, slot;
+    int32_t nk, flags;
+};
+
+// rows [k0, k0+nk) of a plan own the partial slots [slot0, slot0+ntiles)
+struct RowTile {
+    int64_t k0, slot0, ntiles;
+    int32_t nk, pad;
+};
+
+// One transform's near field in a launch: grid, coefficient columns
+// c + j*ldc and outputs f + j*ldo (j < nrhs), root offsets b, DHT row
+// perturbations e, the plan's tiles and row tiles (device), the grid offsets
+// of its first tile (tile_start, within the launch) and first row tile
+// (rt_start), and the start of its partial area (pbase; slot s of it at
+// pbase + s*nrhs*64).
 struct NearProb {
     GridArgs G;
     const double* c;
     const double* b;
     const double* e;
-    int64_t ldc;
+    double* f;
+    const NearTile* tiles;
+    const RowTile* rts;
+    int64_t ldc, ldo, tile_start, rt_start, pbase;
     int32_t nrhs, pad;
 };
 
-// near-field work item: rows [k0, k0+nk) x columns [n0, n1) of problem prob;
-// its nrhs x 64 partial sums start at partial + pbase.  flags: bit 0 some
-// entry has z < 20, bit 1 some entry has z >= 20, bits 8.. Hankel pairs needed
-// for the smallest z >= 20 of the tile (remainder below 1e-17)
-struct NearTile {
-    int64_t k0, n0, n1, pbase;
-    int32_t nk, flags, prob, pad;
-};
-
-// rows [k0, k0+nk) own the partials of tiles [tile0, tile0+ntiles), which
-// start at partial + pbase (nrhs x 64 per tile); column j goes to f + j*ldo
-struct RowTile {
-    int64_t k0, tile0, ntiles, pbase;
-    double* f;
-    int64_t ldo;
-    int32_t nk, nrhs;
-};
+// Near-field kernel variant of a tile from its flags: 0 only z < 20,
+// 1 both branches (12 Hankel pairs), 2..7 only z >= 20 with M = 3, 4, 5, 6, 8, 12.
+__host__ __device__ inline int near_variant(int32_t flags) {
+    if (!(flags & 2)) return 0;
+    if (flags & 1) return 1;
+    switch (flags >> 8) {
+    case 3: return 2;
+    case 4: return 3;
+    case 5: return 4;
+    case 6: return 5;
+    case 8: return 6;
+    default: return 7;
+    }
+}
 
 struct GroupDev {
     int32_t a, e, t0, t1;
@@ -75,9 +101,12 @@ struct FarArgs {
 // A block applied to nrhs right-hand sides: the work buffer holds
 // (j * (g1-g0) + (g - g0)) * L elements for rhs j and group g.  The groups
 // are cut into nchunk chunks of gchunk groups, one workgroup set per
-// (rhs, chunk).  With nchunk > 1 pass C leaves chunk sums in
+// (rhs, chunk) item.  With nchunk > 1 pass C leaves chunk sums in
 // part[(j * nchunk + chunk) * nrows + k'] and k_far_reduce adds them to f in
-// chunk order; with nchunk == 1 pass C adds into f itself.
+// chunk order; with nchunk == 1 pass C adds into f itself.  wg_ac, wg_b,
+// wg_r: grid offsets of the descriptor's first workgroup in the column
+// passes (L1/8 per item), pass B (ceil(L2/rows) per item) and the chunk
+// reduction (ceil(nrows/256) per rhs).
 struct FarDesc {
     FarArgs A;
     const double* c;
@@ -88,34 +117,31 @@ struct FarDesc {
     const void* H;
     double* part;
     int64_t ldc, ldo;
+    int64_t wg_ac, wg_b, wg_r;
     int32_t nrhs, nchunk, gchunk, pad;
-};
-
-// workgroup -> descriptor, workgroup index within its (rhs, chunk) set,
-// right-hand side and group chunk (for k_far_reduce: row block and rhs)
-struct WgMap {
-    int32_t desc, wg, j, chunk;
 };
 
 hipError_t upload_tables(const DeviceTables& t);
 hipError_t launch_roots(int64_t nmax, double* b, hipStream_t s);
 hipError_t launch_dht_e(int64_t N, const double* b, double* e, hipStream_t s);
 hipError_t launch_j0(const double* z, int64_t n, double* out, hipStream_t s);
-// single right-hand-side tiles (k_near) and multi right-hand-side tiles
-// (k_near_multi: J_0 evaluated once per entry, product on FP64 MFMA for nrhs >= 16)
-hipError_t launch_near(const NearProb* probs, const NearTile* tiles, int64_t ntiles, double* partial,
-                       hipStream_t s);
-hipError_t launch_near_multi(const NearProb* probs, const NearTile* tiles, int64_t ntiles, bool mfma,
-                             double* partial, hipStream_t s);
-hipError_t launch_near_reduce(const RowTile* rt, int64_t nrt, const double* partial, hipStream_t s);
+// Near field of nprob transforms with ntiles tiles in all: single
+// right-hand-side transforms (k_near) and transforms of 2..64 right-hand
+// sides (k_near_multi: J_0 evaluated once per entry as the A operand of
+// FP64 MFMA); then f = sum of the partials, nrt row tiles in all.
+hipError_t launch_near(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s);
+hipError_t launch_near_multi(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s);
+hipError_t launch_near_reduce(const NearProb* probs, int32_t nprob, int64_t nrt, const double* partial,
+                              hipStream_t s);
 hipError_t launch_chirp_spectrum(const FarArgs& A, bool fp32, void* work, void* H, hipStream_t s);
 // which: 0 pass A (inputs + column FFTs), 1 pass B (row FFT x H^ x inverse), 2 pass C (epilogue).
-// All descriptors of one launch share fp32 and the FFT split (L1, L2).
-// workgroups per block of the column passes (L1/8) and of pass B
+// All ndesc descriptors of one launch share fp32 and the FFT split (L1, L2);
+// nwg is the grid size of that pass.
+// workgroups per item of the column passes (L1/8) and of pass B
 int32_t far_rows_per_wg(int32_t L1);
-hipError_t launch_far_pass(int which, bool fp32, int32_t L1, int32_t L2, const FarDesc* descs,
-                           const WgMap* map, int64_t nwg, hipStream_t s);
+hipError_t launch_far_pass(int which, bool fp32, int32_t L1, int32_t L2, const FarDesc* descs, int32_t ndesc,
+                           int64_t nwg, hipStream_t s);
 // f += sum over chunks of part, 256 rows per workgroup
-hipError_t launch_far_reduce(const FarDesc* descs, const WgMap* map, int64_t nwg, hipStream_t s);
+hipError_t launch_far_reduce(const FarDesc* descs, int32_t ndesc, int64_t nwg, hipStream_t s);
 
 } // namespace hank

@@ -118,250 +118,355 @@ __device__ __forceinline__ double rsqrt_full(double z) {
     return y;
 }
 
-// J_0 at entry (k, n) of a near-field tile.  Row data per lane: Kd = K_k,
-// rk = r^_k, ek = e_k; column data (uniform): Nd = N_n, bn = b_n; ir = K_k N_n
-// mod 2D exactly.  M Hankel pairs; SMALL/ASY select the branches the tile needs.
-template <int M, bool SMALL, bool ASY>
-__device__ __forceinline__ double near_j0(const GridArgs& G, double Kd, double rk, double ek, double Nd,
-                                          double bn, int64_t ir) {
-    constexpr Hankel0 H = make_hankel0();
-    const double lam = fma(Nd, G.pi_Qc, bn);
-    const double delta = fma(ek, lam, rk * bn);
-    const double I = Kd * Nd; // exact: K_k N_n < 2^53
-    const double pz = I * G.piD_hi;
-    const double z = (pz + (fma(I, G.piD_hi, -pz) + I * G.piD_lo)) + delta;
-    double J = 0.0;
-    if (ASY) {
-        // phase/pi = ir/D - 1/4 + delta/pi
-        const double phi = fma((double)ir, G.invD, -0.25) + delta * 0.31830988618379067154;
-        double sn, cs;
-        sincospi(phi, &sn, &cs);
-        const double y = rsqrt_full(z), zi = y * y, zi2 = zi * zi;
-        double P = H.p[M - 1], Q = H.q[M - 1];
-#pragma unroll
-        for (int m = M - 2; m >= 0; --m) {
-            P = fma(P, zi2, H.p[m]);
-            Q = fma(Q, zi2, H.q[m]);
-        }
-        J = 0.79788456080286535588 * y * fma(cs, P, -sn * (Q * zi));
+// sin and cos of a residual phase |x| < 0.06 (Taylor; the first omitted terms
+// are below 1e-17)
+__device__ __forceinline__ void sincos_tiny(double x, double* s, double* c) {
+    const double x2 = x * x;
+    *s = x * fma(x2, fma(x2, fma(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+    *c = fma(x2, fma(x2, fma(x2, fma(x2, 1.0 / 40320.0, -1.0 / 720.0), 1.0 / 24.0), -0.5), 1.0);
+}
+
+// Index of the last of n descriptors whose grid offset (member M) is <= bid:
+// the descriptor of workgroup bid (offsets are non-decreasing; a descriptor
+// with no workgroups is never the last one at or below a valid bid).
+template <typename T, int64_t T::*M>
+__device__ __forceinline__ int find_desc(const T* __restrict__ d, int n, int64_t bid) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].*M <= bid)
+            lo = mid;
+        else
+            hi = mid - 1;
     }
+    return lo;
+}
+
+// State of one lane (one row k) sweeping the columns n, n+4, n+8, ... of a
+// near-field tile.  With z = z~ + delta, z~ = pi K_k N_n / D (Lemma 3.2's
+// split) the Hankel phase z - pi/4, in units of pi, is
+//     L_n + rho_n / pi,   L_n = ir_n/D - 1/4 + e_k N_n / Qc,   rho_n = (e_k + r^_k) b_n,
+// where ir_n = K_k N_n mod 2D is exact.  L_n grows by the same amount at every
+// step, so u = e^{i pi L_n} is advanced by one complex rotation w and set
+// afresh every 16 steps; e^{i rho_n} comes from sincos_tiny (b_n <= b_1 < 0.05).
+// Integers (ir, N_n) are carried exactly in doubles.
+struct NearLane {
+    double Kd, rk, ek, sk;
+    double ir, ir16, D2;
+    double Nd, dNd;
+    cx<double> u, w;
+    bool active;
+};
+
+__device__ __forceinline__ NearLane near_lane(const GridArgs& G, const double* __restrict__ evec,
+                                              const NearTile& T, int lane, int64_t n) {
+    NearLane r;
+    r.active = lane < T.nk;
+    const int64_t k = T.k0 + (r.active ? lane : 0);
+    const int64_t K = G.ar * k + G.br;
+    const int64_t D2 = 2 * G.D;
+    const int64_t Nn = G.ac * n + G.bc;
+    const int64_t step = (K * 4 * G.ac) % D2;
+    r.Kd = (double)K;
+    r.rk = r.Kd / (double)G.Dr;
+    r.ek = G.row_pert ? evec[k - 1] : 0.0;
+    r.sk = r.ek + r.rk;
+    r.ir = (double)((K * Nn) % D2);
+    r.ir16 = (double)((16 * step) % D2);
+    r.D2 = (double)D2;
+    r.Nd = (double)Nn;
+    r.dNd = (double)(4 * G.ac);
+    // w = e^{i pi step/D} (exactly reduced) times e^{i pi e_k 4 ac / Qc}
+    double s0, c0, s1, c1;
+    sincospi_ratio(step, G.D, &s0, &c0);
+    sincos_tiny(M_PI * r.ek * r.dNd * G.invQc, &s1, &c1);
+    r.w = cmul(mk(c0, s0), mk(c1, s1));
+    r.u = mk(1.0, 0.0);
+    return r;
+}
+
+// u = e^{i pi L_n} at the lane's current column
+__device__ __forceinline__ void near_anchor(const GridArgs& G, NearLane& r) {
+    double s, c;
+    sincospi(fma(r.ir, G.invD, -0.25) + r.ek * r.Nd * G.invQc, &s, &c);
+    r.u = mk(c, s);
+}
+
+// to the lane's column 16 steps on from the last anchor
+__device__ __forceinline__ void near_skip16(NearLane& r) {
+    r.ir += r.ir16;
+    if (r.ir >= r.D2) r.ir -= r.D2;
+}
+
+// Hankel expansion (Sec. 3.1, M pairs of terms) at the lane's current column;
+// bn = b_n (0 without column perturbations).  z only sets the amplitude and
+// the P, Q series, so it is formed to working precision.
+template <int M, bool PERT>
+__device__ __forceinline__ double near_asy(const GridArgs& G, const NearLane& r, double bn) {
+    constexpr Hankel0 H = make_hankel0();
+    const double delta = PERT ? fma(r.ek, fma(r.Nd, G.pi_Qc, bn), r.rk * bn) : 0.0;
+    const double z = fma(r.Kd * r.Nd, G.piD_hi, delta);
+    const double y = rsqrt_full(z), zi = y * y, zi2 = zi * zi;
+    double P = H.p[M - 1], Q = H.q[M - 1];
+#pragma unroll
+    for (int m = M - 2; m >= 0; --m) {
+        P = fma(P, zi2, H.p[m]);
+        Q = fma(Q, zi2, H.q[m]);
+    }
+    double cs = r.u.x, sn = r.u.y;
+    if (PERT) {
+        double s, c;
+        sincos_tiny(r.sk * bn, &s, &c);
+        cs = fma(r.u.x, c, -r.u.y * s);
+        sn = fma(r.u.y, c, r.u.x * s);
+    }
+    return (0.79788456080286535588 * y) * fma(cs, P, -sn * (Q * zi)); // sqrt(2/pi)
+}
+
+// z at the lane's current column with pi K N / D carried in two parts (the
+// small-argument branch needs it to absolute accuracy)
+__device__ __forceinline__ double near_z_exact(const GridArgs& G, const NearLane& r, double bn) {
+    const double delta = fma(r.ek, fma(r.Nd, G.pi_Qc, bn), r.rk * bn);
+    const double I = r.Kd * r.Nd; // exact: K_k N_n < 2^53
+    const double pz = I * G.piD_hi;
+    return (pz + (fma(I, G.piD_hi, -pz) + I * G.piD_lo)) + delta;
+}
+
+// J_0 at the lane's current column, then one step on
+template <int M, bool SMALL, bool ASY, bool PERT>
+__device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, double bn) {
+    double J = 0.0;
+    if (ASY) J = near_asy<M, PERT>(G, r, bn);
     if (SMALL) {
+        const double z = near_z_exact(G, r, bn);
         if (!ASY || z < J0_ASY_Z) J = j0_small(z);
     }
+    if (ASY) r.u = cmul(r.u, r.w);
+    r.Nd += r.dNd;
     return J;
 }
 
-// Near-field sweep of one tile (one right-hand side): columns n, n+4, ... < n1.
-template <int M, bool SMALL, bool ASY>
-__device__ __forceinline__ double near_sweep(const GridArgs& G, const double* __restrict__ c,
-                                             const double* __restrict__ bvec, int64_t n, int64_t n1,
-                                             double Kd, double rk, double ek, int64_t ir, int64_t step) {
-    const int64_t D2 = 2 * G.D;
+// Build knobs (measured variants): unroll of the near-field column loop, and
+// a lower bound on waves per SIMD for k_near (0: the compiler's choice).
+#ifndef HANK_NEAR_UNROLL
+#define HANK_NEAR_UNROLL 4
+#endif
+#ifndef HANK_NEAR_WPE
+#define HANK_NEAR_WPE 0
+#endif
+#define HANK_STR2(x) #x
+#define HANK_PRAGMA(x) _Pragma(HANK_STR2(x))
+
+struct alignas(16) ColCB {
+    double c, b;
+};
+
+// Near-field sweep of one tile (one right-hand side): columns n, n+4, ... < n1,
+// coefficients and root offsets read from LDS (cb[i] is column n0 + i).
+template <int M, bool SMALL, bool ASY, bool PERT>
+__device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb, int64_t n0, int64_t n, int64_t n1,
+                                             NearLane& r) {
     double acc = 0.0;
-    for (; n < n1; n += 4) {
-        const double cn = c[n - 1];
-        const double bn = G.col_pert ? bvec[n - 1] : 0.0;
-        const double Nd = (double)(G.ac * n + G.bc);
-        acc = fma(cn, near_j0<M, SMALL, ASY>(G, Kd, rk, ek, Nd, bn, ir), acc);
-        ir += step;
-        if (ir >= D2) ir -= D2;
+    for (; n < n1; n += 64) {
+        if (ASY) near_anchor(G, r);
+        const int cnt = (int)min<int64_t>(16, (n1 - n + 3) / 4);
+        const ColCB* p = cb + (n - n0);
+        HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
+        for (int i = 0; i < cnt; ++i) {
+            const ColCB v = p[4 * i];
+            acc = fma(v.c, near_step<M, SMALL, ASY, PERT>(G, r, PERT ? v.b : 0.0), acc);
+        }
+        near_skip16(r);
     }
     return acc;
 }
 
-// Row state of a near-field tile for lane `lane` and the column start n.
-struct NearRow {
-    double Kd, rk, ek;
-    int64_t ir, step;
-    bool active;
-};
-
-__device__ __forceinline__ NearRow near_row(const GridArgs& G, const double* __restrict__ evec, const NearTile& T,
-                                            int lane, int64_t n) {
-    NearRow r;
-    r.active = lane < T.nk;
-    const int64_t k = T.k0 + (r.active ? lane : 0);
-    const int64_t K = G.ar * k + G.br;
-    r.Kd = (double)K;
-    r.rk = (double)K / (double)G.Dr;
-    r.ek = G.row_pert ? evec[k - 1] : 0.0;
-    const int64_t D2 = 2 * G.D;
-    r.ir = (K * (G.ac * n + G.bc)) % D2;
-    r.step = (K * 4 * G.ac) % D2;
-    return r;
+// One workgroup = 64 rows (one per lane) x a column range of at most
+// NEAR_TILE_COLS; its 4 waves take every 4th column (the column data are
+// wave-uniform LDS reads) and their sums are added in a fixed order.  The
+// tile's flags (host-computed bounds on z over the tile) select the Hankel
+// term count and the branches.  One kernel serves every variant, so that
+// tiles of all kinds share a launch and fill the chip together.
+template <bool PERT>
+__device__ __forceinline__ double near_tile(const GridArgs& G, const ColCB* cb, const NearTile& T, NearLane& R,
+                                            int64_t n) {
+#define SWEEP(M_, S_, A_) return near_sweep<M_, S_, A_, PERT>(G, cb, T.n0, n, T.n1, R)
+    switch (near_variant(T.flags)) {
+    case 0: SWEEP(3, true, false);
+    case 1: SWEEP(12, true, true);
+    case 2: SWEEP(3, false, true);
+    case 3: SWEEP(4, false, true);
+    case 4: SWEEP(5, false, true);
+    case 5: SWEEP(6, false, true);
+    case 6: SWEEP(8, false, true);
+    default: SWEEP(12, false, true);
+    }
+#undef SWEEP
 }
 
-// One workgroup = 64 rows (one per lane) x a column range; its 4 waves take
-// every 4th column (wave-uniform, so the column data are scalar loads) and
-// their sums are added in a fixed order.  The tile's flags (host-computed
-// bounds on z over the tile) select the Hankel term count and the branches.
-__global__ __launch_bounds__(256) void k_near(const NearProb* __restrict__ probs,
-                                              const NearTile* __restrict__ tiles,
-                                              double* __restrict__ partial) {
+__global__ __launch_bounds__(256)
+#if HANK_NEAR_WPE
+__attribute__((amdgpu_waves_per_eu(HANK_NEAR_WPE)))
+#endif
+void k_near(const NearProb* __restrict__ probs, int nprob, double* __restrict__ partial) {
+    __shared__ ColCB cb[NEAR_TILE_COLS];
     __shared__ double red[4][64];
-    const NearTile T = tiles[blockIdx.x];
-    const GridArgs G = probs[T.prob].G; // by value: scalar registers, loaded once
-    const double* c = probs[T.prob].c;
-    const double* bvec = probs[T.prob].b;
+    const NearProb& P = probs[find_desc<NearProb, &NearProb::tile_start>(probs, nprob, blockIdx.x)];
+    const NearTile T = P.tiles[blockIdx.x - P.tile_start];
+    double* out = partial + P.pbase + T.slot * 64;
+    const GridArgs G = P.G; // by value: scalar registers, loaded once
+    const double* c = P.c;
+    const double* bvec = P.b;
+    const double* evec = P.e;
+    const int ncol = (int)(T.n1 - T.n0);
+    for (int i = threadIdx.x; i < ncol; i += 256) {
+        ColCB v;
+        v.c = c[T.n0 - 1 + i];
+        v.b = G.col_pert ? bvec[T.n0 - 1 + i] : 0.0;
+        cb[i] = v;
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t n = T.n0 + wave;
-    const NearRow R = near_row(G, probs[T.prob].e, T, lane, n);
-    const bool small = T.flags & 1, asy = T.flags & 2;
-    const int M = T.flags >> 8;
-    double acc = 0.0;
-#define SWEEP(M_, S_, A_) near_sweep<M_, S_, A_>(G, c, bvec, n, T.n1, R.Kd, R.rk, R.ek, R.ir, R.step)
-    if (!asy) {
-        acc = SWEEP(3, true, false);
-    } else if (small) {
-        acc = SWEEP(12, true, true);
-    } else {
-        switch (M) {
-        case 3: acc = SWEEP(3, false, true); break;
-        case 4: acc = SWEEP(4, false, true); break;
-        case 5: acc = SWEEP(5, false, true); break;
-        case 6: acc = SWEEP(6, false, true); break;
-        case 8: acc = SWEEP(8, false, true); break;
-        default: acc = SWEEP(12, false, true); break;
-        }
-    }
-#undef SWEEP
+    NearLane R = near_lane(G, evec, T, lane, n);
+    const double acc = G.col_pert ? near_tile<true>(G, cb, T, R, n) : near_tile<false>(G, cb, T, R, n);
     red[wave][lane] = R.active ? acc : 0.0;
     __syncthreads();
-    if (wave == 0)
-        partial[T.pbase + lane] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    if (wave == 0) out[lane] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Many right-hand sides: the tile's J_0 values are evaluated once, 64 columns
-// at a time, into LDS, and applied to every right-hand side -- a
-// (64 rows x 64 columns) by (64 columns x nrhs) product per step.  With MFMA
-// (nrhs >= 16) wave w owns rows 16w..16w+15 and all right-hand-side blocks of
-// 16 on v_mfma_f64_16x16x4f64; otherwise thread (row, wave) accumulates the
-// right-hand sides j = wave, wave+4, wave+8, wave+12 with FMAs.
-template <int M, bool SMALL, bool ASY, bool MFMA>
-__device__ __forceinline__ void near_multi_body(const NearProb& P, const NearTile& T, double (*Js)[65],
-                                                double (*Cs)[65], double* __restrict__ partial) {
+// Several right-hand sides (nrhs <= 64): a (64 rows x columns) by
+// (columns x nrhs) product on v_mfma_f64_16x16x4f64 whose A operand is J_0
+// evaluated in place.  Wave w owns rows 16w..16w+15; in a step of 4 columns
+// lane l evaluates J_0 for row 16w + l%16 and column l/16 -- exactly the A
+// layout (lane -> row l%16, k l/16) -- so J never goes through LDS, and each
+// lane sweeps its columns with stride 4 like k_near.  The coefficients of 64
+// columns at a time are staged in LDS as the B operand (lane -> k l/16,
+// right-hand side l%16); several workgroups per compute unit hide the
+// staging latency.
+// the fields of a NearProb that the sweeps use, held in scalar registers
+struct NearJob {
+    GridArgs G;
+    const double* c;
+    const double* b;
+    const double* e;
+    int64_t ldc;
+    int32_t nrhs;
+};
+
+__device__ __forceinline__ NearJob near_job(const NearProb& P) {
+    NearJob J;
+    J.G = P.G;
+    J.c = P.c;
+    J.b = P.b;
+    J.e = P.e;
+    J.ldc = P.ldc;
+    J.nrhs = P.nrhs;
+    return J;
+}
+
+constexpr int CS_LD = 80; // row stride of the coefficient tile (16 mod 32 banks)
+
+template <int M, bool SMALL, bool ASY, bool PERT>
+__device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile& T, double (*Cs)[CS_LD],
+                                                double* Bs, double* __restrict__ out) {
     const GridArgs& G = P.G;
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int nr = P.nrhs;
-    NearRow R = near_row(G, P.e, T, lane, T.n0 + wave);
-    const int64_t D2 = 2 * G.D;
-    v4d accm[4];
-    double acc[4];
+    const int nblk = (nr + 15) >> 4;
+    const int row = 16 * wave + (lane & 15), kq = lane >> 4;
+    NearLane R = near_lane(G, P.e, T, row, T.n0 + kq);
+    v4d acc[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        accm[i] = v4d{0.0, 0.0, 0.0, 0.0};
-        acc[i] = 0.0;
-    }
+    for (int i = 0; i < 4; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
     for (int64_t nb = T.n0; nb < T.n1; nb += 64) {
-        // J tile: wave w fills columns w, w+4, ..., w+60 for its lane's row
-#pragma unroll 4
-        for (int i = 0; i < 16; ++i) {
-            const int col = wave + 4 * i;
-            const int64_t n = nb + col;
-            double J = 0.0;
-            if (n < T.n1) {
-                const double bn = G.col_pert ? P.b[n - 1] : 0.0;
-                J = near_j0<M, SMALL, ASY>(G, R.Kd, R.rk, R.ek, (double)(G.ac * n + G.bc), bn, R.ir);
-            }
-            Js[col][lane] = R.active ? J : 0.0;
-            R.ir += R.step;
-            if (R.ir >= D2) R.ir -= D2;
-        }
-        // coefficient tile: Cs[col][j] = c_j[nb + col]
-#pragma unroll 4
-        for (int i = 0; i < 16; ++i) {
-            const int j = (t >> 6) + 4 * i;
+        // stage: thread t carries column t%64 of right-hand sides t/64 + 4i
+        {
             const int64_t n = nb + lane;
-            Cs[lane][j] = (j < nr && n < T.n1) ? P.c[(int64_t)j * P.ldc + n - 1] : 0.0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int j = (t >> 6) + 4 * i;
+                Cs[lane][j] = (j < nr && n < T.n1) ? P.c[(int64_t)j * P.ldc + n - 1] : 0.0;
+            }
+            if (PERT && t < 64) Bs[t] = n < T.n1 ? P.b[n - 1] : 0.0;
         }
         __syncthreads();
-        if (MFMA) {
-            // A (16x4): lane -> row l%16, k l/16;  B (4x16): lane -> k l/16, column l%16
-            const int ar = 16 * wave + (lane & 15), kq = lane >> 4;
-            for (int kc = 0; kc < 16; ++kc) {
-                const double a = Js[4 * kc + kq][ar];
+        if (ASY) near_anchor(G, R);
+#pragma unroll 1
+        for (int i = 0; i < 16; ++i) {
+            const int col = 4 * i + kq;
+            double J = near_step<M, SMALL, ASY, PERT>(G, R, PERT ? Bs[col] : 0.0);
+            J = (R.active && nb + col < T.n1) ? J : 0.0;
 #pragma unroll
-                for (int jb = 0; jb < 4; ++jb) {
-                    if (16 * jb < nr) {
-                        const double b = Cs[4 * kc + kq][16 * jb + (lane & 15)];
-                        accm[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, accm[jb], 0, 0, 0);
-                    }
-                }
-            }
-        } else {
-            for (int col = 0; col < 64; ++col) {
-                const double J = Js[col][lane];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i] = fma(J, Cs[col][wave + 4 * i], acc[i]);
-            }
+            for (int jb = 0; jb < 4; ++jb)
+                if (jb < nblk) acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(J, Cs[col][16 * jb + (lane & 15)], acc[jb], 0, 0, 0);
         }
+        near_skip16(R);
         __syncthreads();
     }
-    if (MFMA) {
-        // D (16x16): lane l, register r -> row l/16 + 4r, column l%16 (FP64 layout)
+    // D (16x16): lane l, register r -> row l/16 + 4r, column l%16 (FP64 layout)
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
-            const int j = 16 * jb + (lane & 15);
-            if (j < nr) {
+    for (int jb = 0; jb < 4; ++jb) {
+        const int j = 16 * jb + (lane & 15);
+        if (j < nr) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    partial[T.pbase + (int64_t)j * 64 + 16 * wave + (lane >> 4) + 4 * r] = accm[jb][r];
-            }
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int j = wave + 4 * i;
-            if (j < nr) partial[T.pbase + (int64_t)j * 64 + lane] = acc[i];
+            for (int r = 0; r < 4; ++r) out[(int64_t)j * 64 + 16 * wave + (lane >> 4) + 4 * r] = acc[jb][r];
         }
     }
 }
 
-template <bool MFMA>
-__global__ __launch_bounds__(256) void k_near_multi(const NearProb* __restrict__ probs,
-                                                    const NearTile* __restrict__ tiles,
-                                                    double* __restrict__ partial) {
-    __shared__ double Js[64][65];
-    __shared__ double Cs[64][65];
-    const NearTile T = tiles[blockIdx.x];
-    const NearProb P = probs[T.prob]; // by value: scalar registers, loaded once
-    const bool small = T.flags & 1, asy = T.flags & 2;
-    const int M = T.flags >> 8;
-    if (!asy) {
-        near_multi_body<3, true, false, MFMA>(P, T, Js, Cs, partial);
-    } else if (small) {
-        near_multi_body<12, true, true, MFMA>(P, T, Js, Cs, partial);
-    } else {
-        switch (M) {
-        case 3: near_multi_body<3, false, true, MFMA>(P, T, Js, Cs, partial); break;
-        case 4: near_multi_body<4, false, true, MFMA>(P, T, Js, Cs, partial); break;
-        case 5: near_multi_body<5, false, true, MFMA>(P, T, Js, Cs, partial); break;
-        case 6: near_multi_body<6, false, true, MFMA>(P, T, Js, Cs, partial); break;
-        case 8: near_multi_body<8, false, true, MFMA>(P, T, Js, Cs, partial); break;
-        default: near_multi_body<12, false, true, MFMA>(P, T, Js, Cs, partial); break;
-        }
+template <bool PERT>
+__device__ __forceinline__ void near_multi_tile(const NearJob& P, const NearTile& T, double (*Cs)[CS_LD], double* Bs,
+                                                double* __restrict__ partial) {
+#define BODY(M_, S_, A_) near_multi_body<M_, S_, A_, PERT>(P, T, Cs, Bs, partial); break
+    switch (near_variant(T.flags)) {
+    case 0: BODY(3, true, false);
+    case 1: BODY(12, true, true);
+    case 2: BODY(3, false, true);
+    case 3: BODY(4, false, true);
+    case 4: BODY(5, false, true);
+    case 5: BODY(6, false, true);
+    case 6: BODY(8, false, true);
+    default: BODY(12, false, true);
     }
+#undef BODY
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_near_multi(const NearProb* __restrict__ probs, int nprob,
+                                                    double* __restrict__ partial) {
+    __shared__ double Cs[64][CS_LD];
+    __shared__ double Bs[64];
+    const NearProb& Pr = probs[find_desc<NearProb, &NearProb::tile_start>(probs, nprob, blockIdx.x)];
+    const NearTile T = Pr.tiles[blockIdx.x - Pr.tile_start];
+    const NearJob P = near_job(Pr); // by value: scalar registers, loaded once
+    double* out = partial + Pr.pbase + T.slot * (int64_t)P.nrhs * 64;
+    if (P.G.col_pert)
+        near_multi_tile<true>(P, T, Cs, Bs, out);
+    else
+        near_multi_tile<false>(P, T, Cs, Bs, out);
 }
 
 // f_k = sum of the row's tile partials, per right-hand side; 4 waves take
 // every 4th tile and their sums are combined in a fixed order.
-__global__ __launch_bounds__(256) void k_near_reduce(const RowTile* __restrict__ rt,
+__global__ __launch_bounds__(256) void k_near_reduce(const NearProb* __restrict__ probs, int nprob,
                                                      const double* __restrict__ partial) {
     __shared__ double red[4][64];
-    const RowTile R = rt[blockIdx.x];
+    const NearProb& P = probs[find_desc<NearProb, &NearProb::rt_start>(probs, nprob, blockIdx.x)];
+    const RowTile R = P.rts[blockIdx.x - P.rt_start];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t per_tile = (int64_t)R.nrhs * 64;
-    for (int j = 0; j < R.nrhs; ++j) {
+    const int64_t per_tile = (int64_t)P.nrhs * 64;
+    const double* base = partial + P.pbase + R.slot0 * per_tile;
+    for (int j = 0; j < P.nrhs; ++j) {
         double s = 0.0;
-        for (int64_t t = wave; t < R.ntiles; t += 4) s += partial[R.pbase + t * per_tile + (int64_t)j * 64 + lane];
+        for (int64_t t = wave; t < R.ntiles; t += 4) s += base[t * per_tile + (int64_t)j * 64 + lane];
         red[wave][lane] = s;
         __syncthreads();
         if (wave == 0 && lane < R.nk)
-            R.f[(int64_t)j * R.ldo + R.k0 + lane - 1] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+            P.f[(int64_t)j * P.ldo + R.k0 + lane - 1] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
         __syncthreads();
     }
 }
@@ -382,6 +487,40 @@ __device__ __forceinline__ double ipow_d(double x, int e) {
     return inv ? 1.0 / r : r;
 }
 
+// (descriptor, workgroup within its item, right-hand side, group chunk) of
+// this workgroup.  which: 0 column passes (L1/8 workgroups per item),
+// 1 pass B (per_b workgroups per item), 2 chunk reduction (ceil(nrows/256)
+// per right-hand side).
+struct FarItem {
+    int desc, wg, j, chunk;
+};
+
+__device__ __forceinline__ FarItem far_item(const FarDesc* __restrict__ descs, int ndesc, int which, int per_b) {
+    const int64_t bid = blockIdx.x;
+    FarItem it;
+    int64_t local;
+    int per;
+    if (which == 0) {
+        it.desc = find_desc<FarDesc, &FarDesc::wg_ac>(descs, ndesc, bid);
+        local = bid - descs[it.desc].wg_ac;
+        per = descs[it.desc].A.L1 / 8;
+    } else if (which == 1) {
+        it.desc = find_desc<FarDesc, &FarDesc::wg_b>(descs, ndesc, bid);
+        local = bid - descs[it.desc].wg_b;
+        per = per_b;
+    } else {
+        it.desc = find_desc<FarDesc, &FarDesc::wg_r>(descs, ndesc, bid);
+        local = bid - descs[it.desc].wg_r;
+        per = (int)((descs[it.desc].A.nrows + 255) / 256);
+    }
+    const int item = (int)(local / per);
+    it.wg = (int)(local % per);
+    const int nch = which == 2 ? 1 : descs[it.desc].nchunk;
+    it.j = item / nch;
+    it.chunk = item % nch;
+    return it;
+}
+
 // Pass A on a block's data: y_n' = q(n') c_n X_g(n), column FFTs over j2, for
 // every right-hand side and group of the descriptor.  Per column position the
 // group-independent factors are kept:
@@ -389,11 +528,10 @@ __device__ __forceinline__ double ipow_d(double x, int e) {
 // and X_g = la^a vw^e sum_b K_{g,b} x^b, with vw^e updated incrementally over
 // the groups (sorted by a, then e).
 template <typename F, int L2, int W>
-__global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict__ descs,
-                                                       const WgMap* __restrict__ wmap) {
+__global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict__ descs, int ndesc) {
     constexpr int R = 8, NTC = L2 / R;
     __shared__ cx<F> sh[W * (L2 + L2 / 8)];
-    const WgMap mp = wmap[blockIdx.x];
+    const FarItem mp = far_item(descs, ndesc, 0, 0);
     const FarDesc& D = descs[mp.desc];
     const FarArgs& A = D.A;
     const int t = threadIdx.x, w = t % W, tt = t / W;
@@ -545,11 +683,11 @@ __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b_fwd(FarArgs A, const c
 #define HANK_PASSB_HREG 1
 #endif
 template <typename F, int L1, int ROWS>
-__global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(const FarDesc* __restrict__ descs,
-                                                           const WgMap* __restrict__ wmap) {
+__global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(const FarDesc* __restrict__ descs, int ndesc,
+                                                           int per_b) {
     constexpr int R = 8, NTR = L1 / R;
     __shared__ cx<F> sh[ROWS * (L1 + L1 / 8)];
-    const WgMap mp = wmap[blockIdx.x];
+    const FarItem mp = far_item(descs, ndesc, 1, per_b);
     const FarDesc& D = descs[mp.desc];
     const FarArgs& A = D.A;
     const int t = threadIdx.x, rl = t / NTR, tt = t % NTR;
@@ -604,11 +742,10 @@ __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(const FarDesc* __restr
 // A_g(k) = scale_g (e_k/eref)^a (r^_k/r0)^(e - 1/2), per right-hand side, with
 // the power of r^_k/r0 updated incrementally over the groups.
 template <typename F, int L2, int W>
-__global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict__ descs,
-                                                       const WgMap* __restrict__ wmap) {
+__global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict__ descs, int ndesc) {
     constexpr int R = 8, NTC = L2 / R;
     __shared__ cx<F> sh[W * (L2 + L2 / 8)];
-    const WgMap mp = wmap[blockIdx.x];
+    const FarItem mp = far_item(descs, ndesc, 0, 0);
     const FarDesc& D = descs[mp.desc];
     const FarArgs& A = D.A;
     const int t = threadIdx.x, w = t % W, tt = t / W;
@@ -688,9 +825,8 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict
 }
 
 // f += sum of the pass-C chunk sums, in chunk order (deterministic)
-__global__ __launch_bounds__(256) void k_far_reduce(const FarDesc* __restrict__ descs,
-                                                    const WgMap* __restrict__ wmap) {
-    const WgMap mp = wmap[blockIdx.x];
+__global__ __launch_bounds__(256) void k_far_reduce(const FarDesc* __restrict__ descs, int ndesc) {
+    const FarItem mp = far_item(descs, ndesc, 2, 0);
     const FarDesc& D = descs[mp.desc];
     const int64_t kp = (int64_t)mp.wg * 256 + threadIdx.x;
     if (kp >= D.A.nrows) return;
@@ -724,53 +860,49 @@ hipError_t launch_j0(const double* z, int64_t n, double* out, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_near(const NearProb* probs, const NearTile* tiles, int64_t ntiles, double* partial,
-                       hipStream_t s) {
-    if (ntiles > 0) hipLaunchKernelGGL(k_near, dim3((unsigned)ntiles), dim3(256), 0, s, probs, tiles, partial);
+hipError_t launch_near(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s) {
+    if (ntiles > 0) hipLaunchKernelGGL(k_near, dim3((unsigned)ntiles), dim3(256), 0, s, probs, (int)nprob, partial);
     return hipGetLastError();
 }
 
-hipError_t launch_near_multi(const NearProb* probs, const NearTile* tiles, int64_t ntiles, bool mfma,
-                             double* partial, hipStream_t s) {
-    if (ntiles <= 0) return hipSuccess;
-    if (mfma)
-        hipLaunchKernelGGL(k_near_multi<true>, dim3((unsigned)ntiles), dim3(256), 0, s, probs, tiles, partial);
-    else
-        hipLaunchKernelGGL(k_near_multi<false>, dim3((unsigned)ntiles), dim3(256), 0, s, probs, tiles, partial);
+hipError_t launch_near_multi(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s) {
+    if (ntiles > 0)
+        hipLaunchKernelGGL(k_near_multi, dim3((unsigned)ntiles), dim3(256), 0, s, probs, (int)nprob, partial);
     return hipGetLastError();
 }
 
-hipError_t launch_near_reduce(const RowTile* rt, int64_t nrt, const double* partial, hipStream_t s) {
-    if (nrt > 0) hipLaunchKernelGGL(k_near_reduce, dim3((unsigned)nrt), dim3(256), 0, s, rt, partial);
+hipError_t launch_near_reduce(const NearProb* probs, int32_t nprob, int64_t nrt, const double* partial,
+                              hipStream_t s) {
+    if (nrt > 0) hipLaunchKernelGGL(k_near_reduce, dim3((unsigned)nrt), dim3(256), 0, s, probs, (int)nprob, partial);
     return hipGetLastError();
 }
 
 // column passes: which 0 = A on data, 1 = A on the chirp kernel, 2 = C
 template <typename F, int L2>
-static void pass_ac_dispatch(int which, const FarArgs* A, const FarDesc* descs, const WgMap* map, int64_t nwg,
-                             void* buf, hipStream_t s) {
+static void pass_ac_dispatch(int which, const FarArgs* A, const FarDesc* descs, int ndesc, int64_t nwg, void* buf,
+                             hipStream_t s) {
     constexpr int W = 8;
     dim3 block(W * L2 / 8);
     if (which == 0)
-        hipLaunchKernelGGL((k_pass_a<F, L2, W>), dim3((unsigned)nwg), block, 0, s, descs, map);
+        hipLaunchKernelGGL((k_pass_a<F, L2, W>), dim3((unsigned)nwg), block, 0, s, descs, ndesc);
     else if (which == 1)
         hipLaunchKernelGGL((k_pass_a_kernel<F, L2, W>), dim3((unsigned)(A->L1 / W)), block, 0, s, *A, (cx<F>*)buf);
     else
-        hipLaunchKernelGGL((k_pass_c<F, L2, W>), dim3((unsigned)nwg), block, 0, s, descs, map);
+        hipLaunchKernelGGL((k_pass_c<F, L2, W>), dim3((unsigned)nwg), block, 0, s, descs, ndesc);
 }
 
 template <typename F>
-static hipError_t pass_ac(int which, int32_t L2, const FarArgs* A, const FarDesc* descs, const WgMap* map,
-                          int64_t nwg, void* buf, hipStream_t s) {
+static hipError_t pass_ac(int which, int32_t L2, const FarArgs* A, const FarDesc* descs, int ndesc, int64_t nwg,
+                          void* buf, hipStream_t s) {
     switch (L2) {
-    case 8: pass_ac_dispatch<F, 8>(which, A, descs, map, nwg, buf, s); break;
-    case 16: pass_ac_dispatch<F, 16>(which, A, descs, map, nwg, buf, s); break;
-    case 32: pass_ac_dispatch<F, 32>(which, A, descs, map, nwg, buf, s); break;
-    case 64: pass_ac_dispatch<F, 64>(which, A, descs, map, nwg, buf, s); break;
-    case 128: pass_ac_dispatch<F, 128>(which, A, descs, map, nwg, buf, s); break;
-    case 256: pass_ac_dispatch<F, 256>(which, A, descs, map, nwg, buf, s); break;
-    case 512: pass_ac_dispatch<F, 512>(which, A, descs, map, nwg, buf, s); break;
-    case 1024: pass_ac_dispatch<F, 1024>(which, A, descs, map, nwg, buf, s); break;
+    case 8: pass_ac_dispatch<F, 8>(which, A, descs, ndesc, nwg, buf, s); break;
+    case 16: pass_ac_dispatch<F, 16>(which, A, descs, ndesc, nwg, buf, s); break;
+    case 32: pass_ac_dispatch<F, 32>(which, A, descs, ndesc, nwg, buf, s); break;
+    case 64: pass_ac_dispatch<F, 64>(which, A, descs, ndesc, nwg, buf, s); break;
+    case 128: pass_ac_dispatch<F, 128>(which, A, descs, ndesc, nwg, buf, s); break;
+    case 256: pass_ac_dispatch<F, 256>(which, A, descs, ndesc, nwg, buf, s); break;
+    case 512: pass_ac_dispatch<F, 512>(which, A, descs, ndesc, nwg, buf, s); break;
+    case 1024: pass_ac_dispatch<F, 1024>(which, A, descs, ndesc, nwg, buf, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -783,7 +915,7 @@ constexpr int rows_per_wg() {
 
 // row passes: fwd_only = the chirp spectrum (one block by value), else pass B
 template <typename F, int L1>
-static void pass_b_dispatch(bool fwd_only, const FarArgs* A, const FarDesc* descs, const WgMap* map,
+static void pass_b_dispatch(bool fwd_only, const FarArgs* A, int32_t L2, const FarDesc* descs, int ndesc,
                             int64_t nwg, void* buf, void* H, hipStream_t s) {
     constexpr int ROWS = rows_per_wg<L1>();
     dim3 block(ROWS * L1 / 8);
@@ -791,24 +923,25 @@ static void pass_b_dispatch(bool fwd_only, const FarArgs* A, const FarDesc* desc
         hipLaunchKernelGGL((k_pass_b_fwd<F, L1, ROWS>), dim3((unsigned)((A->L2 + ROWS - 1) / ROWS)), block, 0, s, *A,
                            (const cx<F>*)buf, (cx<F>*)H);
     else
-        hipLaunchKernelGGL((k_pass_b<F, L1, ROWS>), dim3((unsigned)nwg), block, 0, s, descs, map);
+        hipLaunchKernelGGL((k_pass_b<F, L1, ROWS>), dim3((unsigned)nwg), block, 0, s, descs, ndesc,
+                           (int)((L2 + ROWS - 1) / ROWS));
 }
 
 template <typename F>
-static hipError_t pass_b(bool fwd_only, int32_t L1, const FarArgs* A, const FarDesc* descs, const WgMap* map,
+static hipError_t pass_b(bool fwd_only, int32_t L1, const FarArgs* A, int32_t L2, const FarDesc* descs, int ndesc,
                          int64_t nwg, void* buf, void* H, hipStream_t s) {
     switch (L1) {
-    case 8: pass_b_dispatch<F, 8>(fwd_only, A, descs, map, nwg, buf, H, s); break;
-    case 16: pass_b_dispatch<F, 16>(fwd_only, A, descs, map, nwg, buf, H, s); break;
-    case 32: pass_b_dispatch<F, 32>(fwd_only, A, descs, map, nwg, buf, H, s); break;
-    case 64: pass_b_dispatch<F, 64>(fwd_only, A, descs, map, nwg, buf, H, s); break;
-    case 128: pass_b_dispatch<F, 128>(fwd_only, A, descs, map, nwg, buf, H, s); break;
-    case 256: pass_b_dispatch<F, 256>(fwd_only, A, descs, map, nwg, buf, H, s); break;
-    case 512: pass_b_dispatch<F, 512>(fwd_only, A, descs, map, nwg, buf, H, s); break;
-    case 1024: pass_b_dispatch<F, 1024>(fwd_only, A, descs, map, nwg, buf, H, s); break;
-    case 2048: pass_b_dispatch<F, 2048>(fwd_only, A, descs, map, nwg, buf, H, s); break;
-    case 4096: pass_b_dispatch<F, 4096>(fwd_only, A, descs, map, nwg, buf, H, s); break;
-    case 8192: pass_b_dispatch<F, 8192>(fwd_only, A, descs, map, nwg, buf, H, s); break;
+    case 8: pass_b_dispatch<F, 8>(fwd_only, A, L2, descs, ndesc, nwg, buf, H, s); break;
+    case 16: pass_b_dispatch<F, 16>(fwd_only, A, L2, descs, ndesc, nwg, buf, H, s); break;
+    case 32: pass_b_dispatch<F, 32>(fwd_only, A, L2, descs, ndesc, nwg, buf, H, s); break;
+    case 64: pass_b_dispatch<F, 64>(fwd_only, A, L2, descs, ndesc, nwg, buf, H, s); break;
+    case 128: pass_b_dispatch<F, 128>(fwd_only, A, L2, descs, ndesc, nwg, buf, H, s); break;
+    case 256: pass_b_dispatch<F, 256>(fwd_only, A, L2, descs, ndesc, nwg, buf, H, s); break;
+    case 512: pass_b_dispatch<F, 512>(fwd_only, A, L2, descs, ndesc, nwg, buf, H, s); break;
+    case 1024: pass_b_dispatch<F, 1024>(fwd_only, A, L2, descs, ndesc, nwg, buf, H, s); break;
+    case 2048: pass_b_dispatch<F, 2048>(fwd_only, A, L2, descs, ndesc, nwg, buf, H, s); break;
+    case 4096: pass_b_dispatch<F, 4096>(fwd_only, A, L2, descs, ndesc, nwg, buf, H, s); break;
+    case 8192: pass_b_dispatch<F, 8192>(fwd_only, A, L2, descs, ndesc, nwg, buf, H, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -816,28 +949,28 @@ static hipError_t pass_b(bool fwd_only, int32_t L1, const FarArgs* A, const FarD
 
 int32_t far_rows_per_wg(int32_t L1) { return L1 >= 2048 ? 1 : 2048 / L1; }
 
-hipError_t launch_far_reduce(const FarDesc* descs, const WgMap* map, int64_t nwg, hipStream_t s) {
-    if (nwg > 0) hipLaunchKernelGGL(k_far_reduce, dim3((unsigned)nwg), dim3(256), 0, s, descs, map);
+hipError_t launch_far_reduce(const FarDesc* descs, int32_t ndesc, int64_t nwg, hipStream_t s) {
+    if (nwg > 0) hipLaunchKernelGGL(k_far_reduce, dim3((unsigned)nwg), dim3(256), 0, s, descs, (int)ndesc);
     return hipGetLastError();
 }
 
 hipError_t launch_chirp_spectrum(const FarArgs& A, bool fp32, void* work, void* H, hipStream_t s) {
-    hipError_t e = fp32 ? pass_ac<float>(1, A.L2, &A, nullptr, nullptr, 0, work, s)
-                        : pass_ac<double>(1, A.L2, &A, nullptr, nullptr, 0, work, s);
+    hipError_t e = fp32 ? pass_ac<float>(1, A.L2, &A, nullptr, 0, 0, work, s)
+                        : pass_ac<double>(1, A.L2, &A, nullptr, 0, 0, work, s);
     if (e != hipSuccess) return e;
-    return fp32 ? pass_b<float>(true, A.L1, &A, nullptr, nullptr, 0, work, H, s)
-                : pass_b<double>(true, A.L1, &A, nullptr, nullptr, 0, work, H, s);
+    return fp32 ? pass_b<float>(true, A.L1, &A, A.L2, nullptr, 0, 0, work, H, s)
+                : pass_b<double>(true, A.L1, &A, A.L2, nullptr, 0, 0, work, H, s);
 }
 
-hipError_t launch_far_pass(int which, bool fp32, int32_t L1, int32_t L2, const FarDesc* descs, const WgMap* map,
+hipError_t launch_far_pass(int which, bool fp32, int32_t L1, int32_t L2, const FarDesc* descs, int32_t ndesc,
                            int64_t nwg, hipStream_t s) {
     if (nwg <= 0) return hipSuccess;
     if (which == 1)
-        return fp32 ? pass_b<float>(false, L1, nullptr, descs, map, nwg, nullptr, nullptr, s)
-                    : pass_b<double>(false, L1, nullptr, descs, map, nwg, nullptr, nullptr, s);
+        return fp32 ? pass_b<float>(false, L1, nullptr, L2, descs, ndesc, nwg, nullptr, nullptr, s)
+                    : pass_b<double>(false, L1, nullptr, L2, descs, ndesc, nwg, nullptr, nullptr, s);
     const int w = (which == 0) ? 0 : 2;
-    return fp32 ? pass_ac<float>(w, L2, nullptr, descs, map, nwg, nullptr, s)
-                : pass_ac<double>(w, L2, nullptr, descs, map, nwg, nullptr, s);
+    return fp32 ? pass_ac<float>(w, L2, nullptr, descs, ndesc, nwg, nullptr, s)
+                : pass_ac<double>(w, L2, nullptr, descs, ndesc, nwg, nullptr, s);
 }
 
 } // namespace hank

@@ -90,9 +90,9 @@ struct Plan {
 struct CostModel {
     double fft_pt_group64 = 3.0e-11; // per FFT point per group per right-hand side, FP64 bulk (measured)
     double fft_pt_group32 = 1.7e-11; // same, FP32 bulk
-    double near_entry = 4.6e-12;     // per directly summed entry, one right-hand side (measured)
-    double near_multi_entry = 7.0e-12; // per entry with several right-hand sides (J_0 once, staged in LDS)
-    double near_rhs = 2.7e-13;       // per entry and right-hand side of the product (FP64 MFMA / FMA)
+    double near_entry = 3.2e-12;     // per directly summed entry, one right-hand side (measured)
+    double near_multi_entry = 4.2e-12; // per entry with several right-hand sides (J_0 once per entry)
+    double near_rhs = 4.5e-14;       // per entry and right-hand side of the product (FP64 MFMA)
     double block = 20e-6;            // fixed cost per block (three launches)
 };
 

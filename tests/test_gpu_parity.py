@@ -133,7 +133,7 @@ def test_deterministic_and_linear():
         assert np.max(np.abs(fab - (2.0 * fa - 3.0 * fb))) <= 1e-12 * np.sum(np.abs(a) + np.abs(b))
 
 
-@pytest.mark.parametrize("nrhs", [2, 5, 16, 23, 64])
+@pytest.mark.parametrize("nrhs", [2, 5, 16, 23, 64, 130])
 @pytest.mark.parametrize("task", ["fourier_bessel", "dht0"])
 @pytest.mark.parametrize("mode", ["tuned", "far"])
 def test_multiple_right_hand_sides(task, nrhs, mode):
