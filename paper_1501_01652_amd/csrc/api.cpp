@@ -238,9 +238,26 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
             r.ntiles = int64_t(tiles.size()) - r.slot0;
             rts.push_back(r);
         }
-    auto tile_cost = [](const NearTile& T) {
-        static const double w[8] = {3.0, 3.0, 1.0, 1.05, 1.1, 1.15, 1.25, 1.45};
-        return double(T.n1 - T.n0) * w[near_variant(T.flags)];
+    // relative cost of a tile: its 64-column blocks priced by the variant the
+    // kernel picks for each (the same bounds on z as there)
+    auto tile_cost = [&](const NearTile& T) {
+        static const double w[5] = {0.8, 2.0, 1.0, 1.1, 1.45};
+        const double Klo = double(g.ar * T.k0 + g.br), Khi = double(g.ar * (T.k0 + T.nk - 1) + g.br);
+        const double piD = M_PI / double(g.D);
+        double c = 0;
+        for (int64_t nb = T.n0; nb < T.n1; nb += 64) {
+            const int64_t nl = std::min(nb + 63, T.n1 - 1);
+            const double zlo = Klo * double(g.ac * nb + g.bc) * piD, zhi = Khi * double(g.ac * nl + g.bc) * piD + 0.25;
+            int v;
+            if (!(zhi >= J0_ASY_Z))
+                v = 0;
+            else if (zlo < J0_ASY_Z)
+                v = 1;
+            else
+                v = zlo < 44.0 ? 4 : zlo < 123.0 ? 3 : 2;
+            c += double(nl - nb + 1) * w[v];
+        }
+        return c;
     };
     std::stable_sort(tiles.begin(), tiles.end(),
                      [&](const NearTile& a, const NearTile& b) { return tile_cost(a) > tile_cost(b); });

@@ -249,7 +249,7 @@ __device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, doub
 // Build knobs (measured variants): unroll of the near-field column loop, and
 // a lower bound on waves per SIMD for k_near (0: the compiler's choice).
 #ifndef HANK_NEAR_UNROLL
-#define HANK_NEAR_UNROLL 4
+#define HANK_NEAR_UNROLL 2
 #endif
 #ifndef HANK_NEAR_WPE
 #define HANK_NEAR_WPE 0
@@ -261,21 +261,53 @@ struct alignas(16) ColCB {
     double c, b;
 };
 
-// Near-field sweep of one tile (one right-hand side): columns n, n+4, ... < n1,
-// coefficients and root offsets read from LDS (cb[i] is column n0 + i).
+// Kernel variant of the block of columns [nlo, nhi] of a tile with rows of
+// K from Klo to Khi, from bounds on z over it (z~ <= z <= z~ + 0.25), so that
+// only blocks that straddle z = 20 pay for both branches: 0 only z < 20,
+// 1 both branches, 2..4 Hankel with M = 4, 6, 12 pairs (remainder below
+// 1e-17 for z >= 123, 44, 20).
+__device__ __forceinline__ int block_variant(const GridArgs& G, double Klo, double Khi, double Nlo, double Nhi) {
+    const double zlo = Klo * Nlo * G.piD_hi, zhi = Khi * Nhi * G.piD_hi + 0.25;
+    if (!(zhi >= J0_ASY_Z)) return 0;
+    if (zlo < J0_ASY_Z) return 1;
+    return zlo < 44.0 ? 4 : zlo < 123.0 ? 3 : 2;
+}
+
+// One 64-column block of a sweep: the lane's columns p[0], p[4], ... (cnt of them)
 template <int M, bool SMALL, bool ASY, bool PERT>
-__device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb, int64_t n0, int64_t n, int64_t n1,
+__device__ __forceinline__ void near_block(const GridArgs& G, const ColCB* p, int cnt, NearLane& r, double& acc) {
+    if (ASY) near_anchor(G, r);
+    HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
+    for (int i = 0; i < cnt; ++i) {
+        const ColCB v = p[4 * i];
+        acc = fma(v.c, near_step<M, SMALL, ASY, PERT>(G, r, PERT ? v.b : 0.0), acc);
+    }
+}
+
+// Near-field sweep of one tile (one right-hand side) for the wave whose first
+// column is n: columns n, n+4, ... < T.n1, 16 per block of 64, coefficients
+// and root offsets read from LDS (cb[i] is column T.n0 + i).  The variant is
+// chosen per block (wave-uniform).
+template <bool PERT>
+__device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb, const NearTile& T, int64_t n,
                                              NearLane& r) {
+    const double Klo = (double)(G.ar * T.k0 + G.br), Khi = (double)(G.ar * (T.k0 + T.nk - 1) + G.br);
     double acc = 0.0;
-    for (; n < n1; n += 64) {
-        if (ASY) near_anchor(G, r);
-        const int cnt = (int)min<int64_t>(16, (n1 - n + 3) / 4);
-        const ColCB* p = cb + (n - n0);
-        HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
-        for (int i = 0; i < cnt; ++i) {
-            const ColCB v = p[4 * i];
-            acc = fma(v.c, near_step<M, SMALL, ASY, PERT>(G, r, PERT ? v.b : 0.0), acc);
+    for (int64_t nb = T.n0; nb < T.n1; nb += 64) {
+        const int64_t nlast = min(nb + 63, T.n1 - 1);
+        const int v = block_variant(G, Klo, Khi, (double)(G.ac * nb + G.bc), (double)(G.ac * nlast + G.bc));
+        const int64_t nw = n + (nb - T.n0);
+        const int cnt = (int)min<int64_t>(16, (T.n1 - nw + 3) / 4);
+        const ColCB* p = cb + (nw - T.n0);
+#define BLOCK(M_, S_, A_) near_block<M_, S_, A_, PERT>(G, p, cnt, r, acc); break
+        switch (v) {
+        case 0: BLOCK(3, true, false);
+        case 1: BLOCK(12, true, true);
+        case 2: BLOCK(4, false, true);
+        case 3: BLOCK(6, false, true);
+        default: BLOCK(12, false, true);
         }
+#undef BLOCK
         near_skip16(r);
     }
     return acc;
@@ -283,27 +315,9 @@ __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb,
 
 // One workgroup = 64 rows (one per lane) x a column range of at most
 // NEAR_TILE_COLS; its 4 waves take every 4th column (the column data are
-// wave-uniform LDS reads) and their sums are added in a fixed order.  The
-// tile's flags (host-computed bounds on z over the tile) select the Hankel
-// term count and the branches.  One kernel serves every variant, so that
-// tiles of all kinds share a launch and fill the chip together.
-template <bool PERT>
-__device__ __forceinline__ double near_tile(const GridArgs& G, const ColCB* cb, const NearTile& T, NearLane& R,
-                                            int64_t n) {
-#define SWEEP(M_, S_, A_) return near_sweep<M_, S_, A_, PERT>(G, cb, T.n0, n, T.n1, R)
-    switch (near_variant(T.flags)) {
-    case 0: SWEEP(3, true, false);
-    case 1: SWEEP(12, true, true);
-    case 2: SWEEP(3, false, true);
-    case 3: SWEEP(4, false, true);
-    case 4: SWEEP(5, false, true);
-    case 5: SWEEP(6, false, true);
-    case 6: SWEEP(8, false, true);
-    default: SWEEP(12, false, true);
-    }
-#undef SWEEP
-}
-
+// wave-uniform LDS reads) and their sums are added in a fixed order.  One
+// kernel serves every variant, so that tiles of all kinds share a launch and
+// fill the chip together.
 __global__ __launch_bounds__(256)
 #if HANK_NEAR_WPE
 __attribute__((amdgpu_waves_per_eu(HANK_NEAR_WPE)))
@@ -330,7 +344,7 @@ void k_near(const NearProb* __restrict__ probs, int nprob, double* __restrict__ 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t n = T.n0 + wave;
     NearLane R = near_lane(G, evec, T, lane, n);
-    const double acc = G.col_pert ? near_tile<true>(G, cb, T, R, n) : near_tile<false>(G, cb, T, R, n);
+    const double acc = G.col_pert ? near_sweep<true>(G, cb, T, n, R) : near_sweep<false>(G, cb, T, n, R);
     red[wave][lane] = R.active ? acc : 0.0;
     __syncthreads();
     if (wave == 0) out[lane] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
@@ -370,7 +384,24 @@ __device__ __forceinline__ NearJob near_job(const NearProb& P) {
 
 constexpr int CS_LD = 80; // row stride of the coefficient tile (16 mod 32 banks)
 
+// 16 steps of 4 columns (one 64-column block) of the multi right-hand-side product
 template <int M, bool SMALL, bool ASY, bool PERT>
+__device__ __forceinline__ void near_multi_block(const GridArgs& G, NearLane& R, const double (*Cs)[CS_LD],
+                                                 const double* Bs, int64_t nb, int64_t n1, int kq, int lane, int nblk,
+                                                 v4d (&acc)[4]) {
+    if (ASY) near_anchor(G, R);
+#pragma unroll 1
+    for (int i = 0; i < 16; ++i) {
+        const int col = 4 * i + kq;
+        double J = near_step<M, SMALL, ASY, PERT>(G, R, PERT ? Bs[col] : 0.0);
+        J = (R.active && nb + col < n1) ? J : 0.0;
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+            if (jb < nblk) acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(J, Cs[col][16 * jb + (lane & 15)], acc[jb], 0, 0, 0);
+    }
+}
+
+template <bool PERT>
 __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile& T, double (*Cs)[CS_LD],
                                                 double* Bs, double* __restrict__ out) {
     const GridArgs& G = P.G;
@@ -380,6 +411,7 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
     const int nblk = (nr + 15) >> 4;
     const int row = 16 * wave + (lane & 15), kq = lane >> 4;
     NearLane R = near_lane(G, P.e, T, row, T.n0 + kq);
+    const double Klo = (double)(G.ar * T.k0 + G.br), Khi = (double)(G.ar * (T.k0 + T.nk - 1) + G.br);
     v4d acc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -395,16 +427,17 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
             if (PERT && t < 64) Bs[t] = n < T.n1 ? P.b[n - 1] : 0.0;
         }
         __syncthreads();
-        if (ASY) near_anchor(G, R);
-#pragma unroll 1
-        for (int i = 0; i < 16; ++i) {
-            const int col = 4 * i + kq;
-            double J = near_step<M, SMALL, ASY, PERT>(G, R, PERT ? Bs[col] : 0.0);
-            J = (R.active && nb + col < T.n1) ? J : 0.0;
-#pragma unroll
-            for (int jb = 0; jb < 4; ++jb)
-                if (jb < nblk) acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(J, Cs[col][16 * jb + (lane & 15)], acc[jb], 0, 0, 0);
+        const int64_t nlast = min(nb + 63, T.n1 - 1);
+        const int v = block_variant(G, Klo, Khi, (double)(G.ac * nb + G.bc), (double)(G.ac * nlast + G.bc));
+#define BLOCK(M_, S_, A_) near_multi_block<M_, S_, A_, PERT>(G, R, Cs, Bs, nb, T.n1, kq, lane, nblk, acc); break
+        switch (v) {
+        case 0: BLOCK(3, true, false);
+        case 1: BLOCK(12, true, true);
+        case 2: BLOCK(4, false, true);
+        case 3: BLOCK(6, false, true);
+        default: BLOCK(12, false, true);
         }
+#undef BLOCK
         near_skip16(R);
         __syncthreads();
     }
@@ -419,23 +452,6 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
     }
 }
 
-template <bool PERT>
-__device__ __forceinline__ void near_multi_tile(const NearJob& P, const NearTile& T, double (*Cs)[CS_LD], double* Bs,
-                                                double* __restrict__ partial) {
-#define BODY(M_, S_, A_) near_multi_body<M_, S_, A_, PERT>(P, T, Cs, Bs, partial); break
-    switch (near_variant(T.flags)) {
-    case 0: BODY(3, true, false);
-    case 1: BODY(12, true, true);
-    case 2: BODY(3, false, true);
-    case 3: BODY(4, false, true);
-    case 4: BODY(5, false, true);
-    case 5: BODY(6, false, true);
-    case 6: BODY(8, false, true);
-    default: BODY(12, false, true);
-    }
-#undef BODY
-}
-
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_near_multi(const NearProb* __restrict__ probs, int nprob,
                                                     double* __restrict__ partial) {
     __shared__ double Cs[64][CS_LD];
@@ -445,9 +461,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const NearJob P = near_job(Pr); // by value: scalar registers, loaded once
     double* out = partial + Pr.pbase + T.slot * (int64_t)P.nrhs * 64;
     if (P.G.col_pert)
-        near_multi_tile<true>(P, T, Cs, Bs, out);
+        near_multi_body<true>(P, T, Cs, Bs, out);
     else
-        near_multi_tile<false>(P, T, Cs, Bs, out);
+        near_multi_body<false>(P, T, Cs, Bs, out);
 }
 
 // f_k = sum of the row's tile partials, per right-hand side; 4 waves take
@@ -485,6 +501,13 @@ __device__ __forceinline__ double ipow_d(double x, int e) {
         u >>= 1;
     }
     return inv ? 1.0 / r : r;
+}
+
+// LDS elements per column FFT buffer of the column passes: L2 + L2/8 made
+// odd, so that the W columns of a workgroup start in different banks
+template <int L2>
+constexpr int col_stride() {
+    return (L2 + L2 / 8) | 1;
 }
 
 // (descriptor, workgroup within its item, right-hand side, group chunk) of
@@ -530,13 +553,13 @@ __device__ __forceinline__ FarItem far_item(const FarDesc* __restrict__ descs, i
 template <typename F, int L2, int W>
 __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict__ descs, int ndesc) {
     constexpr int R = 8, NTC = L2 / R;
-    __shared__ cx<F> sh[W * (L2 + L2 / 8)];
+    __shared__ cx<F> sh[W * col_stride<L2>()];
     const FarItem mp = far_item(descs, ndesc, 0, 0);
     const FarDesc& D = descs[mp.desc];
     const FarArgs& A = D.A;
     const int t = threadIdx.x, w = t % W, tt = t / W;
     const int64_t j1 = (int64_t)mp.wg * W + w;
-    cx<F>* my = sh + w * (L2 + L2 / 8);
+    cx<F>* my = sh + w * col_stride<L2>();
     const int ng = A.g1 - A.g0;
     cx<F>* buf = (cx<F>*)D.buf;
 
@@ -624,10 +647,10 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict
 template <typename F, int L2, int W>
 __global__ __launch_bounds__(W * L2 / 8) void k_pass_a_kernel(FarArgs A, cx<F>* __restrict__ buf) {
     constexpr int R = 8, NTC = L2 / R;
-    __shared__ cx<F> sh[W * (L2 + L2 / 8)];
+    __shared__ cx<F> sh[W * col_stride<L2>()];
     const int t = threadIdx.x, w = t % W, tt = t / W;
     const int64_t j1 = (int64_t)blockIdx.x * W + w;
-    cx<F>* my = sh + w * (L2 + L2 / 8);
+    cx<F>* my = sh + w * col_stride<L2>();
     cx<F> v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -744,13 +767,13 @@ __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(const FarDesc* __restr
 template <typename F, int L2, int W>
 __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict__ descs, int ndesc) {
     constexpr int R = 8, NTC = L2 / R;
-    __shared__ cx<F> sh[W * (L2 + L2 / 8)];
+    __shared__ cx<F> sh[W * col_stride<L2>()];
     const FarItem mp = far_item(descs, ndesc, 0, 0);
     const FarDesc& D = descs[mp.desc];
     const FarArgs& A = D.A;
     const int t = threadIdx.x, w = t % W, tt = t / W;
     const int64_t j1 = (int64_t)mp.wg * W + w;
-    cx<F>* my = sh + w * (L2 + L2 / 8);
+    cx<F>* my = sh + w * col_stride<L2>();
     const int ng = A.g1 - A.g0;
     const cx<F>* buf = (const cx<F>*)D.buf;
     double rho[R], ek[R], acc[R], pw[R];

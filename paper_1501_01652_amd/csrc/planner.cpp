@@ -135,8 +135,13 @@ void fft_split(int64_t L, int32_t& L1, int32_t& L2) {
     int lg = 0;
     while ((int64_t(1) << lg) < L) ++lg;
     // columns (passes A and C) of 2^l2 <= 1024 points, rows (pass B) of
-    // 2^l1 <= 8192 points; balanced below 2^16, columns of 256 above
-    int l2 = (lg <= 16) ? lg / 2 : std::max(8, lg - 13);
+    // 2^l1 <= 2^l1max points (l1max = 13, HANK_FFT_L1MAX overrides);
+    // balanced below 2^16, columns of at least 256 above
+    static const int l1max = [] {
+        const char* e = std::getenv("HANK_FFT_L1MAX");
+        return e ? std::max(8, std::min(13, std::atoi(e))) : 13;
+    }();
+    int l2 = (lg <= 16) ? lg / 2 : std::min(10, std::max(8, lg - l1max));
     int l1 = lg - l2;
     L1 = int32_t(1) << l1;
     L2 = int32_t(1) << l2;
