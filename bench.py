@@ -222,6 +222,7 @@ def main():
         import oracle
         nthreads = oracle.default_threads()
         probe = inputs.sampled_rows(N, 2 * nthreads, seed=inputs.SEED_SAMPLED_ROWS)[:nthreads]
+        oracle.eval_rows(task, c_host, rows=probe[:1], nthreads=1)  # one-time set-up (roots) off the clock
         t0 = time.perf_counter()
         oracle.eval_rows(task, c_host, rows=probe, nthreads=nthreads)
         tp = time.perf_counter() - t0

@@ -233,13 +233,21 @@ __device__ __forceinline__ double near_z_exact(const GridArgs& G, const NearLane
 }
 
 // J_0 at the lane's current column, then one step on
+// (both branches: each lane takes its own, so a wave pays for both only where
+// its rows straddle z = 20)
 template <int M, bool SMALL, bool ASY, bool PERT>
 __device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, double bn) {
-    double J = 0.0;
-    if (ASY) J = near_asy<M, PERT>(G, r, bn);
-    if (SMALL) {
+    double J;
+    if (SMALL && ASY) {
         const double z = near_z_exact(G, r, bn);
-        if (!ASY || z < J0_ASY_Z) J = j0_small(z);
+        if (z < J0_ASY_Z)
+            J = j0_small(z);
+        else
+            J = near_asy<M, PERT>(G, r, bn);
+    } else if (SMALL) {
+        J = j0_small(near_z_exact(G, r, bn));
+    } else {
+        J = near_asy<M, PERT>(G, r, bn);
     }
     if (ASY) r.u = cmul(r.u, r.w);
     r.Nd += r.dNd;
