@@ -19,7 +19,77 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector peak
+# measured HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
+# a plain copy of known size), valid while the kernel sources are unchanged
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+KERNEL_SOURCES = ["paper_1501_01652_amd/csrc/kernels.hip", "paper_1501_01652_amd/csrc/fft_device.h",
+                  "paper_1501_01652_amd/csrc/device_common.h", "paper_1501_01652_amd/csrc/kernels.h"]
+COPY_BYTES = 1 << 30           # the calibration copy (--only copy)
 METRIC = "DHT0 points/sec at N=2^20, ε=1e-8 vs direct; batched p50/p99 latency"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if there is none or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    if k is None or t.get("source_hash") != kernel_source_hash():
+        return None
+    return 1024.0 * (k["fetch_kib"] * t["fetch_scale"] + k["write_kib"] * t["write_scale"])
+
+
+def run_copy(torch):
+    """A plain device copy of COPY_BYTES, to calibrate the HBM byte counters."""
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"copy_bytes": COPY_BYTES, "copies": 3}
+
+
+def write_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, command):
+    """Build TRAFFIC_FILE from rocprofv3 --pmc counter collections (csv):
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the headline run and of
+    the calibration copy (--only copy), whose true traffic is COPY_BYTES each way."""
+    import csv
+
+    def per_kernel(path, counter):
+        acc = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"].split("(")[0].split("<")[0].replace("void ", "").replace("hank::", "")
+                acc.setdefault(name.strip(), []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    def copy_kib(path, counter):
+        vals = per_kernel(path, counter)
+        return max(vals.values())  # the copy is the largest dispatch of that run
+
+    fscale = (COPY_BYTES / 1024.0) / copy_kib(copy_fetch_csv, "FETCH_SIZE")
+    wscale = (COPY_BYTES / 1024.0) / copy_kib(copy_write_csv, "WRITE_SIZE")
+    f, w = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    kernels = {k: {"fetch_kib": f[k], "write_kib": w.get(k, 0.0)} for k in f if k.startswith("k_")}
+    out = {"source_hash": kernel_source_hash(), "fetch_scale": fscale, "write_scale": wscale,
+           "command": command, "kernels": kernels}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1, sort_keys=True)
+    return out
 
 
 def parse():
@@ -39,7 +109,9 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=1024, help="requests of the batched workload (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--only", choices=["all", "headline", "batched", "serve"], default="all")
+    ap.add_argument("--only", choices=["all", "headline", "batched", "serve", "copy"], default="all")
+    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write the HBM traffic summary from rocprofv3 counter csv files and exit")
     return ap.parse_args()
 
 
@@ -125,9 +197,14 @@ def run_serve(hank, inputs, torch, seconds, rate, max_batch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU (this build has no multi-GPU path); "
-              "got --gpus %d" % args.gpus, file=sys.stderr)
+        print("bench.py runs on exactly one GPU; runs on several GPUs are not supported "
+              "(got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.write_traffic:
+        cmd = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- python3 bench.py "
+               "--only headline --steps 2 --warmup 1 --no-cpu --no-direct; the same for --only copy")
+        print(json.dumps(write_traffic(*args.write_traffic, command=cmd)))
+        return
     import numpy as np
     import torch
 
@@ -150,6 +227,9 @@ def main():
     if args.only in ("batched", "serve"):
         run_extra()
         print(json.dumps(extra))
+        return
+    if args.only == "copy":
+        print(json.dumps(run_copy(torch)))
         return
 
     task, N, eps = args.task, args.N, args.eps
@@ -199,11 +279,13 @@ def main():
             flops = dom["work"] * NEAR_FLOPS_PER_ENTRY
             ach = flops / (dom["total_ms"] * 1e-3) / 1e12
             roofline = {"kernel": "near", "bound": "alu", "achieved": ach, "peak": FP64_VECTOR_TFLOPS,
-                        "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_TFLOPS, "traffic": None}
+                        "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_TFLOPS,
+                        "traffic": measured_traffic("k_near")}
         else:
             ach = dom["bytes"] / (dom["total_ms"] * 1e-3) / 1e9
             roofline = {"kernel": dom["name"], "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                        "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                        "traffic": measured_traffic("k_" + dom["name"]),
                         "bytes_per_launch": dom["bytes"] / max(1, dom["launches"])}
 
     direct = None
@@ -221,12 +303,17 @@ def main():
     if not args.no_cpu:
         import oracle
         nthreads = oracle.default_threads()
-        probe = inputs.sampled_rows(N, 2 * nthreads, seed=inputs.SEED_SAMPLED_ROWS)[:nthreads]
+        probe = inputs.sampled_rows(N, 4 * nthreads, seed=inputs.SEED_SAMPLED_ROWS)[:3 * nthreads]
         oracle.eval_rows(task, c_host, rows=probe[:1], nthreads=1)  # one-time set-up (roots) off the clock
+        # marginal cost per row from two sample sizes (each call also has a fixed set-up)
         t0 = time.perf_counter()
+        oracle.eval_rows(task, c_host, rows=probe[:nthreads], nthreads=nthreads)
+        t1 = time.perf_counter()
         oracle.eval_rows(task, c_host, rows=probe, nthreads=nthreads)
-        tp = time.perf_counter() - t0
-        nrows = int(max(nthreads, min(N, args.cpu_seconds / max(tp, 1e-6) * len(probe))))
+        t2 = time.perf_counter()
+        per_row = max(((t2 - t1) - (t1 - t0)) / (2 * nthreads), 1e-6)
+        setup = max(0.0, (t1 - t0) - nthreads * per_row)
+        nrows = int(max(nthreads, min(N, (args.cpu_seconds - setup) / per_row)))
         rows = np.sort(np.random.default_rng(inputs.SEED_SAMPLED_ROWS).choice(
             np.arange(1, N + 1), size=nrows, replace=False))
         t0 = time.perf_counter()

@@ -658,7 +658,7 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
                     FarDesc& D = descs[di];
                     const int64_t items = int64_t(D.nrhs) * D.nchunk;
                     D.wg_ac = Ln.nac;
-                    Ln.nac += items * (D.A.L1 / 8);
+                    Ln.nac += items * (D.A.L1 / col_width(D.A.L2));
                     D.wg_b = Ln.nb;
                     Ln.nb += items * ((D.A.L2 + rows - 1) / rows);
                     D.wg_r = Ln.nr;
@@ -697,6 +697,7 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
 
     // ---------- launches ----------
     hipEvent_t ev;
+    const int32_t nprob = int32_t(probs.size());
     if (ntiles1 > 0) {
         if ((st = prof_begin(ev, s))) return st;
         HIP_TRY(launch_near(dprobs, nsingle, ntiles1, dpart, s));
@@ -704,11 +705,11 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
     }
     if (ntilesm > 0) {
         if ((st = prof_begin(ev, s))) return st;
-        HIP_TRY(launch_near_multi(dprobs + nsingle, int32_t(probs.size()) - nsingle, ntilesm, dpart, s));
+        HIP_TRY(launch_near_multi(dprobs + nsingle, nprob - nsingle, ntilesm, dpart, s));
         if ((st = prof_end(K_NEAR_MULTI, ev, 0.0, multi_entries, s))) return st;
     }
     if ((st = prof_begin(ev, s))) return st;
-    HIP_TRY(launch_near_reduce(dprobs, int32_t(probs.size()), nrts, dpart, s));
+    HIP_TRY(launch_near_reduce(dprobs, nprob, nrts, dpart, s));
     if ((st = prof_end(K_NEAR_REDUCE, ev, 8.0 * double(pbase), 0.0, s))) return st;
 
     const FarDesc* ddesc = static_cast<const FarDesc*>(g_ex.descs.p);

@@ -519,7 +519,7 @@ constexpr int col_stride() {
 }
 
 // (descriptor, workgroup within its item, right-hand side, group chunk) of
-// this workgroup.  which: 0 column passes (L1/8 workgroups per item),
+// this workgroup.  which: 0 column passes (L1/col_width(L2) workgroups per item),
 // 1 pass B (per_b workgroups per item), 2 chunk reduction (ceil(nrows/256)
 // per right-hand side).
 struct FarItem {
@@ -534,7 +534,7 @@ __device__ __forceinline__ FarItem far_item(const FarDesc* __restrict__ descs, i
     if (which == 0) {
         it.desc = find_desc<FarDesc, &FarDesc::wg_ac>(descs, ndesc, bid);
         local = bid - descs[it.desc].wg_ac;
-        per = descs[it.desc].A.L1 / 8;
+        per = descs[it.desc].A.L1 / col_width(descs[it.desc].A.L2);
     } else if (which == 1) {
         it.desc = find_desc<FarDesc, &FarDesc::wg_b>(descs, ndesc, bid);
         local = bid - descs[it.desc].wg_b;
@@ -912,7 +912,7 @@ hipError_t launch_near_reduce(const NearProb* probs, int32_t nprob, int64_t nrt,
 template <typename F, int L2>
 static void pass_ac_dispatch(int which, const FarArgs* A, const FarDesc* descs, int ndesc, int64_t nwg, void* buf,
                              hipStream_t s) {
-    constexpr int W = 8;
+    constexpr int W = col_width(L2);
     dim3 block(W * L2 / 8);
     if (which == 0)
         hipLaunchKernelGGL((k_pass_a<F, L2, W>), dim3((unsigned)nwg), block, 0, s, descs, ndesc);
