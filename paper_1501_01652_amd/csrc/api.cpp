@@ -186,18 +186,41 @@ size_t group_batch(size_t bytes_per_group, size_t ngroups) {
     return std::min(gb, std::max<size_t>(1, ngroups));
 }
 
-// Branches and Hankel term count of a near-field tile from bounds on z over it:
-// z >= z~ (the perturbations e_k, b_n are non-negative) and z <= z~ + 0.25.
-int32_t near_flags(const Grid& g, const NearTile& t) {
-    const double zlo = g.ztilde(t.k0, t.n0);
-    const double zhi = g.ztilde(t.k0 + t.nk - 1, t.n1 - 1) + 0.25;
-    int32_t f = 0;
-    if (zlo < J0_ASY_Z) f |= 1;
-    if (zhi >= J0_ASY_Z) f |= 2;
-    const double za = std::max(zlo, J0_ASY_Z);
-    const int M = za < 28.0 ? 12 : za < 44.0 ? 8 : za < 65.0 ? 6 : za < 123.0 ? 5 : za < 376.0 ? 4 : 3;
-    return f | (M << 8);
+// Per-block kernel variants of the near field.  The near field's share of the
+// error budget is eps/8 per entry (the far blocks take eps/2), so a block
+// whose smallest z is at least s_{0,M}(eps/8) (Sec. 3.1, eq. (errorBound))
+// needs only M Hankel pairs; below z = 20 the tabulated Taylor pieces are
+// used whatever eps.  Direct mode keeps the full-accuracy rule (1e-17).
+struct NearRule {
+    double zM[6]; // s_{0,M} for M = 2, 3, 4, 6, 8, 12
+    bool mix6;    // 6 pairs suffice at z = 20
+};
+
+NearRule near_rule(const Plan& p) {
+    const double e = p.direct ? 1e-17 : p.eps / 8.0;
+    const int Ms[6] = {2, 3, 4, 6, 8, 12};
+    NearRule r{};
+    for (int i = 0; i < 6; ++i) r.zM[i] = param_s(0, Ms[i], e);
+    r.mix6 = r.zM[3] <= J0_ASY_Z;
+    return r;
 }
+
+// Variant of the block of columns [n0, n1] of rows [k0, k1], from bounds on z
+// over it: z >= z~ (the perturbations e_k, b_n are non-negative) and
+// z <= z~ + 0.25.
+int near_block_variant(const Grid& g, const NearRule& r, int64_t k0, int64_t k1, int64_t n0, int64_t n1) {
+    const double zlo = g.ztilde(k0, n0), zhi = g.ztilde(k1, n1) + 0.25;
+    if (!(zhi >= J0_ASY_Z)) return NV_SMALL;
+    if (zlo < J0_ASY_Z) return r.mix6 ? NV_MIX6 : NV_MIX12;
+    const int codes[6] = {NV_M2, NV_M3, NV_M4, NV_M6, NV_M8, NV_M12};
+    for (int i = 0; i < 6; ++i)
+        if (r.zM[i] <= zlo) return codes[i];
+    return NV_M12;
+}
+
+// relative cost per entry of each variant (VALU operations, measured from the
+// compiled loops)
+constexpr double NV_COST[NV_COUNT] = {0.9, 1.9, 1.7, 0.85, 0.9, 1.0, 1.1, 1.2, 1.35};
 
 hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
     const Plan& p = dp.plan;
@@ -219,6 +242,7 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
     std::vector<NearTile>& tiles = dp.tiles;
     std::vector<RowTile>& rts = dp.rts;
     const int64_t chunk = near_chunk(p.near);
+    const NearRule rule = near_rule(p);
     for (auto& seg : p.near)
         for (int64_t k = seg.k0; k < seg.k1; k += 64) {
             RowTile r{};
@@ -231,32 +255,21 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
                 t.nk = r.nk;
                 t.n0 = n;
                 t.n1 = std::min(seg.ncut, n + chunk);
-                t.flags = near_flags(g, t);
+                for (int64_t nb = t.n0, b = 0; nb < t.n1; nb += 64, ++b) {
+                    const int v = near_block_variant(g, rule, t.k0, t.k0 + t.nk - 1, nb, std::min(nb + 63, t.n1 - 1));
+                    t.bvar[b >> 3] |= uint32_t(v) << (4 * (b & 7));
+                }
                 t.slot = int64_t(tiles.size());
                 tiles.push_back(t);
             }
             r.ntiles = int64_t(tiles.size()) - r.slot0;
             rts.push_back(r);
         }
-    // relative cost of a tile: its 64-column blocks priced by the variant the
-    // kernel picks for each (the same bounds on z as there)
+    // relative cost of a tile: its 64-column blocks priced by their variant
     auto tile_cost = [&](const NearTile& T) {
-        static const double w[5] = {0.8, 2.0, 1.0, 1.1, 1.45};
-        const double Klo = double(g.ar * T.k0 + g.br), Khi = double(g.ar * (T.k0 + T.nk - 1) + g.br);
-        const double piD = M_PI / double(g.D);
         double c = 0;
-        for (int64_t nb = T.n0; nb < T.n1; nb += 64) {
-            const int64_t nl = std::min(nb + 63, T.n1 - 1);
-            const double zlo = Klo * double(g.ac * nb + g.bc) * piD, zhi = Khi * double(g.ac * nl + g.bc) * piD + 0.25;
-            int v;
-            if (!(zhi >= J0_ASY_Z))
-                v = 0;
-            else if (zlo < J0_ASY_Z)
-                v = 1;
-            else
-                v = zlo < 44.0 ? 4 : zlo < 123.0 ? 3 : 2;
-            c += double(nl - nb + 1) * w[v];
-        }
+        for (int64_t nb = T.n0, b = 0; nb < T.n1; nb += 64, ++b)
+            c += double(std::min<int64_t>(64, T.n1 - nb)) * NV_COST[(T.bvar[b >> 3] >> (4 * (b & 7))) & 15];
         return c;
     };
     std::stable_sort(tiles.begin(), tiles.end(),

@@ -27,14 +27,21 @@ struct GridArgs {
 // columns of one near-field tile (its coefficients are staged in LDS)
 constexpr int NEAR_TILE_COLS = 2048;
 
+// Near-field kernel variant of a block of 64 columns of a tile, chosen on
+// the host from bounds on z over the block and the near field's share of the
+// error budget: NV_SMALL only z < 20 (tabulated Taylor pieces), NV_MIX* both
+// branches (each lane takes its own; the Hankel side with 12 or 6 pairs),
+// NV_M* only z >= 20 with 2..12 Hankel pairs.
+enum NearVariant { NV_SMALL = 0, NV_MIX12, NV_MIX6, NV_M2, NV_M3, NV_M4, NV_M6, NV_M8, NV_M12, NV_COUNT };
+
 // near-field work item of a plan: rows [k0, k0+nk) x columns [n0, n1).  Its
 // partial sums (nrhs x 64) sit in slot `slot` of the transform's partial
-// area.  flags: bit 0 some entry has z < 20, bit 1 some entry has z >= 20,
-// bits 8.. Hankel pairs needed for the smallest z >= 20 of the tile
-// (remainder below 1e-17)
+// area.  bvar: the variant of column block b (columns n0 + 64b ...) in bits
+// 4(b%8).. of bvar[b/8].
 struct NearTile {
     int64_t k0, n0, n1, slot;
-    int32_t nk, flags;
+    int32_t nk, pad;
+    uint32_t bvar[4];
 };
 
 // rows [k0, k0+nk) of a plan own the partial slots [slot0, slot0+ntiles)
@@ -60,21 +67,6 @@ struct NearProb {
     int64_t ldc, ldo, tile_start, rt_start, pbase;
     int32_t nrhs, pad;
 };
-
-// Near-field kernel variant of a tile from its flags: 0 only z < 20,
-// 1 both branches (12 Hankel pairs), 2..7 only z >= 20 with M = 3, 4, 5, 6, 8, 12.
-__host__ __device__ inline int near_variant(int32_t flags) {
-    if (!(flags & 2)) return 0;
-    if (flags & 1) return 1;
-    switch (flags >> 8) {
-    case 3: return 2;
-    case 4: return 3;
-    case 5: return 4;
-    case 6: return 5;
-    case 8: return 6;
-    default: return 7;
-    }
-}
 
 struct GroupDev {
     int32_t a, e, t0, t1;

@@ -255,12 +255,14 @@ __device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, doub
 }
 
 // Build knobs (measured variants): unroll of the near-field column loop, and
-// a lower bound on waves per SIMD for k_near (0: the compiler's choice).
+// a lower bound on waves per SIMD for k_near (0: the compiler's choice; 3
+// keeps it below 168 registers at the price of a small spill, which measured
+// faster than 2 waves without).
 #ifndef HANK_NEAR_UNROLL
 #define HANK_NEAR_UNROLL 2
 #endif
 #ifndef HANK_NEAR_WPE
-#define HANK_NEAR_WPE 0
+#define HANK_NEAR_WPE 3
 #endif
 #define HANK_STR2(x) #x
 #define HANK_PRAGMA(x) _Pragma(HANK_STR2(x))
@@ -269,16 +271,10 @@ struct alignas(16) ColCB {
     double c, b;
 };
 
-// Kernel variant of the block of columns [nlo, nhi] of a tile with rows of
-// K from Klo to Khi, from bounds on z over it (z~ <= z <= z~ + 0.25), so that
-// only blocks that straddle z = 20 pay for both branches: 0 only z < 20,
-// 1 both branches, 2..4 Hankel with M = 4, 6, 12 pairs (remainder below
-// 1e-17 for z >= 123, 44, 20).
-__device__ __forceinline__ int block_variant(const GridArgs& G, double Klo, double Khi, double Nlo, double Nhi) {
-    const double zlo = Klo * Nlo * G.piD_hi, zhi = Khi * Nhi * G.piD_hi + 0.25;
-    if (!(zhi >= J0_ASY_Z)) return 0;
-    if (zlo < J0_ASY_Z) return 1;
-    return zlo < 44.0 ? 4 : zlo < 123.0 ? 3 : 2;
+// variant (NearVariant) of the 64-column block starting at column nb of tile T
+__device__ __forceinline__ int tile_block_variant(const NearTile& T, int64_t nb) {
+    const int b = (int)((nb - T.n0) >> 6);
+    return (int)((T.bvar[b >> 3] >> (4 * (b & 7))) & 15u);
 }
 
 // One 64-column block of a sweep: the lane's columns p[0], p[4], ... (cnt of them)
@@ -299,20 +295,21 @@ __device__ __forceinline__ void near_block(const GridArgs& G, const ColCB* p, in
 template <bool PERT>
 __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb, const NearTile& T, int64_t n,
                                              NearLane& r) {
-    const double Klo = (double)(G.ar * T.k0 + G.br), Khi = (double)(G.ar * (T.k0 + T.nk - 1) + G.br);
     double acc = 0.0;
     for (int64_t nb = T.n0; nb < T.n1; nb += 64) {
-        const int64_t nlast = min(nb + 63, T.n1 - 1);
-        const int v = block_variant(G, Klo, Khi, (double)(G.ac * nb + G.bc), (double)(G.ac * nlast + G.bc));
         const int64_t nw = n + (nb - T.n0);
         const int cnt = (int)min<int64_t>(16, (T.n1 - nw + 3) / 4);
         const ColCB* p = cb + (nw - T.n0);
 #define BLOCK(M_, S_, A_) near_block<M_, S_, A_, PERT>(G, p, cnt, r, acc); break
-        switch (v) {
-        case 0: BLOCK(3, true, false);
-        case 1: BLOCK(12, true, true);
-        case 2: BLOCK(4, false, true);
-        case 3: BLOCK(6, false, true);
+        switch (tile_block_variant(T, nb)) {
+        case NV_SMALL: BLOCK(3, true, false);
+        case NV_MIX12: BLOCK(12, true, true);
+        case NV_MIX6: BLOCK(6, true, true);
+        case NV_M2: BLOCK(2, false, true);
+        case NV_M3: BLOCK(3, false, true);
+        case NV_M4: BLOCK(4, false, true);
+        case NV_M6: BLOCK(6, false, true);
+        case NV_M8: BLOCK(8, false, true);
         default: BLOCK(12, false, true);
         }
 #undef BLOCK
@@ -419,7 +416,6 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
     const int nblk = (nr + 15) >> 4;
     const int row = 16 * wave + (lane & 15), kq = lane >> 4;
     NearLane R = near_lane(G, P.e, T, row, T.n0 + kq);
-    const double Klo = (double)(G.ar * T.k0 + G.br), Khi = (double)(G.ar * (T.k0 + T.nk - 1) + G.br);
     v4d acc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -435,14 +431,16 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
             if (PERT && t < 64) Bs[t] = n < T.n1 ? P.b[n - 1] : 0.0;
         }
         __syncthreads();
-        const int64_t nlast = min(nb + 63, T.n1 - 1);
-        const int v = block_variant(G, Klo, Khi, (double)(G.ac * nb + G.bc), (double)(G.ac * nlast + G.bc));
 #define BLOCK(M_, S_, A_) near_multi_block<M_, S_, A_, PERT>(G, R, Cs, Bs, nb, T.n1, kq, lane, nblk, acc); break
-        switch (v) {
-        case 0: BLOCK(3, true, false);
-        case 1: BLOCK(12, true, true);
-        case 2: BLOCK(4, false, true);
-        case 3: BLOCK(6, false, true);
+        switch (tile_block_variant(T, nb)) {
+        case NV_SMALL: BLOCK(3, true, false);
+        case NV_MIX12: BLOCK(12, true, true);
+        case NV_MIX6: BLOCK(6, true, true);
+        case NV_M2: BLOCK(2, false, true);
+        case NV_M3: BLOCK(3, false, true);
+        case NV_M4: BLOCK(4, false, true);
+        case NV_M6: BLOCK(6, false, true);
+        case NV_M8: BLOCK(8, false, true);
         default: BLOCK(12, false, true);
         }
 #undef BLOCK
