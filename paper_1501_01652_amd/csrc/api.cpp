@@ -798,6 +798,7 @@ struct hank_server {
         double done = -1;
         int32_t state = 0;
         int64_t bytes = 0;
+        double est = 0; // modelled GPU seconds (the planner's cost model)
     };
     struct Batch {
         std::vector<int64_t> tickets;
@@ -806,6 +807,11 @@ struct hank_server {
     };
     int64_t budget = 0, max_pending = 0;
     int32_t max_batch = 1;
+    // modelled GPU time per batch (HANK_SERVE_SLICE_MS, default 4 ms)
+    double slice_s = [] {
+        const char* e = std::getenv("HANK_SERVE_SLICE_MS");
+        return (e ? std::atof(e) : 4.0) * 1e-3;
+    }();
     hipStream_t stream = nullptr;
     int device = 0;
     std::mutex mu;
@@ -863,12 +869,17 @@ struct hank_server {
             if (inflight.size() < 2 && !waiting.empty()) {
                 Batch b;
                 std::vector<hank_request> reqs;
+                double est = 0;
                 while (!waiting.empty() && int32_t(b.tickets.size()) < max_batch) {
                     Rec& r = recs[size_t(waiting.front())];
                     if (!b.tickets.empty() && inflight_bytes + b.bytes + r.bytes > budget) break;
+                    // a batch holds about one time slice of modelled work, so that
+                    // large transforms run alone and small ones share launches
+                    if (!b.tickets.empty() && est + r.est > slice_s) break;
                     if (b.tickets.empty() && inflight_bytes > 0 && inflight_bytes + r.bytes > budget) break;
                     b.tickets.push_back(waiting.front());
                     b.bytes += r.bytes;
+                    est += r.est;
                     r.state = 1;
                     reqs.push_back(r.req);
                     waiting.pop_front();
@@ -947,6 +958,7 @@ hank_status hank_server_submit(hank_server* srv, const hank_request* r, double a
     hank_status st = check_args(r->task, r->c, r->N, r->nrhs, r->ldc, r->eps, r->out, r->ldo);
     if (st) return st;
     int64_t bytes = 0;
+    double est = 0;
     {
         std::lock_guard<std::recursive_mutex> lk(g_mu);
         hank_options o{};
@@ -954,11 +966,13 @@ hank_status hank_server_submit(hank_server* srv, const hank_request* r, double a
         DevPlan* dp = nullptr;
         if ((st = get_plan(r->task, r->N, r->eps, &o, srv->stream, dp, r->nrhs))) return st;
         bytes = request_bytes(*dp, r->nrhs);
+        est = dp->plan.cost * double(r->nrhs) / double(std::max<int64_t>(1, dp->plan.nrhs));
     }
     std::lock_guard<std::mutex> lk(srv->mu);
     hank_server::Rec rec;
     rec.req = *r;
     rec.bytes = bytes;
+    rec.est = est;
     rec.arrival = (arrival_s < 0 && srv->started) ? srv->now() : std::max(0.0, arrival_s);
     *ticket = int64_t(srv->recs.size());
     srv->recs.push_back(rec);
