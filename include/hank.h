@@ -199,6 +199,9 @@ typedef struct {
     double fft_bytes;      /* algorithmic bytes of the far-field passes             */
     int32_t first_direct;  /* columns (FB) or rows (DHT) summed directly, paper rule */
     int32_t bulk_fp32;     /* 1 if the transform bulk runs in FP32                  */
+    int32_t fp32_transforms; /* transforms run in FP32 (all with bulk_fp32; with an
+                              FP64 bulk, those whose contribution is small enough
+                              that FP32 rounding stays within eps/8)            */
 } hank_plan_summary;
 
 hank_status hank_plan_info(int32_t task, int64_t N, double eps, const hank_options* options,

@@ -49,7 +49,8 @@ class PlanSummary(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("near_entries", ctypes.c_int64), ("far_transforms", ctypes.c_int64),
                 ("fft_points", ctypes.c_int64), ("fft_bytes", ctypes.c_double),
-                ("first_direct", ctypes.c_int32), ("bulk_fp32", ctypes.c_int32)]
+                ("first_direct", ctypes.c_int32), ("bulk_fp32", ctypes.c_int32),
+                ("fp32_transforms", ctypes.c_int32)]
 
 
 class BlockInfo(ctypes.Structure):

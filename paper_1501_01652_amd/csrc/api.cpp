@@ -68,7 +68,8 @@ int64_t near_chunk(const std::vector<NearSeg>& segs) {
 struct DevBlock {
     Block hb;
     FarArgs args{};
-    void* H = nullptr;
+    void* H = nullptr;   // chirp spectrum for the FP64 groups [0, g64)
+    void* H32 = nullptr; // and for the FP32 groups [g64, ngroups)
     GroupDev* groups = nullptr;
     TermDev* terms = nullptr;
 };
@@ -101,6 +102,7 @@ struct DevPlan {
         fr(d_rts);
         for (auto& d : blocks) {
             fr(d.H);
+            fr(d.H32);
             fr(d.groups);
             fr(d.terms);
         }
@@ -282,11 +284,10 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
         HIP_TRY(hipMemcpyAsync(dp.d_rts, rts.data(), rts.size() * sizeof(RowTile), hipMemcpyHostToDevice, s));
 
     // far-field blocks (the scratch only holds one chirp kernel at a time)
-    const size_t esz = p.fp32 ? 8 : 16;
     size_t work_elems = 0;
     for (auto& hb : p.blocks) work_elems = std::max(work_elems, size_t(hb.L));
     if (!p.blocks.empty())
-        if ((st = dev_alloc(reinterpret_cast<char*&>(dp.work), work_elems * esz, dp.bytes))) return st;
+        if ((st = dev_alloc(reinterpret_cast<char*&>(dp.work), work_elems * 16, dp.bytes))) return st;
     std::vector<std::vector<GroupDev>> hg(p.blocks.size());
     std::vector<std::vector<TermDev>> ht(p.blocks.size());
     dp.blocks.resize(p.blocks.size());
@@ -300,7 +301,9 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
         if ((st = dev_alloc(d.terms, ht[i].size(), dp.bytes))) return st;
         HIP_TRY(hipMemcpyAsync(d.groups, hg[i].data(), hg[i].size() * sizeof(GroupDev), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(d.terms, ht[i].data(), ht[i].size() * sizeof(TermDev), hipMemcpyHostToDevice, s));
-        if ((st = dev_alloc(reinterpret_cast<char*&>(d.H), size_t(hb.L) * esz, dp.bytes))) return st;
+        const bool any64 = hb.g64 > 0, any32 = hb.g64 < int32_t(hb.groups.size());
+        if (any64 && (st = dev_alloc(reinterpret_cast<char*&>(d.H), size_t(hb.L) * 16, dp.bytes))) return st;
+        if (any32 && (st = dev_alloc(reinterpret_cast<char*&>(d.H32), size_t(hb.L) * 8, dp.bytes))) return st;
         FarArgs& A = d.args;
         A.ka = hb.ka;
         A.na = hb.na;
@@ -334,7 +337,8 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
         A.col_pert = g.col_pert;
         A.groups = d.groups;
         A.terms = d.terms;
-        HIP_TRY(launch_chirp_spectrum(A, p.fp32, dp.work, d.H, s));
+        if (any64) HIP_TRY(launch_chirp_spectrum(A, false, dp.work, d.H, s));
+        if (any32) HIP_TRY(launch_chirp_spectrum(A, true, dp.work, d.H32, s));
     }
     // the host vectors above must outlive the asynchronous copies
     HIP_TRY(hipStreamSynchronize(s));
@@ -583,6 +587,7 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
         struct Item {
             size_t job;
             int32_t g0, g1;
+            bool f32;
         };
         std::vector<std::vector<Item>> sub(1);
         std::vector<size_t> subbytes(1, 0);
@@ -590,24 +595,33 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
             Job& J = jobs[ji];
             if (bi >= J.dp->blocks.size()) continue;
             const DevBlock& d = J.dp->blocks[bi];
-            const size_t per_group = size_t(d.args.L) * (J.dp->plan.fp32 ? 8 : 16) * size_t(J.nrhs);
-            size_t gb = std::max<size_t>(1, std::min<size_t>(size_t(d.args.ngroups), budget / per_group));
-            gb = std::min(gb, group_batch(size_t(d.args.L) * (J.dp->plan.fp32 ? 8 : 16), size_t(d.args.ngroups)));
-            int si = 0;
-            for (int32_t g0 = 0; g0 < d.args.ngroups; g0 += int32_t(gb), ++si) {
-                const int32_t g1 = std::min(d.args.ngroups, g0 + int32_t(gb));
-                const size_t need = per_group * size_t(g1 - g0);
-                // group batches of one block go to successive sub-waves
-                size_t k = size_t(si);
-                while (k < sub.size() && subbytes[k] + need > budget && subbytes[k] > 0) ++k;
-                if (k >= sub.size()) {
-                    sub.emplace_back();
-                    subbytes.push_back(0);
-                    k = sub.size() - 1;
+            // the FP64 groups [0, g64) and the FP32 groups [g64, ngroups)
+            const int32_t g64 = d.hb.g64, ng = d.args.ngroups;
+            const int32_t lo[2] = {0, g64}, hi[2] = {g64, ng};
+            for (int pr = 0; pr < 2; ++pr) {
+                if (hi[pr] <= lo[pr]) continue;
+                const size_t esz = pr ? 8 : 16;
+                const int32_t cnt = hi[pr] - lo[pr];
+                const size_t per_group = size_t(d.args.L) * esz * size_t(J.nrhs);
+                size_t gb = std::max<size_t>(1, std::min<size_t>(size_t(cnt), budget / per_group));
+                gb = std::min(gb, group_batch(size_t(d.args.L) * esz, size_t(cnt)));
+                int si = 0;
+                for (int32_t g0 = lo[pr]; g0 < hi[pr]; g0 += int32_t(gb), ++si) {
+                    const int32_t g1 = std::min(hi[pr], g0 + int32_t(gb));
+                    const size_t need = per_group * size_t(g1 - g0);
+                    // group batches of one block and precision go to successive
+                    // sub-waves (each pass C adds into f)
+                    size_t k = size_t(si);
+                    while (k < sub.size() && subbytes[k] + need > budget && subbytes[k] > 0) ++k;
+                    if (k >= sub.size()) {
+                        sub.emplace_back();
+                        subbytes.push_back(0);
+                        k = sub.size() - 1;
+                    }
+                    sub[k].push_back(Item{ji, g0, g1, pr == 1});
+                    subbytes[k] += need;
+                    si = int(k);
                 }
-                sub[k].push_back(Item{ji, g0, g1});
-                subbytes[k] += need;
-                si = int(k);
             }
         }
         for (size_t k = 0; k < sub.size(); ++k) {
@@ -617,7 +631,7 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
             for (auto& it : sub[k]) {
                 const Job& J = jobs[it.job];
                 const DevBlock& d = J.dp->blocks[bi];
-                shapes[{J.dp->plan.fp32, d.args.L1, d.args.L2}].push_back(it);
+                shapes[{it.f32, d.args.L1, d.args.L2}].push_back(it);
             }
             size_t off = 0; // bytes within the work buffer for this sub-wave
             for (auto& kv : shapes) {
@@ -638,7 +652,7 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
                     D.b = J.dp->b;
                     D.e = J.dp->e;
                     D.f = J.f;
-                    D.H = d.H;
+                    D.H = it.f32 ? d.H32 : d.H;
                     D.ldc = J.ldc;
                     D.ldo = J.ldo;
                     D.nrhs = int32_t(J.nrhs);
@@ -779,9 +793,11 @@ hank_status transform(int32_t task, const double* c, int64_t N, int64_t nrhs, in
 // Device bytes a request occupies while in flight: the far-field workspace
 // of its largest block plus its near-field partials.
 int64_t request_bytes(const DevPlan& dp, int64_t nrhs) {
-    const double esz = dp.plan.fp32 ? 8.0 : 16.0;
     double far = 0;
-    for (auto& b : dp.blocks) far = std::max(far, double(b.args.L) * double(b.args.ngroups) * esz * double(nrhs));
+    for (auto& b : dp.blocks) {
+        const double per = 16.0 * double(b.hb.g64) + 8.0 * double(b.args.ngroups - b.hb.g64);
+        far = std::max(far, double(b.args.L) * per * double(nrhs));
+    }
     return int64_t(far + double(dp.tiles.size()) * 64.0 * 8.0 * double(nrhs));
 }
 
@@ -1245,11 +1261,12 @@ hank_status hank_plan_info(int32_t task, int64_t N, double eps, const hank_optio
     s.near_entries = p.near_entries;
     s.first_direct = p.first_direct;
     s.bulk_fp32 = p.fp32;
-    const double esz = p.fp32 ? 8.0 : 16.0;
     for (auto& b : p.blocks) {
+        const int64_t g32 = int64_t(b.groups.size()) - b.g64;
         s.far_transforms += int64_t(b.groups.size());
+        s.fp32_transforms += int32_t(g32);
         s.fft_points += int64_t(b.groups.size()) * b.L;
-        s.fft_bytes += double(b.groups.size()) * double(b.L) * esz * 4.0;
+        s.fft_bytes += (16.0 * double(b.g64) + 8.0 * double(g32)) * double(b.L) * 4.0;
     }
     *out = s;
     return HANK_OK;

@@ -472,8 +472,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         near_multi_body<false>(P, T, Cs, Bs, out);
 }
 
-// f_k = sum of the row's tile partials, per right-hand side; 4 waves take
-// every 4th tile and their sums are combined in a fixed order.
+// f_k = sum of the row's tile partials, per right-hand side.  One right-hand
+// side: 4 waves take every 4th tile and their sums are combined in a fixed
+// order; several: wave w sums right-hand sides w, w+4, ... over the tiles in
+// order.
 __global__ __launch_bounds__(256) void k_near_reduce(const NearProb* __restrict__ probs, int nprob,
                                                      const double* __restrict__ partial) {
     __shared__ double red[4][64];
@@ -482,6 +484,15 @@ __global__ __launch_bounds__(256) void k_near_reduce(const NearProb* __restrict_
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t per_tile = (int64_t)P.nrhs * 64;
     const double* base = partial + P.pbase + R.slot0 * per_tile;
+    if (P.nrhs > 1) {
+        for (int j = wave; j < P.nrhs; j += 4) {
+            const double* q = base + (int64_t)j * 64 + lane;
+            double s = 0.0;
+            for (int64_t t = 0; t < R.ntiles; ++t) s += q[t * per_tile];
+            if (lane < R.nk) P.f[(int64_t)j * P.ldo + R.k0 + lane - 1] = s;
+        }
+        return;
+    }
     for (int j = 0; j < P.nrhs; ++j) {
         double s = 0.0;
         for (int64_t t = wave; t < R.ntiles; t += 4) s += base[t * per_tile + (int64_t)j * 64 + lane];

@@ -60,9 +60,18 @@ struct Block {
     double r0, w0, s0;      // r^_ka, w^_na, z~ at the block corner
     double eref, lref, bref;
     int32_t maxa, maxb, maxm; // largest exponents used by its terms
+    int32_t g64 = 0;          // groups [0, g64) in FP64, [g64, end) in FP32
     std::vector<Group> groups;
     std::vector<Term> terms;
 };
+
+// Precision of a block's transforms: bulk 0 all FP64, 2 all FP32, 1 FP32 for
+// the groups whose contribution is too small for FP32 rounding to matter
+// (bound of every entry of the group's matrix relative to |c_n| times
+// 4 log2(L) u_32 at most eps/(8 G)), provided the saving under cost model cm
+// pays for a second set of launches; reorders the groups FP64 first.
+struct CostModel;
+void set_group_precision(const Grid& g, Block& b, double eps, int bulk, const CostModel& cm);
 
 // Rows [k0, k1) sum columns [1, ncut) directly.
 struct NearSeg {
@@ -88,9 +97,9 @@ struct Plan {
 // Cost-model constants (seconds); refined from measurements through the
 // environment (HANK_COST_FFT, HANK_COST_NEAR, HANK_COST_BLOCK).
 struct CostModel {
-    double fft_pt_group64 = 3.0e-11; // per FFT point per group per right-hand side, FP64 bulk (measured)
-    double fft_pt_group32 = 1.7e-11; // same, FP32 bulk
-    double near_entry = 3.2e-12;     // per directly summed entry, one right-hand side (measured)
+    double fft_pt_group64 = 3.3e-11; // per FFT point per group per right-hand side, FP64 (measured)
+    double fft_pt_group32 = 1.95e-11; // same, FP32
+    double near_entry = 2.9e-12;     // per directly summed entry, one right-hand side (measured)
     double near_multi_entry = 4.2e-12; // per entry with several right-hand sides (J_0 once per entry)
     double near_rhs = 4.5e-14;       // per entry and right-hand side of the product (FP64 MFMA)
     double block = 20e-6;            // fixed cost per block (three launches)

@@ -334,6 +334,35 @@ bool build_block_terms(const Grid& g, Block& bk, double eps, int mode, int Mpape
     return true;
 }
 
+void set_group_precision(const Grid& g, Block& bk, double eps, int bulk, const CostModel& cm) {
+    const int G = int(bk.groups.size());
+    if (bulk != 1) {
+        bk.g64 = bulk == 2 ? 0 : G;
+        return;
+    }
+    int lg = 0;
+    while ((int64_t(1) << lg) < bk.L) ++lg;
+    const double u32 = 5.9604644775390625e-8; // 2^-24
+    const double limit = eps / (8.0 * double(std::max(G, 1))) / (4.0 * double(lg) * u32);
+    const double rmax = g.rhat(bk.kb);
+    std::vector<Group> g64, g32;
+    for (auto& G_ : bk.groups) {
+        // |A_g(k) X_g(n)| <= scale (r^_k/r0)^(e-1/2) sum|K| |c_n|: the other ratios are <= 1
+        double ksum = 0;
+        for (int t = G_.t0; t < G_.t1; ++t) ksum += std::hypot(bk.terms[size_t(t)].kre, bk.terms[size_t(t)].kim);
+        const double rowf = std::max(1.0, std::pow(rmax / bk.r0, double(G_.e) - 0.5));
+        (G_.scale * rowf * ksum <= limit ? g32 : g64).push_back(G_);
+    }
+    const double saving = double(bk.L) * double(g32.size()) * (cm.fft_pt_group64 - cm.fft_pt_group32);
+    if (g32.empty() || (!g64.empty() && saving < cm.block)) {
+        bk.g64 = G;
+        return;
+    }
+    bk.g64 = int32_t(g64.size());
+    bk.groups = g64;
+    bk.groups.insert(bk.groups.end(), g32.begin(), g32.end());
+}
+
 // ---------------------------------------------------------------------------
 // Partition
 // ---------------------------------------------------------------------------
@@ -452,8 +481,11 @@ static bool near_segments(const Grid& g, const std::vector<Block>& blocks, std::
 static double plan_cost(const Plan& p, const CostModel& cm) {
     const double r = double(p.nrhs);
     double c = double(p.near_entries) * (p.nrhs == 1 ? cm.near_entry : cm.near_multi_entry + r * cm.near_rhs);
-    double per = p.fp32 ? cm.fft_pt_group32 : cm.fft_pt_group64;
-    for (auto& b : p.blocks) c += cm.block + double(b.groups.size()) * double(b.L) * per * r;
+    for (auto& b : p.blocks) {
+        const double g64 = double(b.g64), g32 = double(b.groups.size()) - g64;
+        c += cm.block * ((g64 > 0 && g32 > 0) ? 2.0 : 1.0) +
+             double(b.L) * (g64 * cm.fft_pt_group64 + g32 * cm.fft_pt_group32) * r;
+    }
     return c;
 }
 
@@ -511,6 +543,7 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
         for (auto& b : p.blocks) {
             if (!build_block_terms(p.g, b, eps, 1, p.M, p.K, p.T))
                 throw std::runtime_error("paper plan exceeds supported term count");
+            set_group_precision(p.g, b, eps, p.fp32 ? 2 : 0, cm);
             ok.push_back(b);
         }
         p.blocks = ok;
@@ -535,6 +568,7 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
             return it->second.first;
         }
         bool ok = build_block_terms(p.g, b, eps, 0, 0, 0, 0);
+        if (ok) set_group_precision(p.g, b, eps, p.fp32 ? 2 : (precision == 0 ? 1 : 0), cm);
         memo[key] = {ok, b};
         return ok;
     };
