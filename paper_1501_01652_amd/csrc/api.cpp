@@ -685,7 +685,7 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
                     FarDesc& D = descs[di];
                     const int64_t items = int64_t(D.nrhs) * D.nchunk;
                     D.wg_ac = Ln.nac;
-                    Ln.nac += items * (D.A.L1 / col_width(D.A.L2));
+                    Ln.nac += items * (D.A.L1 / col_width(D.A.L2, Ln.fp32));
                     D.wg_b = Ln.nb;
                     Ln.nb += items * ((D.A.L2 + rows - 1) / rows);
                     D.wg_r = Ln.nr;

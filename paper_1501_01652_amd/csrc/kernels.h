@@ -127,12 +127,16 @@ hipError_t launch_near_reduce(const NearProb* probs, int32_t nprob, int64_t nrt,
                               hipStream_t s);
 hipError_t launch_chirp_spectrum(const FarArgs& A, bool fp32, void* work, void* H, hipStream_t s);
 // Columns per workgroup of the column passes (A, C) for column FFTs of L2
-// points: 8 (128-byte row segments), 4 from L2 = 512 up when
-// HANK_COLW_BIG = 4, which halves the workgroup's LDS.
+// points: 128-byte row segments (8 FP64 or 16 FP32 columns) for
+// 64 <= L2 < 512, 8 otherwise (the split keeps L1 >= L2, so L1 >= 8 columns
+// always, >= 16 from L2 = 64); HANK_COLW_BIG = 4 halves the FP64 workgroup's
+// LDS from L2 = 512 on.
 #ifndef HANK_COLW_BIG
 #define HANK_COLW_BIG 8
 #endif
-__host__ __device__ constexpr int col_width(int L2) { return L2 >= 512 ? HANK_COLW_BIG : 8; }
+__host__ __device__ constexpr int col_width(int L2, bool fp32) {
+    return L2 >= 512 ? (fp32 ? 8 : HANK_COLW_BIG) : (fp32 && L2 >= 64 ? 16 : 8);
+}
 
 // which: 0 pass A (inputs + column FFTs), 1 pass B (row FFT x H^ x inverse), 2 pass C (epilogue).
 // All ndesc descriptors of one launch share fp32 and the FFT split (L1, L2);

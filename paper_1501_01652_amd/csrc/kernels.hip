@@ -528,26 +528,23 @@ constexpr int col_stride() {
 }
 
 // (descriptor, workgroup within its item, right-hand side, group chunk) of
-// this workgroup.  which: 0 column passes (L1/col_width(L2) workgroups per item),
-// 1 pass B (per_b workgroups per item), 2 chunk reduction (ceil(nrows/256)
-// per right-hand side).
+// this workgroup.  which: 0 column passes (per workgroups per item), 1 pass B
+// (per workgroups per item), 2 chunk reduction (ceil(nrows/256) per
+// right-hand side).
 struct FarItem {
     int desc, wg, j, chunk;
 };
 
-__device__ __forceinline__ FarItem far_item(const FarDesc* __restrict__ descs, int ndesc, int which, int per_b) {
+__device__ __forceinline__ FarItem far_item(const FarDesc* __restrict__ descs, int ndesc, int which, int per) {
     const int64_t bid = blockIdx.x;
     FarItem it;
     int64_t local;
-    int per;
     if (which == 0) {
         it.desc = find_desc<FarDesc, &FarDesc::wg_ac>(descs, ndesc, bid);
         local = bid - descs[it.desc].wg_ac;
-        per = descs[it.desc].A.L1 / col_width(descs[it.desc].A.L2);
     } else if (which == 1) {
         it.desc = find_desc<FarDesc, &FarDesc::wg_b>(descs, ndesc, bid);
         local = bid - descs[it.desc].wg_b;
-        per = per_b;
     } else {
         it.desc = find_desc<FarDesc, &FarDesc::wg_r>(descs, ndesc, bid);
         local = bid - descs[it.desc].wg_r;
@@ -571,7 +568,7 @@ template <typename F, int L2, int W>
 __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict__ descs, int ndesc) {
     constexpr int R = 8, NTC = L2 / R;
     __shared__ cx<F> sh[W * col_stride<L2>()];
-    const FarItem mp = far_item(descs, ndesc, 0, 0);
+    const FarItem mp = far_item(descs, ndesc, 0, descs[0].A.L1 / W);
     const FarDesc& D = descs[mp.desc];
     const FarArgs& A = D.A;
     const int t = threadIdx.x, w = t % W, tt = t / W;
@@ -785,7 +782,7 @@ template <typename F, int L2, int W>
 __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict__ descs, int ndesc) {
     constexpr int R = 8, NTC = L2 / R;
     __shared__ cx<F> sh[W * col_stride<L2>()];
-    const FarItem mp = far_item(descs, ndesc, 0, 0);
+    const FarItem mp = far_item(descs, ndesc, 0, descs[0].A.L1 / W);
     const FarDesc& D = descs[mp.desc];
     const FarArgs& A = D.A;
     const int t = threadIdx.x, w = t % W, tt = t / W;
@@ -921,7 +918,7 @@ hipError_t launch_near_reduce(const NearProb* probs, int32_t nprob, int64_t nrt,
 template <typename F, int L2>
 static void pass_ac_dispatch(int which, const FarArgs* A, const FarDesc* descs, int ndesc, int64_t nwg, void* buf,
                              hipStream_t s) {
-    constexpr int W = col_width(L2);
+    constexpr int W = col_width(L2, sizeof(F) == 4);
     dim3 block(W * L2 / 8);
     if (which == 0)
         hipLaunchKernelGGL((k_pass_a<F, L2, W>), dim3((unsigned)nwg), block, 0, s, descs, ndesc);

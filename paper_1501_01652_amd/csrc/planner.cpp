@@ -418,6 +418,27 @@ static void push_block(std::vector<Block>& out, int64_t ka, int64_t kb, int64_t 
 
 // The staircase of Fig. 4: a square-ish block Q1 from (k0, n0) plus P row
 // strips and P column strips, each strip's corner on the curve z~ = s.
+// A block whose FFT would exceed MAX_FFT points (8192-point rows x
+// 1024-point columns) is cut into f x f sub-blocks, rows and columns in f
+// nearly equal parts, f the smallest power of two that fits.  The sub-blocks
+// cover the same entries, each with its own corner and terms.
+static const int64_t MAX_FFT = int64_t(1) << 23;
+static void split_large(std::vector<Block>& v) {
+    std::vector<Block> out;
+    for (auto& b : v) {
+        const int64_t R = b.kb - b.ka + 1, C = b.nb - b.na + 1;
+        int64_t f = 1;
+        while ((R + f - 1) / f + (C + f - 1) / f - 1 > MAX_FFT) f *= 2;
+        for (int64_t i = 0; i < f; ++i)
+            for (int64_t j = 0; j < f; ++j) {
+                const int64_t ka = b.ka + i * R / f, kb = b.ka + (i + 1) * R / f - 1;
+                const int64_t na = b.na + j * C / f, nb = b.na + (j + 1) * C / f - 1;
+                if (ka <= kb && na <= nb) push_block(out, ka, kb, na, nb);
+            }
+    }
+    v.swap(out);
+}
+
 static std::vector<Block> staircase(const Grid& g, double s, double R0, double beta, int P,
                                     int64_t kfloor, int64_t nfloor) {
     std::vector<Block> out;
@@ -443,6 +464,7 @@ static std::vector<Block> staircase(const Grid& g, double s, double R0, double b
         if (ka <= N) push_block(out, ka, N, np, nprev - 1);
         nprev = np;
     }
+    split_large(out);
     return out;
 }
 

@@ -108,3 +108,29 @@ def test_dht0_2pow20_deterministic():
     a = host(hank.transform("dht0", c, eps))
     b = host(hank.transform("dht0", c, eps))
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("task,eps", [("schlomilch", 1e-14), ("dht0", 1e-8)])
+def test_largest_size(task, eps):
+    """N = 2^24, the largest N the library accepts: its far blocks are cut so
+    that no FFT exceeds 2^23 points.  Rows: the first and last four, the first
+    and last row of every block and seeded uniform rows."""
+    N = 1 << 24
+    rng = np.random.default_rng(2024)
+    c = rng.uniform(-1.0, 1.0, N)
+    blocks = hank.plan_blocks(task, N, eps)
+    assert max(b["fft_len"] for b in blocks) <= 1 << 23
+    rows = {1, 2, 3, 4, N - 3, N - 2, N - 1, N}
+    for b in blocks:
+        rows |= {b["row0"], b["row1"]}
+    rows |= set(int(k) for k in rng.integers(1, N + 1, 8))
+    check(task, N, eps, c, np.array(sorted(rows), dtype=np.int64), "largest N")
+
+
+def test_beyond_largest_size_is_rejected():
+    import ctypes
+    c = dev(np.zeros(8))
+    n = (1 << 24) + 1
+    st = hank.lib().hank_transform(2, ctypes.c_void_p(c.data_ptr()), n, 1, n, 1e-8,
+                                   ctypes.c_void_p(c.data_ptr() + 32), n, None, None)
+    assert st == 1  # HANK_EINVAL, before any device work
