@@ -259,7 +259,7 @@ __device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, doub
 // keeps it below 168 registers at the price of a small spill, which measured
 // faster than 2 waves without).
 #ifndef HANK_NEAR_UNROLL
-#define HANK_NEAR_UNROLL 2
+#define HANK_NEAR_UNROLL 4
 #endif
 #ifndef HANK_NEAR_WPE
 #define HANK_NEAR_WPE 3
