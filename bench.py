@@ -137,6 +137,16 @@ def run_batched(hank, inputs, torch, count):
         hank.batch(reqs)
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
+    # the same batch captured once as a HIP graph and replayed
+    graph = hank.BatchGraph(reqs)
+    graph.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        graph.launch()
+    torch.cuda.synchronize()
+    tg = (time.perf_counter() - t0) / reps
+    graph.close()
     # one request at a time, same stream, completion stamped by events
     for r in reqs:
         hank.transform(r["task"], r["c"], r["eps"], out=r["out"])
@@ -155,6 +165,7 @@ def run_batched(hank, inputs, torch, count):
             "workload": "task 40/40/20, N log-uniform [2^8, 2^16], 1-64 rhs, eps {1e-4,1e-8,1e-14}, "
                         "c ~ U[-1,1], seed %d" % inputs.SEED_BATCH,
             "batched_transforms_per_s": count / tb, "batched_ms": tb * 1e3,
+            "graph_transforms_per_s": count / tg, "graph_ms": tg * 1e3,
             "batched_latency_p50_ms": tb * 1e3, "batched_latency_p99_ms": tb * 1e3,
             "sequential_transforms_per_s": count / ts, "sequential_ms": ts * 1e3,
             "sequential_latency_p50_ms": pct(0.5), "sequential_latency_p99_ms": pct(0.99),
@@ -248,17 +259,43 @@ def main():
     torch.cuda.synchronize()
 
     hank.profile(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    evs[0].record(stream)
+    for i in range(args.steps):
         hank.transform(task, c, eps, out=out, stream=stream, **kw)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stats = hank.profile_report()
     hank.profile(False)
     ms_per_step = 1e3 * elapsed / args.steps
     value = N * args.steps / elapsed
+    step_ms = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
+    step_q = lambda q: step_ms[min(len(step_ms) - 1, int(q * (len(step_ms) - 1) + 0.5))]
     info = hank.plan_info(task, N, eps, **kw)
+
+    # measured device copy bandwidth (read + write of COPY_BYTES), the
+    # practical HBM ceiling beside the nominal peak
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * COPY_BYTES / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    # the whole plan against HBM: algorithmic bytes of its transforms (one read
+    # and one write per FFT, two FFTs per transform) plus reading c and writing f
+    plan_bytes = info["fft_bytes"] + 16.0 * N
+    plan_gbs = plan_bytes / (step_q(0.5) * 1e-3) / 1e9
+    plan_roofline = {"algorithmic_bytes": plan_bytes, "achieved_GBps": plan_gbs,
+                     "frac_of_peak": plan_gbs / HBM_PEAK_GBS, "frac_of_copy": plan_gbs / copy_gbs,
+                     "copy_GBps": copy_gbs}
 
     kernels = {}
     for s in stats:
@@ -334,6 +371,8 @@ def main():
             "near_entries": info["near_entries"], "far_transforms": info["far_transforms"],
             "plan_build_s": plan_s},
         "roofline": roofline, "cpu_baseline": cpu, "direct_gpu": direct, "kernels": kernels,
+        "step_ms": {"median": step_q(0.5), "p90": step_q(0.9), "min": step_ms[0], "max": step_ms[-1]},
+        "plan_roofline": plan_roofline,
     }
     run_extra()
     line.update(extra)

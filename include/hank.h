@@ -115,6 +115,20 @@ typedef struct {
 
 hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t stream);
 
+/* A batch captured once as a HIP graph and replayed without host work: the
+ * same requests (the same c and out pointers; their contents may change
+ * between launches) on the stream of each launch.  The graph owns its
+ * workspace, so launches of different graphs and ordinary calls do not share
+ * buffers; launches of one graph must not overlap each other.  Plans are built
+ * (on `stream`) at creation; the graph keeps pointers into the plan cache, so
+ * hank_cache_clear fails while graphs exist.  Destroy a graph only after its
+ * last launch has completed.  Errors as for hank_batch (nothing is captured). */
+typedef struct hank_graph hank_graph;
+hank_status hank_batch_graph_create(const hank_request* reqs, int64_t count, hank_stream_t stream,
+                                    hank_graph** out);
+hank_status hank_batch_graph_launch(hank_graph* graph, hank_stream_t stream);
+hank_status hank_batch_graph_destroy(hank_graph* graph);
+
 /* ---- Serving: continuous batching ---------------------------------------------
  * A server owns a worker thread and a stream.  Submitted requests become
  * eligible at their arrival time (seconds after hank_server_start; a negative

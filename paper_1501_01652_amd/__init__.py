@@ -29,7 +29,8 @@ EXPORTS = ["hank_schlomilch", "hank_fourier_bessel", "hank_dht0", "hank_transfor
            "hank_param_neumann", "hank_param_pK", "hank_param_qT", "hank_plan_info",
            "hank_plan_block", "hank_root_offsets", "hank_j0", "hank_profile", "hank_profile_report",
            "hank_server_create", "hank_server_warm", "hank_server_submit", "hank_server_start",
-           "hank_server_drain", "hank_server_status", "hank_server_stats", "hank_server_destroy"]
+           "hank_server_drain", "hank_server_status", "hank_server_stats", "hank_server_destroy",
+           "hank_batch_graph_create", "hank_batch_graph_launch", "hank_batch_graph_destroy"]
 
 
 class HankError(RuntimeError):
@@ -92,6 +93,12 @@ def lib():
             L.hank_transform.argtypes = [i32, p, i64, i64, i64, d, p, i64, ctypes.POINTER(Options), p]
             L.hank_batch.restype = i32
             L.hank_batch.argtypes = [ctypes.POINTER(Request), i64, p]
+            L.hank_batch_graph_create.restype = i32
+            L.hank_batch_graph_create.argtypes = [ctypes.POINTER(Request), i64, p, ctypes.POINTER(p)]
+            L.hank_batch_graph_launch.restype = i32
+            L.hank_batch_graph_launch.argtypes = [p, p]
+            L.hank_batch_graph_destroy.restype = i32
+            L.hank_batch_graph_destroy.argtypes = [p]
             L.hank_last_error.restype = ctypes.c_char_p
             L.hank_last_error.argtypes = []
             L.hank_cache_clear.restype = i32
@@ -204,9 +211,7 @@ def dht0(c, eps: float, out=None, stream=None):
     return out
 
 
-def batch(requests, stream=None):
-    """Submit many transforms at once.  requests: iterable of dicts with keys
-    task, c, out, eps and optionally precision (c, out of shape (N,) or (nrhs, N))."""
+def _requests(requests):
     reqs = list(requests)
     arr = (Request * max(1, len(reqs)))()
     for i, r in enumerate(reqs):
@@ -216,7 +221,43 @@ def batch(requests, stream=None):
         nrhs = 1 if c.dim() == 1 else c.shape[0]
         arr[i] = Request(_task(r["task"]), int(r.get("precision", 0)), N, nrhs, N, N, float(r["eps"]),
                          c.data_ptr(), o.data_ptr())
-    _check(lib().hank_batch(arr, len(reqs), _stream(stream)))
+    return arr, len(reqs)
+
+
+def batch(requests, stream=None):
+    """Submit many transforms at once.  requests: iterable of dicts with keys
+    task, c, out, eps and optionally precision (c, out of shape (N,) or (nrhs, N))."""
+    arr, n = _requests(requests)
+    _check(lib().hank_batch(arr, n, _stream(stream)))
+
+
+class BatchGraph:
+    """A batch captured once as a HIP graph (hank_batch_graph_*): launch()
+    replays the same requests, reading and writing the same tensors, without
+    host work.  Keep the tensors alive while the graph is used."""
+
+    def __init__(self, requests, stream=None):
+        self._reqs = list(requests)  # keeps the tensors referenced
+        arr, n = _requests(self._reqs)
+        h = ctypes.c_void_p()
+        _check(lib().hank_batch_graph_create(arr, n, _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().hank_batch_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            import torch
+            torch.cuda.synchronize()
+            _check(lib().hank_batch_graph_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def plan_info(task, N: int, eps: float, plan_mode: int = 0, precision: int = 0, direct: int = 0,

@@ -399,6 +399,7 @@ struct Pending {
     double bytes, work;
 };
 bool g_prof = false;
+int g_graphs = 0; // live batch graphs (they hold pointers into cached plans)
 std::vector<Pending> g_pending;
 struct Acc {
     int64_t launches = 0;
@@ -520,8 +521,30 @@ int32_t far_chunks(int64_t L, int32_t ngroups, int64_t nrhs) {
     return int32_t(std::max<int64_t>(1, want));
 }
 
-hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
-    hank_status st;
+// A launch set of the far field: descriptors [d0, d1) of one FFT shape and
+// precision; a record with L1 = 0 separates waves.
+struct FarLaunch {
+    bool fp32;
+    int32_t L1, L2;
+    size_t d0, d1;       // descriptors [d0, d1)
+    int64_t nac, nb, nr; // grid sizes of the column passes, pass B and the chunk reduction
+    double bytesA, bytesB, bytesC, bytesR, work;
+};
+
+// Everything the launches of a list of jobs need, built on the host: near
+// descriptors, far descriptors (buf and part as offsets into the work and
+// chunk-sum buffers), launch sets and buffer sizes.
+struct Prepared {
+    std::vector<NearProb> probs;
+    int32_t nsingle = 0;
+    int64_t pbase = 0, ntiles1 = 0, ntilesm = 0, nrts = 0;
+    double near_entries = 0, multi_entries = 0;
+    std::vector<FarDesc> descs;
+    std::vector<FarLaunch> launches;
+    size_t work_need = 0, part_need = 0;
+};
+
+void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR) {
     // the near-field kernels take at most 64 right-hand sides: split wider jobs
     std::vector<Job> jobs;
     for (const Job& J : jobs_in)
@@ -532,15 +555,13 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
             P.nrhs = std::min<int64_t>(64, J.nrhs - j0);
             jobs.push_back(P);
         }
-    if (!g_ex.done) HIP_TRY(hipEventCreateWithFlags(&g_ex.done, hipEventDisableTiming));
-    if (g_ex.used && g_ex.last != s) HIP_TRY(hipStreamWaitEvent(s, g_ex.done, 0));
 
     // ---------- near field descriptors: single right-hand side jobs first ----------
     std::stable_partition(jobs.begin(), jobs.end(), [](const Job& J) { return J.nrhs == 1; });
-    std::vector<NearProb> probs;
-    int32_t nsingle = 0;
-    int64_t pbase = 0, ntiles1 = 0, ntilesm = 0, nrts = 0;
-    double near_entries = 0, multi_entries = 0;
+    auto& probs = PR.probs;
+    int32_t& nsingle = PR.nsingle;
+    int64_t &pbase = PR.pbase, &ntiles1 = PR.ntiles1, &ntilesm = PR.ntilesm, &nrts = PR.nrts;
+    double &near_entries = PR.near_entries, &multi_entries = PR.multi_entries;
     for (size_t i = 0; i < jobs.size(); ++i) {
         const Job& J = jobs[i];
         NearProb P{};
@@ -568,20 +589,13 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
     }
 
     // ---------- far field descriptors, by wave ----------
-    struct Launch {
-        bool fp32;
-        int32_t L1, L2;
-        size_t d0, d1;          // descriptors [d0, d1)
-        int64_t nac, nb, nr;    // grid sizes of the column passes, pass B and the chunk reduction
-        double bytesA, bytesB, bytesC, bytesR, work;
-    };
-    size_t part_need = 0;
-    std::vector<FarDesc> descs;
-    std::vector<Launch> launches;
+    size_t& part_need = PR.part_need;
+    auto& descs = PR.descs;
+    auto& launches = PR.launches;
     size_t maxblocks = 0;
     for (auto& J : jobs) maxblocks = std::max(maxblocks, J.dp->blocks.size());
     const size_t budget = wave_budget();
-    size_t work_need = 0;
+    size_t& work_need = PR.work_need;
     for (size_t bi = 0; bi < maxblocks; ++bi) {
         // (job, group range) items of this wave
         struct Item {
@@ -635,7 +649,7 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
             }
             size_t off = 0; // bytes within the work buffer for this sub-wave
             for (auto& kv : shapes) {
-                Launch Ln{};
+                FarLaunch Ln{};
                 Ln.fp32 = std::get<0>(kv.first);
                 Ln.L1 = std::get<1>(kv.first);
                 Ln.L2 = std::get<2>(kv.first);
@@ -694,53 +708,35 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
                 launches.push_back(Ln);
             }
             work_need = std::max(work_need, off);
-            launches.push_back(Launch{}); // sub-wave boundary
+            launches.push_back(FarLaunch{}); // sub-wave boundary
         }
     }
+}
 
-    // ---------- uploads (skipped when identical to the previous call) ----------
-    if ((st = ensure(g_ex.work, work_need, s))) return st;
-    if ((st = ensure(g_ex.fpart, std::max<size_t>(part_need, 8), s))) return st;
-    for (auto& D : descs) {
-        D.buf = static_cast<char*>(g_ex.work.p) + reinterpret_cast<size_t>(D.buf);
-        if (D.nchunk > 1)
-            D.part = reinterpret_cast<double*>(static_cast<char*>(g_ex.fpart.p) + reinterpret_cast<size_t>(D.part));
-    }
-    if ((st = ensure(g_ex.partial, size_t(std::max<int64_t>(pbase, 1)) * sizeof(double), s))) return st;
-    std::vector<char> sig;
-    auto add = [&](const void* p, size_t n) {
-        const char* q = static_cast<const char*>(p);
-        sig.insert(sig.end(), q, q + n);
-    };
-    add(probs.data(), probs.size() * sizeof(NearProb));
-    add(descs.data(), descs.size() * sizeof(FarDesc));
-    if (sig != g_ex.sig) {
-        if ((st = upload(g_ex.probs, probs, s))) return st;
-        if ((st = upload(g_ex.descs, descs, s))) return st;
-        g_ex.sig.swap(sig);
-    }
-    const NearProb* dprobs = static_cast<const NearProb*>(g_ex.probs.p);
-    double* dpart = static_cast<double*>(g_ex.partial.p);
-
-    // ---------- launches ----------
+// The launches of prepared jobs on stream s, given the device copies of the
+// descriptors and the partial-sum buffer.
+hank_status enqueue_jobs(const Prepared& PR, const NearProb* dprobs, const FarDesc* ddesc, double* dpart,
+                         hipStream_t s) {
+    hank_status st;
     hipEvent_t ev;
-    const int32_t nprob = int32_t(probs.size());
+    const int32_t nprob = int32_t(PR.probs.size());
+    const int32_t nsingle = PR.nsingle;
+    const int64_t ntiles1 = PR.ntiles1, ntilesm = PR.ntilesm, nrts = PR.nrts, pbase = PR.pbase;
     if (ntiles1 > 0) {
         if ((st = prof_begin(ev, s))) return st;
         HIP_TRY(launch_near(dprobs, nsingle, ntiles1, dpart, s));
-        if ((st = prof_end(K_NEAR, ev, 8.0 * 64.0 * double(ntiles1), near_entries, s))) return st;
+        if ((st = prof_end(K_NEAR, ev, 8.0 * 64.0 * double(ntiles1), PR.near_entries, s))) return st;
     }
     if (ntilesm > 0) {
         if ((st = prof_begin(ev, s))) return st;
         HIP_TRY(launch_near_multi(dprobs + nsingle, nprob - nsingle, ntilesm, dpart, s));
-        if ((st = prof_end(K_NEAR_MULTI, ev, 0.0, multi_entries, s))) return st;
+        if ((st = prof_end(K_NEAR_MULTI, ev, 0.0, PR.multi_entries, s))) return st;
     }
     if ((st = prof_begin(ev, s))) return st;
     HIP_TRY(launch_near_reduce(dprobs, nprob, nrts, dpart, s));
     if ((st = prof_end(K_NEAR_REDUCE, ev, 8.0 * double(pbase), 0.0, s))) return st;
 
-    const FarDesc* ddesc = static_cast<const FarDesc*>(g_ex.descs.p);
-    for (auto& Ln : launches) {
+    for (auto& Ln : PR.launches) {
         if (Ln.L1 == 0) continue; // sub-wave boundary: the stream orders the waves
         const double bytes[3] = {Ln.bytesA, Ln.bytesB, Ln.bytesC};
         const int64_t grid[3] = {Ln.nac, Ln.nb, Ln.nac};
@@ -756,6 +752,42 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
             if ((st = prof_end(K_FAR_REDUCE, ev, Ln.bytesR, 0.0, s))) return st;
         }
     }
+    return HANK_OK;
+}
+
+hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
+    hank_status st;
+    Prepared PR;
+    prepare_jobs(jobs_in, PR);
+    if (!g_ex.done) HIP_TRY(hipEventCreateWithFlags(&g_ex.done, hipEventDisableTiming));
+    if (g_ex.used && g_ex.last != s) HIP_TRY(hipStreamWaitEvent(s, g_ex.done, 0));
+
+    // ---------- uploads (skipped when identical to the previous call) ----------
+    if ((st = ensure(g_ex.work, PR.work_need, s))) return st;
+    if ((st = ensure(g_ex.fpart, std::max<size_t>(PR.part_need, 8), s))) return st;
+    for (auto& D : PR.descs) {
+        D.buf = static_cast<char*>(g_ex.work.p) + reinterpret_cast<size_t>(D.buf);
+        if (D.nchunk > 1)
+            D.part = reinterpret_cast<double*>(static_cast<char*>(g_ex.fpart.p) + reinterpret_cast<size_t>(D.part));
+    }
+    if ((st = ensure(g_ex.partial, size_t(std::max<int64_t>(PR.pbase, 1)) * sizeof(double), s))) return st;
+    std::vector<char> sig;
+    auto add = [&](const void* p, size_t n) {
+        const char* q = static_cast<const char*>(p);
+        sig.insert(sig.end(), q, q + n);
+    };
+    add(PR.probs.data(), PR.probs.size() * sizeof(NearProb));
+    add(PR.descs.data(), PR.descs.size() * sizeof(FarDesc));
+    if (sig != g_ex.sig) {
+        if ((st = upload(g_ex.probs, PR.probs, s))) return st;
+        if ((st = upload(g_ex.descs, PR.descs, s))) return st;
+        g_ex.sig.swap(sig);
+    }
+    const NearProb* dprobs = static_cast<const NearProb*>(g_ex.probs.p);
+    double* dpart = static_cast<double*>(g_ex.partial.p);
+
+    const FarDesc* ddesc = static_cast<const FarDesc*>(g_ex.descs.p);
+    if ((st = enqueue_jobs(PR, dprobs, ddesc, dpart, s))) return st;
     HIP_TRY(hipEventRecord(g_ex.done, s));
     g_ex.last = s;
     g_ex.used = true;
@@ -1109,7 +1141,8 @@ hank_status hank_transform(int32_t task, const double* c, int64_t N, int64_t nrh
     return transform(task, c, N, nrhs, ldc, eps, out, ldo, options, stream);
 }
 
-hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t stream) {
+// Checks a request list and turns it into jobs (plans built as needed, on s).
+static hank_status batch_jobs(const hank_request* reqs, int64_t count, hipStream_t s, std::vector<Job>& jobs) {
     if (count < 0 || (count > 0 && !reqs)) return fail(HANK_EINVAL, "bad request list");
     for (int64_t i = 0; i < count; ++i) {
         const hank_request& r = reqs[i];
@@ -1127,8 +1160,6 @@ hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t st
         }
     }
     if (count == 0) return HANK_OK;
-    std::lock_guard<std::recursive_mutex> lk(g_mu);
-    hipStream_t s = (hipStream_t)stream;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     // host planning of the keys not cached yet, in parallel threads
@@ -1163,7 +1194,7 @@ hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t st
         for (auto& t : th) t.join();
         if (bad) return fail(HANK_EINVAL, "planning failed for a request");
     }
-    std::vector<Job> jobs;
+    jobs.clear();
     for (int64_t i = 0; i < count; ++i) {
         const hank_request& r = reqs[i];
         hank_options o{};
@@ -1175,7 +1206,110 @@ hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t st
         if (st) return st;
         jobs.push_back(Job{dp, r.c, r.ldc, r.out, r.ldo, r.nrhs});
     }
+    return HANK_OK;
+}
+
+hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t stream) {
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<Job> jobs;
+    hank_status st = batch_jobs(reqs, count, s, jobs);
+    if (st || jobs.empty()) return st;
     return run_jobs(jobs, s);
+}
+
+// ---- a batch captured as a HIP graph ----
+struct hank_graph {
+    int device = 0;
+    void *work = nullptr, *fpart = nullptr, *partial = nullptr, *probs = nullptr, *descs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~hank_graph() {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(device);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (void* p : {work, fpart, partial, probs, descs})
+            if (p) (void)hipFree(p);
+        (void)hipSetDevice(cur);
+    }
+};
+
+hank_status hank_batch_graph_create(const hank_request* reqs, int64_t count, hank_stream_t stream,
+                                    hank_graph** out) {
+    if (!out) return fail(HANK_EINVAL, "null pointer");
+    *out = nullptr;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<Job> jobs;
+    hank_status st = batch_jobs(reqs, count, s, jobs);
+    if (st) return st;
+    if (jobs.empty()) return fail(HANK_EINVAL, "empty request list");
+    Prepared PR;
+    prepare_jobs(jobs, PR);
+    std::unique_ptr<hank_graph> g(new hank_graph);
+    HIP_TRY(hipGetDevice(&g->device));
+    auto alloc = [&](void*& p, size_t bytes) -> hank_status {
+        hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 256));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(e == hipErrorOutOfMemory ? HANK_ENOMEM : HANK_EDEVICE, "hipMalloc failed");
+        }
+        return HANK_OK;
+    };
+    if ((st = alloc(g->work, PR.work_need))) return st;
+    if ((st = alloc(g->fpart, PR.part_need))) return st;
+    if ((st = alloc(g->partial, size_t(PR.pbase) * sizeof(double)))) return st;
+    if ((st = alloc(g->probs, PR.probs.size() * sizeof(NearProb)))) return st;
+    if ((st = alloc(g->descs, PR.descs.size() * sizeof(FarDesc)))) return st;
+    for (auto& D : PR.descs) {
+        D.buf = static_cast<char*>(g->work) + reinterpret_cast<size_t>(D.buf);
+        if (D.nchunk > 1)
+            D.part = reinterpret_cast<double*>(static_cast<char*>(g->fpart) + reinterpret_cast<size_t>(D.part));
+    }
+    // plans were built on s: finish before the descriptors are copied
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(g->probs, PR.probs.data(), PR.probs.size() * sizeof(NearProb), hipMemcpyHostToDevice));
+    if (!PR.descs.empty())
+        HIP_TRY(hipMemcpy(g->descs, PR.descs.data(), PR.descs.size() * sizeof(FarDesc), hipMemcpyHostToDevice));
+    // capture the launches (kernels only) on a private stream
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const bool prof = g_prof;
+    g_prof = false;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = enqueue_jobs(PR, static_cast<const NearProb*>(g->probs), static_cast<const FarDesc*>(g->descs),
+                          static_cast<double*>(g->partial), cs);
+        hipGraph_t gr = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &gr);
+        g->graph = gr;
+        if (!st && e2 != hipSuccess) st = fail(HANK_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+    } else {
+        st = fail(HANK_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    g_prof = prof;
+    (void)hipStreamDestroy(cs);
+    if (st) return st;
+    HIP_TRY(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    ++g_graphs;
+    *out = g.release();
+    return HANK_OK;
+}
+
+hank_status hank_batch_graph_launch(hank_graph* g, hank_stream_t stream) {
+    if (!g || !g->exec) return fail(HANK_EINVAL, "null graph");
+    HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return HANK_OK;
+}
+
+hank_status hank_batch_graph_destroy(hank_graph* g) {
+    if (!g) return HANK_OK;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    delete g;
+    --g_graphs;
+    return HANK_OK;
 }
 
 const char* hank_last_error(void) { return t_err.c_str(); }
@@ -1214,6 +1348,7 @@ hank_status hank_profile_report(hank_kernel_stat* out, int32_t max, int32_t* cou
 
 hank_status hank_cache_clear(void) {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
+    if (g_graphs > 0) return fail(HANK_EINVAL, "batch graphs still refer to cached plans");
     (void)hipDeviceSynchronize();
     g_cache.clear();
     return HANK_OK;

@@ -225,3 +225,39 @@ def test_batch_rejects_overlap_and_writes_nothing():
     with pytest.raises(hank.HankError):
         hank.batch([r1, r2])
     assert np.all(host(out) == 3.0)
+
+
+def test_batch_graph_replays_equal_eager():
+    """A batch captured as a HIP graph: every replay, with eager work and
+    synchronisations in between, gives bitwise the eager batch's results."""
+    reqs = _mixed_requests(23, 12)
+    hank.batch(reqs)
+    eager = [host(r["out"]).copy() for r in reqs]
+    with hank.BatchGraph(reqs) as g:
+        for rep in range(3):
+            for r in reqs:
+                r["out"].fill_(float("nan"))
+            # unrelated eager work on the same stream between replays
+            other = dev(np.random.default_rng(rep).standard_normal(3000))
+            hank.transform("dht0", other, 1e-8)
+            torch.cuda.synchronize()
+            g.launch()
+            torch.cuda.synchronize()
+            for r, e in zip(reqs, eager):
+                assert np.array_equal(host(r["out"]), e)
+        with pytest.raises(hank.HankError):  # plans are pinned while graphs exist
+            hank.cache_clear()
+    hank.cache_clear()
+
+
+def test_batch_graph_sees_new_inputs():
+    """The graph reads the requests' input tensors at launch time."""
+    reqs = _mixed_requests(24, 6)
+    with hank.BatchGraph(reqs) as g:
+        for r in reqs:
+            r["c"].mul_(-2.0)
+        g.launch()
+        got = [host(r["out"]).copy() for r in reqs]
+    hank.batch(reqs)
+    for r, x in zip(reqs, got):
+        assert np.array_equal(host(r["out"]), x)
