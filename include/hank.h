@@ -164,6 +164,17 @@ hank_status hank_server_status(hank_server* srv, int64_t ticket, int32_t* state,
 hank_status hank_server_stats(hank_server* srv, hank_server_summary* out);
 hank_status hank_server_destroy(hank_server* srv);
 
+/* ---- FFT autotuner ---------------------------------------------------------
+ * Times the far-field passes on a synthetic block for each FFT length
+ * L = 2^10 .. 2^23 and the splits L = L1 x L2 the kernels support near the
+ * default, and installs the fastest split per length for plans built from
+ * then on (cached plans keep theirs; hank_cache_clear rebuilds).  chosen, if
+ * not NULL, receives log2(L2) per log2(L) for indices 10..23 (24 entries).
+ * Runs on `stream` and synchronises it; about a second. */
+hank_status hank_autotune(hank_stream_t stream, int32_t* chosen);
+/* Back to the default split for plans built from then on. */
+hank_status hank_autotune_reset(void);
+
 /* ---- Library state --------------------------------------------------------- */
 const char* hank_last_error(void);   /* message of the calling thread's last error */
 hank_status hank_cache_clear(void);  /* drop every cached plan (device sync first)  */

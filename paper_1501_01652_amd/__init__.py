@@ -30,7 +30,8 @@ EXPORTS = ["hank_schlomilch", "hank_fourier_bessel", "hank_dht0", "hank_transfor
            "hank_plan_block", "hank_root_offsets", "hank_j0", "hank_profile", "hank_profile_report",
            "hank_server_create", "hank_server_warm", "hank_server_submit", "hank_server_start",
            "hank_server_drain", "hank_server_status", "hank_server_stats", "hank_server_destroy",
-           "hank_batch_graph_create", "hank_batch_graph_launch", "hank_batch_graph_destroy"]
+           "hank_batch_graph_create", "hank_batch_graph_launch", "hank_batch_graph_destroy",
+           "hank_autotune", "hank_autotune_reset"]
 
 
 class HankError(RuntimeError):
@@ -99,6 +100,10 @@ def lib():
             L.hank_batch_graph_launch.argtypes = [p, p]
             L.hank_batch_graph_destroy.restype = i32
             L.hank_batch_graph_destroy.argtypes = [p]
+            L.hank_autotune.restype = i32
+            L.hank_autotune.argtypes = [p, ctypes.POINTER(i32)]
+            L.hank_autotune_reset.restype = i32
+            L.hank_autotune_reset.argtypes = []
             L.hank_last_error.restype = ctypes.c_char_p
             L.hank_last_error.argtypes = []
             L.hank_cache_clear.restype = i32
@@ -229,6 +234,19 @@ def batch(requests, stream=None):
     task, c, out, eps and optionally precision (c, out of shape (N,) or (nrhs, N))."""
     arr, n = _requests(requests)
     _check(lib().hank_batch(arr, n, _stream(stream)))
+
+
+def autotune(stream=None) -> dict:
+    """Time the far-field passes for each FFT length 2^10..2^23 and install the
+    fastest split L = L1 x L2 for plans built afterwards; {log2 L: log2 L2}."""
+    arr = (ctypes.c_int32 * 24)()
+    _check(lib().hank_autotune(_stream(stream), arr))
+    return {lg: arr[lg] for lg in range(10, 24)}
+
+
+def autotune_reset():
+    """Default FFT splits for plans built afterwards."""
+    _check(lib().hank_autotune_reset())
 
 
 class BatchGraph:

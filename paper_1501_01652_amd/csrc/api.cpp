@@ -1346,6 +1346,128 @@ hank_status hank_profile_report(hank_kernel_stat* out, int32_t max, int32_t* cou
     return HANK_OK;
 }
 
+// ---- autotuner of the FFT split ----
+// Times passes A, B and C of a synthetic block (rows = columns = L/2, four
+// transform groups, FP64, one right-hand side) for every split L1 x L2 the
+// kernels support within two steps of the default, L = 2^10 .. 2^23, and
+// installs the fastest for plans built afterwards.
+hank_status hank_autotune(hank_stream_t stream, int32_t* chosen) {
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hank_status st = ensure_tables(dev);
+    if (st) return st;
+    const int G = 4, lgmin = 10, lgmax = 23;
+    const int64_t Lmax = int64_t(1) << lgmax;
+    // device buffers for the largest case
+    void *c = nullptr, *f = nullptr, *buf = nullptr, *H = nullptr, *part = nullptr, *dd = nullptr;
+    GroupDev* dg = nullptr;
+    TermDev* dt = nullptr;
+    auto cleanup = [&]() {
+        for (void* p : {c, f, buf, H, part, dd, (void*)dg, (void*)dt})
+            if (p) (void)hipFree(p);
+    };
+    auto al = [&](void*& p, size_t bytes) -> bool { return hipMalloc(&p, bytes) == hipSuccess; };
+    if (!al(c, size_t(Lmax) * 4) || !al(f, size_t(Lmax) * 4) || !al(buf, size_t(G) * size_t(Lmax) * 16) ||
+        !al(H, size_t(Lmax) * 16) || !al(part, size_t(Lmax) * 4 * G) || !al(dd, sizeof(FarDesc)) ||
+        !al(reinterpret_cast<void*&>(dg), sizeof(GroupDev) * G) || !al(reinterpret_cast<void*&>(dt), sizeof(TermDev) * G)) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(HANK_ENOMEM, "autotune: out of device memory");
+    }
+    GroupDev hg[G];
+    TermDev ht[G];
+    for (int i = 0; i < G; ++i) {
+        hg[i] = GroupDev{0, -i, i, i + 1, 1.0};
+        ht[i] = TermDev{0, i, 0.5, 0.25};
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto run = [&]() -> hank_status {
+        HIP_TRY(hipMemsetAsync(c, 0, size_t(Lmax) * 4, s));
+        HIP_TRY(hipMemsetAsync(H, 0, size_t(Lmax) * 16, s));
+        HIP_TRY(hipMemcpyAsync(dg, hg, sizeof(hg), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(dt, ht, sizeof(ht), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        for (int lg = lgmin; lg <= lgmax; ++lg) {
+            const int64_t L = int64_t(1) << lg;
+            const int def = default_fft_l2(lg);
+            int best = def;
+            float best_ms = 1e30f;
+            for (int l2 = std::max(3, def - 2); l2 <= std::min(10, def + 2); ++l2) {
+                const int l1 = lg - l2;
+                if (l1 < 3 || l1 > 13) continue;
+                FarDesc D{};
+                FarArgs& A = D.A;
+                A.ka = A.na = 1;
+                A.nrows = A.ncols = L / 2;
+                A.L = L;
+                A.L1 = int32_t(1) << l1;
+                A.L2 = int32_t(1) << l2;
+                A.twshift = 23 - lg;
+                A.ngroups = G;
+                A.g0 = 0;
+                A.g1 = G;
+                A.ar = A.ac = 1;
+                A.D = Lmax;
+                A.Dr = A.Qc = Lmax;
+                A.Kka = A.Nna = 1;
+                A.pi_Qc = 1e-6;
+                A.r0 = A.w0 = A.eref = A.lref = A.bref = 1.0;
+                A.groups = dg;
+                A.terms = dt;
+                D.c = static_cast<const double*>(c);
+                D.f = static_cast<double*>(f);
+                D.buf = buf;
+                D.H = H;
+                D.part = static_cast<double*>(part);
+                D.ldc = D.ldo = L / 2;
+                D.nrhs = 1;
+                D.nchunk = far_chunks(L, G, 1);
+                D.gchunk = (G + D.nchunk - 1) / D.nchunk;
+                D.nchunk = (G + D.gchunk - 1) / D.gchunk;
+                const int64_t nac = int64_t(D.nchunk) * (A.L1 / col_width(A.L2, false));
+                const int32_t rows = far_rows_per_wg(A.L1);
+                const int64_t nb = int64_t(D.nchunk) * ((A.L2 + rows - 1) / rows);
+                HIP_TRY(hipMemcpyAsync(dd, &D, sizeof(D), hipMemcpyHostToDevice, s));
+                const FarDesc* pd = static_cast<const FarDesc*>(dd);
+                float ms = 1e30f;
+                for (int rep = 0; rep < 4; ++rep) {
+                    HIP_TRY(hipEventRecord(e0, s));
+                    HIP_TRY(launch_far_pass(0, false, A.L1, A.L2, pd, 1, nac, s));
+                    HIP_TRY(launch_far_pass(1, false, A.L1, A.L2, pd, 1, nb, s));
+                    HIP_TRY(launch_far_pass(2, false, A.L1, A.L2, pd, 1, nac, s));
+                    HIP_TRY(hipEventRecord(e1, s));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float t = 0;
+                    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+                    if (rep > 0) ms = std::min(ms, t);
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = l2;
+                }
+            }
+            set_fft_split(lg, best);
+            if (chosen) chosen[lg] = best;
+        }
+        return HANK_OK;
+    };
+    st = run();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    cleanup();
+    return st;
+}
+
+hank_status hank_autotune_reset(void) {
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    for (int lg = 0; lg < 32; ++lg) set_fft_split(lg, 0);
+    return HANK_OK;
+}
+
 hank_status hank_cache_clear(void) {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
     if (g_graphs > 0) return fail(HANK_EINVAL, "batch graphs still refer to cached plans");

@@ -130,8 +130,11 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
 // the supported term count.
 bool build_block_terms(const Grid& g, Block& b, double eps, int mode, int Mpaper, int K, int T);
 
-// Choose L1 x L2 for an FFT length.
+// Choose L1 x L2 for an FFT length: the autotuned split for log2(L) if one
+// was installed (set_fft_split), else the default rule (default_fft_l2).
 void fft_split(int64_t L, int32_t& L1, int32_t& L2);
+int default_fft_l2(int lg);
+void set_fft_split(int lg, int l2); // l2 = 0 restores the default
 
 CostModel cost_model_from_env();
 

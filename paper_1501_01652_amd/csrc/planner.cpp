@@ -131,9 +131,29 @@ double emax(int64_t k, int64_t N) {
     return 1.0 / (8.0 * (double(N) + 0.75) * (double(k) - 0.25) * M_PI * M_PI);
 }
 
+// l2 chosen by the autotuner per log2(L) (0: the default rule)
+static int g_l2_tuned[32] = {0};
+
+void set_fft_split(int lg, int l2) {
+    if (lg >= 0 && lg < 32) g_l2_tuned[lg] = l2;
+}
+
+int default_fft_l2(int lg);
+
 void fft_split(int64_t L, int32_t& L1, int32_t& L2) {
     int lg = 0;
     while ((int64_t(1) << lg) < L) ++lg;
+    if (lg < 32 && g_l2_tuned[lg] > 0) {
+        L2 = int32_t(1) << g_l2_tuned[lg];
+        L1 = int32_t(1) << (lg - g_l2_tuned[lg]);
+        return;
+    }
+    const int l2 = default_fft_l2(lg);
+    L1 = int32_t(1) << (lg - l2);
+    L2 = int32_t(1) << l2;
+}
+
+int default_fft_l2(int lg) {
     // columns (passes A and C) of 2^l2 <= 1024 points, rows (pass B) of
     // 2^l1 <= 2^l1max points (l1max = 13, HANK_FFT_L1MAX overrides);
     // balanced below 2^16, columns of at least 256 above
@@ -141,10 +161,7 @@ void fft_split(int64_t L, int32_t& L1, int32_t& L2) {
         const char* e = std::getenv("HANK_FFT_L1MAX");
         return e ? std::max(8, std::min(13, std::atoi(e))) : 13;
     }();
-    int l2 = (lg <= 16) ? lg / 2 : std::min(10, std::max(8, lg - l1max));
-    int l1 = lg - l2;
-    L1 = int32_t(1) << l1;
-    L2 = int32_t(1) << l2;
+    return (lg <= 16) ? lg / 2 : std::min(10, std::max(8, lg - l1max));
 }
 
 CostModel cost_model_from_env() {

@@ -261,3 +261,20 @@ def test_batch_graph_sees_new_inputs():
     hank.batch(reqs)
     for r, x in zip(reqs, got):
         assert np.array_equal(host(r["out"]), x)
+
+
+def test_autotuned_splits_keep_parity():
+    """Plans built after hank_autotune use the measured FFT splits; results stay
+    within tolerance of the oracle (then the defaults are restored)."""
+    chosen = hank.autotune()
+    assert set(chosen) == set(range(10, 24))
+    assert all(3 <= l2 <= 10 and 3 <= lg - l2 <= 13 for lg, l2 in chosen.items())
+    try:
+        hank.cache_clear()
+        for task, N, eps in (("dht0", 2500, 1e-8), ("fourier_bessel", 2500, 1e-14), ("schlomilch", 700, 1e-4)):
+            c, ref = oracle_full(task, N, 5000 + N)
+            f = host(hank.transform(task, dev(c), eps, prefer_far=1))
+            assert measured_C(f, ref, eps, c) <= C_TOL
+    finally:
+        hank.autotune_reset()
+        hank.cache_clear()
