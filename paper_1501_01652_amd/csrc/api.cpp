@@ -1349,7 +1349,7 @@ hank_status hank_profile_report(hank_kernel_stat* out, int32_t max, int32_t* cou
 // ---- autotuner of the FFT split ----
 // Times passes A, B and C of a synthetic block (rows = columns = L/2, four
 // transform groups, FP64, one right-hand side) for every split L1 x L2 the
-// kernels support within two steps of the default, L = 2^10 .. 2^23, and
+// kernels support (L1 >= L2) within two steps of the default, L = 2^10 .. 2^23, and
 // installs the fastest for plans built afterwards.
 hank_status hank_autotune(hank_stream_t stream, int32_t* chosen) {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
@@ -1397,7 +1397,7 @@ hank_status hank_autotune(hank_stream_t stream, int32_t* chosen) {
             float best_ms = 1e30f;
             for (int l2 = std::max(3, def - 2); l2 <= std::min(10, def + 2); ++l2) {
                 const int l1 = lg - l2;
-                if (l1 < 3 || l1 > 13) continue;
+                if (l1 < l2 || l1 > 13) continue; // the column passes assume L1 >= L2
                 FarDesc D{};
                 FarArgs& A = D.A;
                 A.ka = A.na = 1;

@@ -143,7 +143,7 @@ int default_fft_l2(int lg);
 void fft_split(int64_t L, int32_t& L1, int32_t& L2) {
     int lg = 0;
     while ((int64_t(1) << lg) < L) ++lg;
-    if (lg < 32 && g_l2_tuned[lg] > 0) {
+    if (lg < 32 && g_l2_tuned[lg] > 0 && 2 * g_l2_tuned[lg] <= lg && lg - g_l2_tuned[lg] <= 13) {
         L2 = int32_t(1) << g_l2_tuned[lg];
         L1 = int32_t(1) << (lg - g_l2_tuned[lg]);
         return;

@@ -268,7 +268,7 @@ def test_autotuned_splits_keep_parity():
     within tolerance of the oracle (then the defaults are restored)."""
     chosen = hank.autotune()
     assert set(chosen) == set(range(10, 24))
-    assert all(3 <= l2 <= 10 and 3 <= lg - l2 <= 13 for lg, l2 in chosen.items())
+    assert all(3 <= l2 <= 10 and l2 <= lg - l2 <= 13 for lg, l2 in chosen.items())
     try:
         hank.cache_clear()
         for task, N, eps in (("dht0", 2500, 1e-8), ("fourier_bessel", 2500, 1e-14), ("schlomilch", 700, 1e-4)):
