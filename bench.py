@@ -109,7 +109,8 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=1024, help="requests of the batched workload (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--only", choices=["all", "headline", "batched", "serve", "copy"], default="all")
+    ap.add_argument("--only", choices=["all", "headline", "batched", "serve", "copy", "ablation"], default="all")
+    ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write the HBM traffic summary from rocprofv3 counter csv files and exit")
     return ap.parse_args()
@@ -170,6 +171,54 @@ def run_batched(hank, inputs, torch, count):
             "sequential_transforms_per_s": count / ts, "sequential_ms": ts * 1e3,
             "sequential_latency_p50_ms": pct(0.5), "sequential_latency_p99_ms": pct(0.99),
             "speedup": ts / tb, "first_call_incl_planning_s": warm_s}
+
+
+def _median_ms(hank, torch, task, c, eps, out, reps, **kw):
+    hank.transform(task, c, eps, out=out, **kw)  # plan build and warm-up
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    stream = torch.cuda.current_stream()
+    evs[0].record(stream)
+    for i in range(reps):
+        hank.transform(task, c, eps, out=out, stream=stream, **kw)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(reps))[reps // 2]
+
+
+def run_ablation(hank, inputs, torch, task, N, eps, c_host):
+    """Cost-model ablations: the tuned partition against the paper's (Table 4)
+    and against one far block (P = 0, Sec. 3.3) on the headline workload; and
+    the M sweep of Sec. 4.3 (Schlomilch, N = 5000, paper plan, M = 1..20)."""
+    c = torch.from_numpy(c_host).to("cuda")
+    out = torch.empty_like(c)
+    part = {}
+    for name, mode in (("tuned", 0), ("paper", 1), ("single_partition", 2)):
+        info = hank.plan_info(task, N, eps, plan_mode=mode)
+        ms = _median_ms(hank, torch, task, c, eps, out, 5, plan_mode=mode)
+        part[name] = {"ms": ms, "points_per_s": N / (ms * 1e-3), "M": info["M"], "P": info["P"],
+                      "blocks": info["nblocks"], "near_entries": info["near_entries"],
+                      "far_transforms": info["far_transforms"], "fft_bytes": info["fft_bytes"]}
+    del c, out
+    hank.cache_clear()
+    Ns = 5000
+    cs = torch.from_numpy(inputs.coefficients("gauss", Ns, inputs.SEED_SCHLOMILCH)).to("cuda")
+    outs = torch.empty_like(cs)
+    sweep = {}
+    for e in (1e-15, 1e-11, 1e-7, 1e-3):
+        ms = {}
+        for M in range(1, 21):
+            ms[M] = _median_ms(hank, torch, "schlomilch", cs, e, outs, 5, plan_mode=1, M=M)
+        best = min(ms, key=ms.get)
+        table4 = hank.plan_info("schlomilch", Ns, e, plan_mode=1)["M"]
+        sweep["%g" % e] = {"ms_by_M": ms, "best_M": best, "table4_M": table4,
+                           "table4_over_best": ms[table4] / ms[best],
+                           "tuned_ms": _median_ms(hank, torch, "schlomilch", cs, e, outs, 5)}
+    direct_ms = _median_ms(hank, torch, "schlomilch", cs, 1e-15, outs, 5, direct=1)
+    hank.cache_clear()
+    return {"partition": part,
+            "m_sweep": {"workload": "schlomilch N=%d, c_n iid N(0,1) seed %d, paper plan" % (Ns, inputs.SEED_SCHLOMILCH),
+                        "by_eps": sweep, "direct_ms": direct_ms}}
 
 
 def run_serve(hank, inputs, torch, seconds, rate, max_batch):
@@ -238,6 +287,10 @@ def main():
     if args.only in ("batched", "serve"):
         run_extra()
         print(json.dumps(extra))
+        return
+    if args.only == "ablation":
+        print(json.dumps(run_ablation(hank, inputs, torch, args.task, args.N, args.eps,
+                                      inputs.workload(args.task, args.N))))
         return
     if args.only == "copy":
         print(json.dumps(run_copy(torch)))
@@ -374,6 +427,9 @@ def main():
         "step_ms": {"median": step_q(0.5), "p90": step_q(0.9), "min": step_ms[0], "max": step_ms[-1]},
         "plan_roofline": plan_roofline,
     }
+    if args.only == "all" and not args.no_ablation:
+        del c, out
+        line["ablation"] = run_ablation(hank, inputs, torch, task, N, eps, c_host)
     run_extra()
     line.update(extra)
     print(json.dumps(line))

@@ -64,7 +64,9 @@ typedef void* hank_stream_t; /* a hipStream_t */
 /* Options; pass NULL for the defaults (all zero). */
 typedef struct {
     int32_t plan_mode;  /* 0: GPU-tuned partition and per-block truncation (default)
-                           1: the paper's parameters (Table 4, K and T of Sec. 5.1/6) */
+                           1: the paper's parameters (Table 4, K and T of Sec. 5.1/6)
+                           2: as 1 with P = 0: one far block Q_1 and everything else
+                              summed directly, the O(N^{3/2}) scheme of Sec. 3.3   */
     int32_t precision;  /* 0: auto -- FP32 transform bulk iff eps >= 1e-6, else FP64
                            1: FP64 bulk   2: FP32 bulk (any eps; accuracy then limited) */
     int32_t direct;     /* 1: skip the fast method and sum every entry on the GPU (the
@@ -76,6 +78,13 @@ typedef struct {
                            own nrhs (rounded up to a power of two, at most 64): with
                            several right-hand sides J_0 is evaluated once per direct
                            entry, so the tuned partition moves toward the near field */
+    int32_t M;          /* plan modes 1 and 2: number of asymptotic terms M of eq.
+                           (HankelExpansion) in place of Table 4's max(floor(0.3 ln
+                           (1/eps)), 3), 1 <= M <= 20; s_{nu,M}(eps), alpha and P
+                           follow from it (the M sweep of Sec. 4.3).  0: Table 4.
+                           HANK_EINVAL in mode 0, outside [0, 20], or below the
+                           smallest M whose remainder bound covers the highest
+                           Bessel order the plan uses (M >= mu_max/2 - 1/4)      */
 } hank_options;
 
 /* ---- The three transforms (Sec. 4, 5, 6) ---------------------------------

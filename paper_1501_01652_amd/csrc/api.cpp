@@ -46,9 +46,11 @@ hank_status fail(hank_status s, const std::string& msg) {
                         std::string(#call) + ": " + hipGetErrorString(e_));                        \
     } while (0)
 
-// Columns per near-field work item: the widest of 2048, 1024, 512, 256 that
-// still gives at least 2048 tiles (two rounds of the chip at four
-// workgroups per compute unit), so that small problems fill the chip and
+// Columns per near-field work item.  A tile's columns are a serial loop, so
+// the widest tile bounds the launch: the width is the largest of 2048, 1024,
+// ..., 64 whose 64-row tile holds no more than the average work of one of the
+// 768 workgroups the chip keeps resident (256 compute units x 3; occupancy of
+// the near kernel).  Small problems then fill the chip with short tiles and
 // large ones keep the per-row reduction short.  HANK_NEAR_COLS fixes it.
 int64_t near_chunk(const std::vector<NearSeg>& segs) {
     static const int64_t fixed = [] {
@@ -56,12 +58,11 @@ int64_t near_chunk(const std::vector<NearSeg>& segs) {
         return e ? std::max<int64_t>(64, std::min<int64_t>(NEAR_TILE_COLS, std::atoll(e))) : int64_t(0);
     }();
     if (fixed) return fixed;
+    double entries = 0;
+    for (auto& seg : segs) entries += double(seg.k1 - seg.k0) * double(seg.ncut - 1);
+    const double resident = 768.0;
     int64_t chunk = NEAR_TILE_COLS;
-    for (; chunk > 256; chunk /= 2) {
-        int64_t tiles = 0;
-        for (auto& seg : segs) tiles += ((seg.k1 - seg.k0 + 63) / 64) * ((seg.ncut - 1 + chunk - 1) / chunk);
-        if (tiles >= 2048) break;
-    }
+    while (chunk > 64 && 64.0 * double(chunk) * resident > entries) chunk /= 2;
     return chunk;
 }
 
@@ -358,7 +359,8 @@ Key plan_key(int task, int64_t N, double eps, const hank_options* o, int dev, in
     int far = o ? o->prefer_far : 0;
     uint64_t eb;
     std::memcpy(&eb, &eps, 8);
-    return Key{task, N, eb, mode, prec, (direct * 2 + far) * 128 + int(rhs_bucket(nrhs)), dev};
+    int M = o ? o->M : 0;
+    return Key{task, N, eb, mode + 4 * M, prec, (direct * 2 + far) * 128 + int(rhs_bucket(nrhs)), dev};
 }
 
 hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hipStream_t s, DevPlan*& out,
@@ -378,7 +380,8 @@ hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hip
     dp->device = dev;
     try {
         dp->plan = prebuilt ? *prebuilt
-                            : make_plan(task, N, eps, mode, prec, direct != 0, cost_model_for(o), rhs_bucket(nrhs));
+                            : make_plan(task, N, eps, mode, prec, direct != 0, cost_model_for(o), rhs_bucket(nrhs),
+                                        o ? o->M : 0);
     } catch (const std::exception& ex) {
         return fail(HANK_EINVAL, std::string("planning failed: ") + ex.what());
     }
@@ -1493,7 +1496,7 @@ static hank_status host_plan(int32_t task, int64_t N, double eps, const hank_opt
     if (!valid_task(task)) return fail(HANK_EINVAL, "unknown task");
     try {
         p = make_plan(task, N, eps, o ? o->plan_mode : 0, o ? o->precision : 0, o && o->direct,
-                      cost_model_for(o), rhs_bucket(o && o->nrhs > 1 ? o->nrhs : 1));
+                      cost_model_for(o), rhs_bucket(o && o->nrhs > 1 ? o->nrhs : 1), o ? o->M : 0);
     } catch (const std::exception& ex) {
         return fail(HANK_EINVAL, ex.what());
     }

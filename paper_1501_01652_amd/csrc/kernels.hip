@@ -274,7 +274,10 @@ struct alignas(16) ColCB {
 // variant (NearVariant) of the 64-column block starting at column nb of tile T
 __device__ __forceinline__ int tile_block_variant(const NearTile& T, int64_t nb) {
     const int b = (int)((nb - T.n0) >> 6);
-    return (int)((T.bvar[b >> 3] >> (4 * (b & 7))) & 15u);
+    // selects rather than an indexed load keep the tile in registers
+    const int q = b >> 3;
+    const uint32_t w = q == 0 ? T.bvar[0] : q == 1 ? T.bvar[1] : q == 2 ? T.bvar[2] : T.bvar[3];
+    return (int)((w >> (4 * (b & 7))) & 15u);
 }
 
 // One 64-column block of a sweep: the lane's columns p[0], p[4], ... (cnt of them)

@@ -123,8 +123,10 @@ double emax(int64_t k, int64_t N);
 
 // Build a plan.  Throws std::invalid_argument on bad input.
 // nrhs: the number of right-hand sides the tuned partition is balanced for.
+// mode: 0 tuned, 1 paper, 2 paper with P = 0 (single partition).
+// Mpaper: M in modes 1 and 2 (0: Table 4's rule).
 Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool direct,
-               const CostModel& cm, int64_t nrhs = 1);
+               const CostModel& cm, int64_t nrhs = 1, int Mpaper = 0);
 
 // Fill terms/groups of a block; returns false if the truncation would exceed
 // the supported term count.

@@ -3,8 +3,9 @@
 // Every parameter follows from eps and N through the paper's error bounds:
 //   M, s_{nu,M}(eps), alpha, beta, P          Table 4 and Sec. 3.1 / 4.2
 //   K, T, the first direct columns/rows       Sec. 5.1 (eqs. (pKe), (qTe)) and Sec. 6
-// Two modes build the partition:
+// Three modes build the partition:
 //   paper  the paper's rules verbatim (global K, T and M for every block);
+//   single the paper's rules with P = 0: one far block (Sec. 3.3);
 //   tuned  the same staircase of rectangular blocks, but the block shape is
 //          chosen by a cost model of this GPU and each block keeps only the
 //          perturbation and asymptotic terms its own error bound requires.
@@ -529,8 +530,11 @@ static double plan_cost(const Plan& p, const CostModel& cm) {
 }
 
 Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool direct, const CostModel& cm,
-               int64_t nrhs) {
+               int64_t nrhs, int Mpaper) {
     if (!(eps >= 1e-15 && eps < 1.0) || !std::isfinite(eps)) throw std::invalid_argument("eps out of range");
+    if (mode < 0 || mode > 2) throw std::invalid_argument("plan_mode must be 0, 1 or 2");
+    if (Mpaper < 0 || Mpaper > 20 || (Mpaper > 0 && mode == 0))
+        throw std::invalid_argument("M must lie in [1, 20] and needs plan_mode 1 or 2");
     int64_t Nmin = (task == T_SCHL || task == T_FB) ? 2 : 1;
     if (N < Nmin || N > (int64_t(1) << 24)) throw std::invalid_argument("N out of range");
     Plan p;
@@ -542,7 +546,7 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
     p.nrhs = std::max<int64_t>(1, nrhs);
 
     // paper parameters (reported in both modes)
-    p.M = paper_M(eps);
+    p.M = Mpaper > 0 ? Mpaper : paper_M(eps);
     int numax = 0;
     if (p.g.col_pert || p.g.row_pert) {
         double f = (task == T_DHT) ? 1.01 : 1.0;
@@ -553,12 +557,15 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
         p.first_direct = int(std::floor(f * std::max(param_pK(p.K, eps), param_qT(p.T, eps))));
         numax = (task == T_DHT) ? 2 * p.K - 2 : p.K - 1;
     }
+    // the remainder bound of eq. (errorBound) holds for orders mu <= 2M + 1/2
+    if (mode != 0 && 2 * p.M + 0.5 < numax)
+        throw std::invalid_argument("M too small for the Bessel orders of this plan");
     p.s = param_s(numax, p.M, eps);
     p.alpha = std::sqrt(p.s / M_PI);
     // DHT: the footnote of Sec. 6 runs Fourier-Bessel on the padded size 4N+3
     int64_t Neff = (task == T_DHT) ? 4 * N + 3 : N;
     p.beta = paper_beta(Neff);
-    p.P = paper_P(p.alpha, p.beta, Neff);
+    p.P = mode == 2 ? 0 : paper_P(p.alpha, p.beta, Neff);
 
     auto finish = [&](Plan& q) -> bool {
         if (!near_segments(q.g, q.blocks, q.near, q.near_entries)) return false;
@@ -575,7 +582,7 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
     if (task == T_FB || task == T_FB_PG) nfloor = p.first_direct + 1;
     if (task == T_DHT) kfloor = p.first_direct + 1;
 
-    if (mode == 1) {
+    if (mode != 0) {
         double R0 = p.alpha / std::sqrt(double(Neff));
         p.blocks = staircase(p.g, p.s, R0, p.beta, p.P, kfloor, nfloor);
         std::vector<Block> ok;

@@ -83,6 +83,14 @@ def test_dht0_2pow20_paper_plan():
     check("dht0", N, eps, c, rows, "paper", plan_mode=1)
 
 
+def test_dht0_2pow20_single_partition():
+    """Plan mode 2 (one far block, Sec. 3.3): about 5e9 direct entries."""
+    N, eps = 1 << 20, 1e-8
+    c = inputs.workload("dht0", N)
+    rows = inputs.sampled_rows(N, 32, boundary_rows("dht0", N, eps, plan_mode=2))
+    check("dht0", N, eps, c, rows, "single partition", plan_mode=2)
+
+
 def test_dht0_2pow20_one_hot_columns():
     """c = e_n at the columns bordering every block: f_k = J_0(r_k w_n) for all k."""
     N, eps = 1 << 20, 1e-8

@@ -70,12 +70,12 @@ def test_device_roots_match_oracle():
 @pytest.mark.parametrize("task", TASKS)
 @pytest.mark.parametrize("N", [2, 17, 100, 700, 2500])
 @pytest.mark.parametrize("eps", [1e-4, 1e-8, 1e-14])
-@pytest.mark.parametrize("mode", ["tuned", "far", "paper"])
+@pytest.mark.parametrize("mode", ["tuned", "far", "paper", "single"])
 def test_parity_all_rows(task, N, eps, mode):
     if N == 2 and task == "dht0":
         N = 1
     c, ref = oracle_full(task, N, 1000 + N)
-    kw = {"tuned": {}, "far": {"prefer_far": 1}, "paper": {"plan_mode": 1}}[mode]
+    kw = {"tuned": {}, "far": {"prefer_far": 1}, "paper": {"plan_mode": 1}, "single": {"plan_mode": 2}}[mode]
     f = host(hank.transform(task, dev(c), eps, **kw))
     Cm = measured_C(f, ref, eps, c)
     nb = hank.plan_info(task, N, eps, **kw)["nblocks"]
@@ -110,6 +110,22 @@ def test_one_hot_every_column_class(task, N, eps, mode):
     print("%s N=%d eps=%g %s columns=%d worst entry error %.3g (%.3g eps)" %
           (task, N, eps, mode, len(cols), worst, worst / eps))
     assert worst <= C_TOL * eps
+
+
+@pytest.mark.parametrize("eps", [1e-15, 1e-11, 1e-7, 1e-3])
+@pytest.mark.parametrize("M", [1, 2, 3, 5, 8, 12, 20])
+def test_m_sweep_parity(eps, M):
+    """The M sweep of Sec. 4.3 (Schlomilch, N = 5000): every M in the paper's
+    range gives a result within the error bound, in both paper plan modes."""
+    N = 5000
+    c, ref = oracle_full("schlomilch", N, 4300)
+    for mode in (1, 2):
+        f = host(hank.transform("schlomilch", dev(c), eps, plan_mode=mode, M=M))
+        Cm = measured_C(f, ref, eps, c)
+        info = hank.plan_info("schlomilch", N, eps, plan_mode=mode, M=M)
+        print("schlomilch N=%d eps=%g M=%d mode=%d blocks=%d near=%d measured C=%.3g" %
+              (N, eps, M, mode, info["nblocks"], info["near_entries"], Cm))
+        assert Cm <= C_TOL
 
 
 @pytest.mark.parametrize("task", ["schlomilch", "fourier_bessel", "dht0"])

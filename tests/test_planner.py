@@ -118,7 +118,7 @@ def _ztilde(task, N, k, n):
 @pytest.mark.parametrize("task,N,eps", [("schlomilch", 4096, 1e-14), ("fourier_bessel", 65536, 1e-8),
                                         ("dht0", 1 << 20, 1e-8), ("dht0", 3000, 1e-4),
                                         ("fourier_bessel", 777, 1e-14)])
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_partition_structure(task, N, eps, mode):
     """Blocks are disjoint rectangles, their far columns form a suffix of every
     row (so the rest is a staircase near field), every block corner lies in the
@@ -133,7 +133,7 @@ def test_partition_structure(task, N, eps, mode):
         assert b["fft_len"] >= (b["row1"] - b["row0"] + 1) + (b["col1"] - b["col0"] + 1) - 1
         z = _ztilde(task, N, b["row0"], b["col0"])
         assert z == pytest.approx(b["zmin"], rel=1e-12)
-        if mode == 1:
+        if mode != 0:
             assert z >= info["s"] * (1 - 1e-12)
             if task == "fourier_bessel":
                 assert b["col0"] > info["first_direct"]
@@ -173,3 +173,51 @@ def test_invalid_plan_arguments():
         hank.plan_info("dht0", 100, float("nan"))
     with pytest.raises(hank.HankError):
         hank.plan_info(9, 100, 1e-8)
+
+
+@pytest.mark.parametrize("N", [5000, 20000])
+def test_single_partition_is_sec33(N):
+    """Plan mode 2 (Sec. 3.3): P = 0 and one far block Q_1.  On the paper grid
+    r_k = k/N the block starts at row ceil(alpha sqrt(N)) as in Fig. 3; its
+    first column is the first one that passes the corner test there, which is
+    at most that index, and the near field holds O(alpha N^{3/2}) entries."""
+    eps = 1e-14
+    info = hank.plan_info("schlomilch_paper_grid", N, eps, plan_mode=2)
+    blocks = hank.plan_blocks("schlomilch_paper_grid", N, eps, plan_mode=2)
+    assert info["P"] == 0 and info["nblocks"] == 1
+    m = math.ceil(info["alpha"] * math.sqrt(N))
+    b = blocks[0]
+    assert b["row0"] == m and b["col0"] <= m and b["row1"] == N and b["col1"] == N
+    assert math.pi * b["row0"] * b["col0"] / N >= info["s"]
+    assert info["near_entries"] <= 2 * m * N
+    # the paper's recursive partition needs fewer direct entries
+    assert hank.plan_info("schlomilch_paper_grid", N, eps, plan_mode=1)["near_entries"] < info["near_entries"]
+
+
+def test_m_override():
+    """M in plan modes 1 and 2 replaces Table 4's rule; s_{0,M}(eps) and alpha
+    follow it (Schlomilch: order 0 only)."""
+    for M in (1, 2, 4, 9, 15, 20):
+        info = hank.plan_info("schlomilch", 5000, 1e-11, plan_mode=1, M=M)
+        assert info["M"] == M
+        assert info["s"] == pytest.approx(hank.param_s(0, M, 1e-11), rel=1e-14)
+        assert info["alpha"] == pytest.approx(math.sqrt(info["s"] / math.pi), rel=1e-14)
+    assert hank.plan_info("schlomilch", 5000, 1e-11, plan_mode=1, M=0)["M"] == 7
+    # fewer asymptotic terms move the corner outward: more direct entries
+    near = [hank.plan_info("schlomilch", 5000, 1e-11, plan_mode=2, M=M)["near_entries"] for M in (1, 2, 3, 5)]
+    assert near == sorted(near, reverse=True)
+
+
+def test_m_override_rejected():
+    with pytest.raises(hank.HankError):
+        hank.plan_info("schlomilch", 5000, 1e-8, plan_mode=0, M=5)  # the tuned plan chooses its own M
+    with pytest.raises(hank.HankError):
+        hank.plan_info("schlomilch", 5000, 1e-8, plan_mode=1, M=21)
+    with pytest.raises(hank.HankError):
+        hank.plan_info("schlomilch", 5000, 1e-8, plan_mode=3)
+    # DHT at 1e-14 uses Bessel orders up to 2K - 2 = 10: the bound of
+    # eq. (errorBound) needs M >= 5
+    assert hank.plan_info("dht0", 1 << 16, 1e-14, plan_mode=1)["K"] == 6
+    with pytest.raises(hank.HankError):
+        hank.plan_info("dht0", 1 << 16, 1e-14, plan_mode=1, M=4)
+    assert hank.plan_info("dht0", 1 << 16, 1e-14, plan_mode=1, M=5)["M"] == 5
