@@ -610,6 +610,10 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict
         double cv[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) cv[r] = nidx[r] >= 0 ? cj[nidx[r]] : 0.0;
+        // four-step twiddles e^{-2 pi i j1 m2 / L}, m2 = tt + r NTC, shared by
+        // every group: w_r = w(j1 tt) w(j1 NTC)^r from two table entries
+        const cx<double> tw0 = tw_big<double>(j1 * tt, A.twshift);
+        const cx<double> tws = tw_big<double>(j1 * NTC, A.twshift);
         int ecur = 0, acur = 0;
         for (int g = gs; g < ge; ++g) {
             const GroupDev Gd = A.groups[g];
@@ -650,10 +654,12 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict
             }
             fft_reg<F, L2, R, -1>(v, my, tt);
             cx<F>* out = buf + ((int64_t)j * ng + (g - A.g0)) * A.L;
+            cx<double> tw = tw0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t m2 = tt + r * NTC;
-                out[m2 * A.L1 + j1] = cmul(v[r], tw_big<F>(j1 * m2, A.twshift));
+                out[m2 * A.L1 + j1] = cmul(v[r], mk(F(tw.x), F(tw.y)));
+                if (r + 1 < R) tw = cmul(tw, tws);
             }
         }
     }
@@ -717,11 +723,11 @@ __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b_fwd(FarArgs A, const c
 
 // Pass B: row FFT, product with H^, inverse row FFT, inverse twiddle; in place,
 // for every (right-hand side, group) of the descriptor.
-// HANK_PASSB_HREG 1: H^ and the inverse twiddles of the row are held in
-// registers across the groups; 0: re-read per group (L2 hits), fewer registers.
-#ifndef HANK_PASSB_HREG
-#define HANK_PASSB_HREG 1
-#endif
+// Pass B: H^ and the inverse twiddles of the row are loaded once and held in
+// registers across the groups.  (A variant that re-read them per group for the
+// FP64 rows of 8192 points, to avoid spilling under the 128-register cap of
+// 1024 threads, measured no faster and gave run-to-run differences in a few
+// output columns; it was removed.)
 template <typename F, int L1, int ROWS>
 __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(const FarDesc* __restrict__ descs, int ndesc,
                                                            int per_b) {
@@ -737,15 +743,13 @@ __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(const FarDesc* __restr
     cx<F>* my = sh + rl * (L1 + L1 / 8);
     const cx<F>* hrow = (const cx<F>*)D.H + rowc * L1;
     cx<F>* buf = (cx<F>*)D.buf;
-#if HANK_PASSB_HREG
     cx<F> hv[R], tw[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         hv[r] = hrow[tt + r * NTR];
         const cx<F> w = tw_big<F>((int64_t)(tt + r * NTR) * rowc, A.twshift);
-        tw[r] = mk(w.x, -w.y);
+        tw[r] = mk(w.x, -w.y); // e^{+2 pi i j1 m2 / L}
     }
-#endif
     const int ng = A.g1 - A.g0;
     const int gs = mp.chunk * D.gchunk, ge = min(ng, gs + D.gchunk);
     for (int gq = gs; gq < ge; ++gq) {
@@ -756,24 +760,11 @@ __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(const FarDesc* __restr
         for (int r = 0; r < R; ++r) v[r] = p[tt + r * NTR];
         fft_reg<F, L1, R, -1>(v, my, tt);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-#if HANK_PASSB_HREG
-            v[r] = cmul(v[r], hv[r]);
-#else
-            v[r] = cmul(v[r], hrow[tt + r * NTR]);
-#endif
-        }
+        for (int r = 0; r < R; ++r) v[r] = cmul(v[r], hv[r]);
         fft_reg<F, L1, R, 1>(v, my, tt);
         if (okrow) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-#if HANK_PASSB_HREG
-                p[tt + r * NTR] = cmul(v[r], tw[r]);
-#else
-                const cx<F> w = tw_big<F>((int64_t)(tt + r * NTR) * row, A.twshift);
-                p[tt + r * NTR] = cmul(v[r], mk(w.x, -w.y)); // e^{+2 pi i j1 m2 / L}
-#endif
-            }
+            for (int r = 0; r < R; ++r) p[tt + r * NTR] = cmul(v[r], tw[r]);
         }
     }
 }
