@@ -389,6 +389,27 @@ def main():
         td = time.perf_counter() - t0
         direct = {"points_per_s": N / td, "ms": td * 1e3, "speedup_fast_vs_direct": value / (N / td)}
 
+    inverse = None
+    if task == "dht0" and args.only == "all":
+        # the inverse DHT of Sec. 6 on the same plan, and the self-inverse
+        # workload of eq. (inverseTest): c~ = dht0(dht0_inverse(c))
+        back = torch.empty_like(c)
+        hank.dht0_inverse(c, eps, out=back)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
+        ev[0].record(stream)
+        for i in range(10):
+            hank.dht0_inverse(c, eps, out=back, stream=stream)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        inv_ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(10))[5]
+        hank.transform(task, back, eps, out=out)
+        torch.cuda.synchronize()
+        inverse = {"ms": inv_ms, "points_per_s": N / (inv_ms * 1e-3),
+                   "roundtrip_max_abs_err": float(torch.max(torch.abs(out - c)).item()),
+                   "c_max_abs": float(torch.max(torch.abs(c)).item())}
+        del back
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -423,7 +444,7 @@ def main():
             "task": task, "N": N, "eps": eps, "blocks": info["nblocks"],
             "near_entries": info["near_entries"], "far_transforms": info["far_transforms"],
             "plan_build_s": plan_s},
-        "roofline": roofline, "cpu_baseline": cpu, "direct_gpu": direct, "kernels": kernels,
+        "roofline": roofline, "cpu_baseline": cpu, "direct_gpu": direct, "inverse_dht": inverse, "kernels": kernels,
         "step_ms": {"median": step_q(0.5), "p90": step_q(0.9), "min": step_ms[0], "max": step_ms[-1]},
         "plan_roofline": plan_roofline,
     }

@@ -254,6 +254,22 @@ typedef struct {
 hank_status hank_plan_block(int32_t task, int64_t N, double eps, const hank_options* options,
                             int32_t k, hank_block_info* out);
 
+/* ---- Inverse DHT (Sec. 6, eqs. (selfinverse) and (inverseTest)) ----------
+ * The DHT is its own inverse up to diagonal scalings as N grows:
+ *     (1/j_{0,N+1}^2) J D_v J D_v ~ I,   J = J_0(j_0 j_0^T / j_{0,N+1}),
+ *     v_n = 2 / J_1(j_{0,n})^2.
+ * hank_dht0_inverse applies c = (1/j_{0,N+1}^2) D_v J D_v f, the inverse of
+ * hank_dht0 in that sense: f and c are device FP64 arrays of N entries that
+ * must not overlap; the transform J runs by the fast method with accuracy eps,
+ * so |c_k - exact_k| = O(eps * v_k/j_{0,N+1}^2 * sum_n v_n |f_n|).  The plan is
+ * hank_dht0's (same cache entry); the call enqueues a scaling, the transform
+ * and a scaling on stream.  Errors as for hank_dht0. */
+hank_status hank_dht0_inverse(const double* f, int64_t N, double eps, double* c, hank_stream_t stream);
+/* v[n-1] = 2 / J_1(j_{0,n})^2 for n = 1..N (the weights above), computed on
+ * the GPU with the roots (J_1 at a root is -J_0' from the last Newton step).
+ * v: device, N doubles.  HANK_EINVAL for a null pointer or N < 1. */
+hank_status hank_dht0_weights(int64_t N, double* v, hank_stream_t stream);
+
 /* ---- Device building blocks, exposed for testing ------------------------- */
 /* b[n-1] = j_{0,n} - (n - 1/4) pi for n = 1..nmax (Lemma 3.2), computed on the
  * GPU by McMahon's expansion and Newton's method.  b: device, nmax doubles. */

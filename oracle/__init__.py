@@ -67,6 +67,8 @@ def _load():
             lib.or_default_threads.restype = i32
             lib.or_hankel_j0.restype = d
             lib.or_hankel_j0.argtypes = [d, i32]
+            lib.or_dht_weights.restype = None
+            lib.or_dht_weights.argtypes = [i64, p, p]
             _lib = lib
     return _lib
 
@@ -150,6 +152,28 @@ def eval_rows(task: str, c: np.ndarray, rows=None, nthreads: int = 0) -> np.ndar
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return out
+
+
+def dht_weights(N: int) -> np.ndarray:
+    """v_n = 2 / J_1(j_{0,n})^2 for n = 1..N (Sec. 6, eq. (selfinverse))."""
+    out = np.empty(int(N), dtype=np.float64)
+    _load().or_dht_weights(int(N), _ptr(root_offsets(N)), _ptr(out))
+    return out
+
+
+def dht0_inverse_rows(f: np.ndarray, rows=None, nthreads: int = 0) -> np.ndarray:
+    """c_k = (v_k / j_{0,N+1}^2) sum_n J_0(j_{0,k} j_{0,n} / j_{0,N+1}) v_n f_n for
+    the 1-based ``rows`` (eq. (inverseTest) applied to f): the DHT's direct sum
+    between the two diagonal scalings."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    N = f.shape[0]
+    v = dht_weights(N)
+    S = roots(N + 1)[-1]
+    if rows is None:
+        rows = np.arange(1, N + 1, dtype=np.int64)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    g = eval_rows("dht0", v * f, rows=rows, nthreads=nthreads)
+    return v[rows - 1] * g / (S * S)
 
 
 def entry(task: str, N: int, k: int, n: int) -> float:

@@ -40,6 +40,10 @@
  *     j_{0,n} = (n - 1/4)*pi + b_n,   0 <= b_n <= 1/(8 (n - 1/4) pi).
  *
  * Sums over n use Neumaier (compensated) summation, n ascending.
+ *
+ * The inverse DHT of Sec. 6 (eq. (inverseTest)), c = (1/j_{0,N+1}^2) D_v J D_v f
+ * with v_n = 2/J_1(j_{0,n})^2, is this same direct sum between two diagonal
+ * scalings (or_dht_weights gives v).
  */
 #include <math.h>
 #include <pthread.h>
@@ -363,6 +367,27 @@ int64_t or_root_offsets(int64_t nmax, double* b) {
         if (!(b[n - 1] >= 0.0)) ++bad;
     }
     return bad;
+}
+
+/* Weights of the self-inverse relation of the DHT (Sec. 6, eq. (selfinverse)):
+ * v[n-1] = 2 / J_1(j_{0,n})^2 for 1 <= n <= N, from the root offsets b.
+ * At z = j_{0,n} = (n - 1/4) pi + b_n the Hankel phase z - 3pi/4 is
+ * (n - 1) pi + b_n, reduced exactly; below z = 20 the series in double-double. */
+void or_dht_weights(int64_t N, const double* b, double* v) {
+    for (int64_t n = 1; n <= N; ++n) {
+        const double bn = b[n - 1];
+        dd z = dd_add(beta_dd(n), dd_from(bn));
+        double j1;
+        if (z.hi < SERIES_ZMAX) {
+            j1 = series_jn(1, z).hi;
+        } else {
+            double P, Q;
+            hankel_pq(1, z.hi, &P, &Q);
+            const double sg = ((n - 1) & 1) ? -1.0 : 1.0;
+            j1 = sg * sqrt(2.0 / (M_PI * z.hi)) * (cos(bn) * P - sin(bn) * Q);
+        }
+        v[n - 1] = 2.0 / (j1 * j1);
+    }
 }
 
 /* ------------------------------------------------------------------ */

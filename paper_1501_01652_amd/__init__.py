@@ -31,7 +31,7 @@ EXPORTS = ["hank_schlomilch", "hank_fourier_bessel", "hank_dht0", "hank_transfor
            "hank_server_create", "hank_server_warm", "hank_server_submit", "hank_server_start",
            "hank_server_drain", "hank_server_status", "hank_server_stats", "hank_server_destroy",
            "hank_batch_graph_create", "hank_batch_graph_launch", "hank_batch_graph_destroy",
-           "hank_autotune", "hank_autotune_reset"]
+           "hank_autotune", "hank_autotune_reset", "hank_dht0_inverse", "hank_dht0_weights"]
 
 
 class HankError(RuntimeError):
@@ -124,6 +124,10 @@ def lib():
                                           ctypes.POINTER(BlockInfo)]
             L.hank_root_offsets.restype = i32
             L.hank_root_offsets.argtypes = [i64, p, p]
+            L.hank_dht0_inverse.restype = i32
+            L.hank_dht0_inverse.argtypes = [p, i64, d, p, p]
+            L.hank_dht0_weights.restype = i32
+            L.hank_dht0_weights.argtypes = [i64, p, p]
             L.hank_j0.restype = i32
             L.hank_j0.argtypes = [p, i64, p, p]
             L.hank_profile.restype = i32
@@ -216,6 +220,27 @@ def dht0(c, eps: float, out=None, stream=None):
     out = _dev_f64(torch.empty_like(c) if out is None else out, "out")
     _check(lib().hank_dht0(ctypes.c_void_p(c.data_ptr()), c.numel(), float(eps),
                            ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def dht0_inverse(f, eps: float, out=None, stream=None):
+    """c = (1/j_{0,N+1}^2) D_v J D_v f with v_n = 2/J_1(j_{0,n})^2: the inverse
+    of dht0 by the self-inverse relation of Sec. 6 (eq. (selfinverse))."""
+    import torch
+    f = _dev_f64(f, "f")
+    out = _dev_f64(torch.empty_like(f) if out is None else out, "out")
+    _check(lib().hank_dht0_inverse(ctypes.c_void_p(f.data_ptr()), f.numel(), float(eps),
+                                   ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def dht0_weights(N: int, out=None, stream=None):
+    """v_n = 2/J_1(j_{0,n})^2 for n = 1..N, computed on the GPU."""
+    import torch
+    if out is None:
+        out = torch.empty(int(N), dtype=torch.float64, device="cuda")
+    out = _dev_f64(out, "out")
+    _check(lib().hank_dht0_weights(int(N), ctypes.c_void_p(out.data_ptr()), _stream(stream)))
     return out
 
 

@@ -80,6 +80,7 @@ struct DevPlan {
     int device = 0;
     double* b = nullptr; // root offsets b_1..b_{N+1}
     double* e = nullptr; // DHT row perturbations e_1..e_N
+    double* v = nullptr; // DHT: v_n = 2/J_1(j_{0,n})^2, n = 1..N (self-inverse weights)
     std::vector<NearTile> tiles; // host copies of the near-field tiles and row tiles
     std::vector<RowTile> rts;
     NearTile* d_tiles = nullptr; // the same on the device
@@ -98,6 +99,7 @@ struct DevPlan {
         };
         fr(b);
         fr(e);
+        fr(v);
         fr(work);
         fr(d_tiles);
         fr(d_rts);
@@ -233,7 +235,8 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
     hank_status st;
     if (g.col_pert || g.row_pert) {
         if ((st = dev_alloc(dp.b, size_t(N + 1), dp.bytes))) return st;
-        HIP_TRY(launch_roots(N + 1, dp.b, s));
+        if (g.row_pert && (st = dev_alloc(dp.v, size_t(N), dp.bytes))) return st;
+        HIP_TRY(launch_roots(N + 1, dp.b, g.row_pert ? N : 0, dp.v, s));
     }
     if (g.row_pert) {
         if ((st = dev_alloc(dp.e, size_t(N), dp.bytes))) return st;
@@ -466,6 +469,7 @@ struct Scratch {
 };
 struct Executor {
     Scratch probs, partial, descs, work, fpart;
+    Scratch inv; // D_v f of the inverse DHT
     hipEvent_t done = nullptr;
     hipStream_t last = nullptr;
     bool used = false;
@@ -1139,6 +1143,36 @@ hank_status hank_dht0(const double* c, int64_t N, double eps, double* out, hank_
     return transform(HANK_TASK_DHT0, c, N, 1, N, eps, out, N, nullptr, stream);
 }
 
+hank_status hank_dht0_inverse(const double* f, int64_t N, double eps, double* c, hank_stream_t stream) {
+    hank_status st = check_args(HANK_TASK_DHT0, f, N, 1, N, eps, c, N);
+    if (st) return st;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    DevPlan* dp = nullptr;
+    if ((st = get_plan(HANK_TASK_DHT0, N, eps, nullptr, s, dp, 1))) return st;
+    if (!g_ex.done) HIP_TRY(hipEventCreateWithFlags(&g_ex.done, hipEventDisableTiming));
+    if (g_ex.used && g_ex.last != s) HIP_TRY(hipStreamWaitEvent(s, g_ex.done, 0));
+    if ((st = ensure(g_ex.inv, size_t(N) * sizeof(double), s))) return st;
+    double* w = static_cast<double*>(g_ex.inv.p);
+    HIP_TRY(launch_dht_scale(N, dp->v, dp->b, f, w, false, s)); // D_v f
+    std::vector<Job> jobs{Job{dp, w, N, c, N, 1}};
+    if ((st = run_jobs(jobs, s))) return st;                   // J_0(...) D_v f
+    HIP_TRY(launch_dht_scale(N, dp->v, dp->b, c, c, true, s)); // D_v ... / j_{0,N+1}^2
+    HIP_TRY(hipEventRecord(g_ex.done, s));
+    return HANK_OK;
+}
+
+hank_status hank_dht0_weights(int64_t N, double* v, hank_stream_t stream) {
+    if (!v || N < 1) return fail(HANK_EINVAL, "bad arguments");
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hank_status st = ensure_tables(dev);
+    if (st) return st;
+    HIP_TRY(launch_roots(N, nullptr, N, v, (hipStream_t)stream));
+    return HANK_OK;
+}
+
 hank_status hank_transform(int32_t task, const double* c, int64_t N, int64_t nrhs, int64_t ldc, double eps,
                            double* out, int64_t ldo, const hank_options* options, hank_stream_t stream) {
     return transform(task, c, N, nrhs, ldc, eps, out, ldo, options, stream);
@@ -1558,7 +1592,7 @@ hank_status hank_root_offsets(int64_t nmax, double* b, hank_stream_t stream) {
     HIP_TRY(hipGetDevice(&dev));
     hank_status st = ensure_tables(dev);
     if (st) return st;
-    HIP_TRY(launch_roots(nmax, b, (hipStream_t)stream));
+    HIP_TRY(launch_roots(nmax, b, 0, nullptr, (hipStream_t)stream));
     return HANK_OK;
 }
 

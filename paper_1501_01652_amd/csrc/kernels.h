@@ -114,7 +114,13 @@ struct FarDesc {
 };
 
 hipError_t upload_tables(const DeviceTables& t);
-hipError_t launch_roots(int64_t nmax, double* b, hipStream_t s);
+// b[n-1] = j_{0,n} - (n-1/4) pi for n <= nmax (b may be null) and, if v is
+// given, v[n-1] = 2/J_1(j_{0,n})^2 for n <= nv (nv <= nmax)
+hipError_t launch_roots(int64_t nmax, double* b, int64_t nv, double* v, hipStream_t s);
+// dst = src * v elementwise (N entries), also divided by j_{0,N+1}^2 when final
+// (b holds N+1 root offsets); dst may equal src
+hipError_t launch_dht_scale(int64_t N, const double* v, const double* b, const double* src, double* dst,
+                            bool final, hipStream_t s);
 hipError_t launch_dht_e(int64_t N, const double* b, double* e, hipStream_t s);
 hipError_t launch_j0(const double* z, int64_t n, double* out, hipStream_t s);
 // Near field of nprob transforms with ntiles tiles in all: single

@@ -36,7 +36,10 @@ __device__ __forceinline__ void j0_taylor_piece(int i, double dz, double* J, dou
     *dJ = d;
 }
 
-__global__ void k_roots(int64_t nmax, double* b) {
+// b[n-1] for n <= nmax (if b is given) and, for n <= nv, the weights
+// v[n-1] = 2 / J_1(j_{0,n})^2 of the self-inverse relation of the DHT (Sec. 6):
+// J_1 at the root is -J_0' there, the by-product of the last Newton step.
+__global__ void k_roots(int64_t nmax, double* b, int64_t nv, double* v) {
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
     if (n > nmax) return;
     const double beta = ((double)n - 0.25) * M_PI;
@@ -59,6 +62,15 @@ __global__ void k_roots(int64_t nmax, double* b) {
             j0_taylor_piece(i, dz, &J, &dJ);
             x -= J / dJ;
         }
+        if (v && n <= nv) {
+            const double z = beta + x;
+            int i = (int)((z - J0_TAYLOR_Z0) * (1.0 / J0_TAYLOR_H));
+            i = i < 0 ? 0 : (i >= J0_TAYLOR_INTERVALS ? J0_TAYLOR_INTERVALS - 1 : i);
+            const double zc = J0_TAYLOR_Z0 + (i + 0.5) * J0_TAYLOR_H;
+            double J, dJ;
+            j0_taylor_piece(i, (beta - zc) + (beta_lo + x), &J, &dJ);
+            v[n - 1] = 2.0 / (dJ * dJ);
+        }
     } else {
         // J_0 ~ A(-1)^n (P0 sin b + Q0 cos b), J_1 ~ A(-1)^n (-P1 cos b + Q1 sin b)
         // (eq. (HankelExpansion) at z = (n-1/2)pi + b + pi/4); Newton: b += J_0/J_1
@@ -71,8 +83,31 @@ __global__ void k_roots(int64_t nmax, double* b) {
             sincos_small(x, &s, &c);
             x += (P0 * s + Q0 * c) / (-P1 * c + Q1 * s);
         }
+        if (v && n <= nv) {
+            // |J_1(z)| = sqrt(2/(pi z)) |P1 cos x - Q1 sin x| at z = (n - 1/4) pi + x
+            const double z = beta + x, zi = 1.0 / z;
+            double P1, Q1, s, c;
+            hankel_pq(1, zi, hankel_terms_for(z), &P1, &Q1);
+            sincos_small(x, &s, &c);
+            const double a = P1 * c - Q1 * s;
+            v[n - 1] = M_PI * z / (a * a);
+        }
     }
-    b[n - 1] = x;
+    if (b) b[n - 1] = x;
+}
+
+// dst[i] = src[i] v[i] for i < N, times 1/j_{0,N+1}^2 (j_{0,N+1} = (N + 3/4) pi
+// + b[N]) when final is set: the diagonal factors of the self-inverse relation
+__global__ void k_dht_scale(int64_t N, const double* __restrict__ v, const double* b, const double* src,
+                            double* dst, int final) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double w = v[i];
+    if (final) {
+        const double S = ((double)N + 0.75) * M_PI + b[N];
+        w /= S * S;
+    }
+    dst[i] = src[i] * w;
 }
 
 __global__ void k_dht_e(int64_t N, const double* b, double* e) {
@@ -874,9 +909,17 @@ hipError_t upload_tables(const DeviceTables& t) {
     return hipMemcpyToSymbol(HIP_SYMBOL(g_tab), &t, sizeof(DeviceTables), 0, hipMemcpyHostToDevice);
 }
 
-hipError_t launch_roots(int64_t nmax, double* b, hipStream_t s) {
+hipError_t launch_roots(int64_t nmax, double* b, int64_t nv, double* v, hipStream_t s) {
     if (nmax <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_roots, dim3((unsigned)((nmax + 255) / 256)), dim3(256), 0, s, nmax, b);
+    hipLaunchKernelGGL(k_roots, dim3((unsigned)((nmax + 255) / 256)), dim3(256), 0, s, nmax, b, nv, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_dht_scale(int64_t N, const double* v, const double* b, const double* src, double* dst,
+                            bool final, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dht_scale, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, v, b, src, dst,
+                       final ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -91,6 +91,22 @@ def test_dht0_2pow20_single_partition():
     check("dht0", N, eps, c, rows, "single partition", plan_mode=2)
 
 
+def test_dht0_inverse_2pow20():
+    """The inverse DHT (Sec. 6) at N = 2^20, eps = 1e-8, on sampled rows; per
+    row |c - oracle| <= C eps v_k/j_{0,N+1}^2 sum_n v_n |f_n|."""
+    N, eps = 1 << 20, 1e-8
+    f = inputs.workload("dht0", N)
+    rows = inputs.sampled_rows(N, 48, boundary_rows("dht0", N, eps))
+    got = host(hank.dht0_inverse(dev(f), eps))[rows - 1]
+    ref = oracle.dht0_inverse_rows(f, rows=rows)
+    v = oracle.dht_weights(N)
+    S = oracle.roots(N + 1)[-1]
+    bound = C_TOL * eps * (v[rows - 1] / S ** 2) * np.sum(v * np.abs(f))
+    ratio = float(np.max(np.abs(got - ref) / bound))
+    print("dht0 inverse N=2^20 eps=%g rows=%d error / bound %.3g" % (eps, len(rows), ratio))
+    assert ratio <= 1.0
+
+
 def test_dht0_2pow20_one_hot_columns():
     """c = e_n at the columns bordering every block: f_k = J_0(r_k w_n) for all k."""
     N, eps = 1 << 20, 1e-8

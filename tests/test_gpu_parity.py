@@ -294,3 +294,63 @@ def test_autotuned_splits_keep_parity():
     finally:
         hank.autotune_reset()
         hank.cache_clear()
+
+
+def test_device_dht_weights_match_oracle():
+    """v_n = 2/J_1(j_{0,n})^2 from the device roots kernel against the oracle."""
+    N = 1 << 20
+    got = host(hank.dht0_weights(N))
+    ref = oracle.dht_weights(N)
+    rel = float(np.max(np.abs(got / ref - 1)))
+    print("dht weights N=%d max relative error %.3g" % (N, rel))
+    assert rel <= 1e-13
+
+
+def _inverse_bound(f, eps):
+    N = f.shape[0]
+    v = oracle.dht_weights(N)
+    S = oracle.roots(N + 1)[-1]
+    # the transform between the scalings is accurate to C eps sum_n v_n |f_n|
+    return C_TOL * eps * (v / S ** 2) * np.sum(v * np.abs(f))
+
+
+@pytest.mark.parametrize("N", [1, 2, 17, 100, 700, 2500])
+@pytest.mark.parametrize("eps", [1e-4, 1e-8, 1e-14])
+def test_dht0_inverse_parity(N, eps):
+    """c = (1/j_{0,N+1}^2) D_v J D_v f (Sec. 6) against the oracle, per row."""
+    f = inputs.coefficients("gauss", N, 7000 + N)
+    ref = oracle.dht0_inverse_rows(f)
+    got = host(hank.dht0_inverse(dev(f), eps))
+    bound = _inverse_bound(f, eps) + 1e-15 * np.abs(ref)
+    ratio = float(np.max(np.abs(got - ref) / bound))
+    print("dht0 inverse N=%d eps=%g error / bound %.3g" % (N, eps, ratio))
+    assert ratio <= 1.0
+
+
+def test_dht0_inverse_roundtrip():
+    """Eq. (inverseTest): c~ = dht0(dht0_inverse(c)) on the GPU against the same
+    composition in the oracle; c~ - c itself is reported (the relation is
+    asymptotic)."""
+    N, eps = 4096, 1e-14
+    c = inputs.coefficients("gauss", N, 77)
+    g_ref = oracle.dht0_inverse_rows(c)
+    ref = oracle.eval_rows("dht0", g_ref)
+    ct = host(hank.dht0(hank.dht0_inverse(dev(c), eps), eps))
+    tol = C_TOL * eps * np.sum(np.abs(g_ref)) + N * float(np.max(_inverse_bound(c, eps)))
+    err = float(np.max(np.abs(ct - ref)))
+    print("dht0 round trip N=%d: |gpu - oracle| %.3g (bound %.3g), |c~ - c| %.3g" %
+          (N, err, tol, float(np.max(np.abs(ct - c)))))
+    assert err <= tol
+
+
+def test_dht0_inverse_errors_leave_output_untouched():
+    import ctypes
+    f = dev(np.ones(64))
+    out = dev(np.full(64, np.nan))
+    L = hank.lib()
+    assert L.hank_dht0_inverse(ctypes.c_void_p(f.data_ptr()), 64, 0.0, ctypes.c_void_p(out.data_ptr()), None) == 1
+    assert L.hank_dht0_inverse(ctypes.c_void_p(f.data_ptr()), 64, 1e-8,
+                               ctypes.c_void_p(f.data_ptr() + 8 * 10), None) == 1  # overlap
+    assert L.hank_dht0_inverse(None, 64, 1e-8, ctypes.c_void_p(out.data_ptr()), None) == 1
+    assert L.hank_dht0_weights(0, ctypes.c_void_p(out.data_ptr()), None) == 1
+    assert np.all(np.isnan(host(out)))

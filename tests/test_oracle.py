@@ -146,3 +146,40 @@ def test_rejects_bad_arguments():
         oracle.eval_rows("schlomilch", np.ones(1))
     with pytest.raises(ValueError):
         oracle.eval_rows("dht0", np.ones(4), rows=[5])
+
+
+def test_dht_weights_against_mpmath():
+    """v_n = 2/J_1(j_{0,n})^2 (Sec. 6, eq. (selfinverse)) against mpmath's own
+    zeros and J_1 at 50-digit precision, on both sides of the series/Hankel
+    switch at z = 20 and for a large root."""
+    N = 40
+    v = oracle.dht_weights(N)
+    mpmath.mp.dps = 50
+    for n in list(range(1, 13)) + [25, 40]:
+        ref = 2 / mpmath.besselj(1, mpmath.besseljzero(0, n)) ** 2
+        assert abs(v[n - 1] / float(ref) - 1) < 4e-15, n
+    big = oracle.dht_weights(5000)[-1]
+    ref = 2 / mpmath.besselj(1, mpmath.besseljzero(0, 5000)) ** 2
+    assert abs(big / float(ref) - 1) < 1e-14
+
+
+@pytest.mark.parametrize("N,bound", [(25, 2e-7), (100, 1e-9), (400, 5e-11)])
+def test_dht_self_inverse(N, bound):
+    """Eq. (selfinverse): (1/j_{0,N+1}^2) J D_v J D_v -> I.  With the oracle's
+    forward sums and its inverse, both compositions return Gaussian c to an
+    error that falls quickly with N (measured about 9e-8, 3e-10 and 9e-12; any
+    dropped factor, a wrong power of J_1 or of j_{0,N+1}, or j_{0,N} in place of
+    j_{0,N+1} gives errors of order 1e-2 or more)."""
+    c = np.random.default_rng(N).standard_normal(N)
+    back = oracle.dht0_inverse_rows(oracle.eval_rows("dht0", c))
+    assert np.max(np.abs(back - c)) < bound
+    again = oracle.eval_rows("dht0", oracle.dht0_inverse_rows(c))  # eq. (inverseTest)
+    assert np.max(np.abs(again - c)) < bound
+
+
+def test_dht_inverse_rows_subset():
+    """Selected rows equal the same rows of the full inverse."""
+    f = np.random.default_rng(3).standard_normal(300)
+    full = oracle.dht0_inverse_rows(f)
+    rows = np.array([1, 2, 150, 299, 300])
+    assert np.array_equal(oracle.dht0_inverse_rows(f, rows=rows), full[rows - 1])
