@@ -102,7 +102,8 @@ struct CostModel {
     double near_entry = 2.9e-12;     // per directly summed entry, one right-hand side (measured)
     double near_multi_entry = 4.2e-12; // per entry with several right-hand sides (J_0 once per entry)
     double near_rhs = 4.5e-14;       // per entry and right-hand side of the product (FP64 MFMA)
-    double block = 20e-6;            // fixed cost per block (three launches)
+    double block = 50e-6;            // fixed cost per block: three dependent launches and a reduce
+                                     // (measured on single transforms, N = 3000..50000)
 };
 
 // ---- parameter formulas ----
