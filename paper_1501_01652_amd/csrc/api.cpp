@@ -467,9 +467,19 @@ struct Scratch {
     void* p = nullptr;
     size_t bytes = 0;
 };
+// Host copies of uploaded descriptors stay alive until the stream has consumed
+// them: a ring of slots, each reused only after its upload event completed.
+struct UploadSlot {
+    std::vector<NearProb> probs;
+    std::vector<FarDesc> descs;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
 struct Executor {
     Scratch probs, partial, descs, work, fpart;
     Scratch inv; // D_v f of the inverse DHT
+    UploadSlot slots[4];
+    int next_slot = 0;
     hipEvent_t done = nullptr;
     hipStream_t last = nullptr;
     bool used = false;
@@ -786,8 +796,16 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
     add(PR.probs.data(), PR.probs.size() * sizeof(NearProb));
     add(PR.descs.data(), PR.descs.size() * sizeof(FarDesc));
     if (sig != g_ex.sig) {
-        if ((st = upload(g_ex.probs, PR.probs, s))) return st;
-        if ((st = upload(g_ex.descs, PR.descs, s))) return st;
+        UploadSlot& u = g_ex.slots[g_ex.next_slot];
+        g_ex.next_slot = (g_ex.next_slot + 1) % 4;
+        if (!u.done) HIP_TRY(hipEventCreateWithFlags(&u.done, hipEventDisableTiming));
+        if (u.pending) HIP_TRY(hipEventSynchronize(u.done));
+        u.probs = PR.probs;
+        u.descs = PR.descs;
+        if ((st = upload(g_ex.probs, u.probs, s))) return st;
+        if ((st = upload(g_ex.descs, u.descs, s))) return st;
+        HIP_TRY(hipEventRecord(u.done, s));
+        u.pending = true;
         g_ex.sig.swap(sig);
     }
     const NearProb* dprobs = static_cast<const NearProb*>(g_ex.probs.p);
