@@ -67,6 +67,12 @@ def _load():
             lib.or_default_threads.restype = i32
             lib.or_hankel_j0.restype = d
             lib.or_hankel_j0.argtypes = [d, i32]
+            lib.or_jn.restype = d
+            lib.or_jn.argtypes = [i32, d]
+            lib.or_eval_rows_nu.restype = i32
+            lib.or_eval_rows_nu.argtypes = [i32, i32, i64, i64, p, p, i64, p, p, i32]
+            lib.or_entry_nu.restype = d
+            lib.or_entry_nu.argtypes = [i32, i32, i64, i64, p, i64, i64]
             lib.or_dht_weights.restype = None
             lib.or_dht_weights.argtypes = [i64, p, p]
             _lib = lib
@@ -134,8 +140,16 @@ def default_threads() -> int:
     return int(_load().or_default_threads())
 
 
-def eval_rows(task: str, c: np.ndarray, rows=None, nthreads: int = 0) -> np.ndarray:
-    """f_k for the 1-based ``rows`` (all rows when None) by direct summation."""
+def jn(nu: int, z):
+    """J_nu(z) for integer 0 <= nu <= 12 (elementwise)."""
+    lib = _load()
+    return np.array([lib.or_jn(int(nu), float(x)) for x in np.atleast_1d(z)])
+
+
+def eval_rows(task: str, c: np.ndarray, rows=None, nthreads: int = 0, nu: int = 0,
+              shift: int = 0) -> np.ndarray:
+    """f_k for the 1-based ``rows`` (all rows when None) by direct summation;
+    for the Schlomilch tasks optionally of order nu with w_n = (n + shift) pi."""
     lib = _load()
     c = np.ascontiguousarray(c, dtype=np.float64)
     N = c.shape[0]
@@ -147,8 +161,8 @@ def eval_rows(task: str, c: np.ndarray, rows=None, nthreads: int = 0) -> np.ndar
         rows = np.arange(1, N + 1, dtype=np.int64)
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     out = np.empty(rows.shape[0], dtype=np.float64)
-    rc = lib.or_eval_rows(t, N, _ptr(c), _ptr(b), rows.shape[0], _ptr(rows), _ptr(out),
-                          int(nthreads))
+    rc = lib.or_eval_rows_nu(t, int(nu), int(shift), N, _ptr(c), _ptr(b), rows.shape[0], _ptr(rows),
+                             _ptr(out), int(nthreads))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return out
@@ -176,8 +190,8 @@ def dht0_inverse_rows(f: np.ndarray, rows=None, nthreads: int = 0) -> np.ndarray
     return v[rows - 1] * g / (S * S)
 
 
-def entry(task: str, N: int, k: int, n: int) -> float:
-    """J_0(r_k w_n) for one matrix entry."""
+def entry(task: str, N: int, k: int, n: int, nu: int = 0, shift: int = 0) -> float:
+    """J_nu(r_k w_n) for one matrix entry (nu, shift: Schlomilch tasks only)."""
     t = TASKS[task]
     b = root_offsets(N + 1) if t in (1, 2, 4) else None
-    return _load().or_entry(t, int(N), _ptr(b), int(k), int(n))
+    return _load().or_entry_nu(t, int(nu), int(shift), int(N), _ptr(b), int(k), int(n))

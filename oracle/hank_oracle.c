@@ -41,6 +41,10 @@
  *
  * Sums over n use Neumaier (compensated) summation, n ascending.
  *
+ * For the Schlomilch tasks the sum may also be of order nu > 0 with
+ * w_n = (n + shift) pi (Sec. 4, Remark 4.1): f_k = sum_n c_n J_nu(r_k w_n), with
+ * J_nu from the same two expansions (series below z = 20 + nu/2).
+ *
  * The inverse DHT of Sec. 6 (eq. (inverseTest)), c = (1/j_{0,N+1}^2) D_v J D_v f
  * with v_n = 2/J_1(j_{0,n})^2, is this same direct sum between two diagonal
  * scalings (or_dht_weights gives v).
@@ -112,11 +116,12 @@ static const dd DD_PI = {3.141592653589793116, 1.2246467991473532e-16};
 /* ------------------------------------------------------------------ */
 /* Taylor series (Sec. 3.2), double-double                             */
 /* ------------------------------------------------------------------ */
-/* J_nu(z) = sum_t (-1)^t (z/2)^(2t+nu) / (t! (t+nu)!), nu = 0 or 1. */
+/* J_nu(z) = sum_t (-1)^t (z/2)^(2t+nu) / (t! (t+nu)!), integer nu >= 0. */
 static dd series_jn(int nu, dd z) {
     dd h = dd_mul_d(z, 0.5);
     dd w = dd_mul(h, h);              /* z^2/4 */
-    dd term = nu ? h : dd_from(1.0);  /* t = 0 term */
+    dd term = dd_from(1.0);           /* t = 0 term: (z/2)^nu / nu! */
+    for (int i = 1; i <= nu; ++i) term = dd_div_d(dd_mul(term, h), (double)i);
     dd sum = term;
     for (int t = 1; t < 200; ++t) {
         term = dd_mul(term, w);
@@ -207,14 +212,22 @@ static dd arg_phase(const arg_t* a, int nu) {
 
 #define SERIES_ZMAX 20.0
 
-static double j0_arg(const arg_t* a) {
+/* Series below z = 20 + nu/2, Hankel above: with 2*12 terms the remainder
+ * bound of (errorBound) is below 1e-17 from z = 19.9 (nu = 0) to 22.2 (nu = 8)
+ * and 25.5 (nu = 12); the largest series term there is below 1e8, so the
+ * double-double sum keeps 1e-23. */
+static double series_zmax(int nu) { return SERIES_ZMAX + 0.5 * nu; }
+
+static double jn_arg(int nu, const arg_t* a) {
     dd z = arg_value(a);
-    if (z.hi < SERIES_ZMAX) return series_jn(0, z).hi;
+    if (z.hi < series_zmax(nu)) return series_jn(nu, z).hi;
     double P, Q, s, c;
-    hankel_pq(0, z.hi, &P, &Q);
-    dd_sincos(arg_phase(a, 0), &s, &c);
+    hankel_pq(nu, z.hi, &P, &Q);
+    dd_sincos(arg_phase(a, nu), &s, &c);
     return sqrt(2.0 / (M_PI * z.hi)) * (c * P - s * Q);
 }
+
+static double j0_arg(const arg_t* a) { return jn_arg(0, a); }
 
 /* an arbitrary double z as an exact argument: I/D = 0, delta = z */
 static arg_t arg_plain(double z) {
@@ -227,6 +240,14 @@ double or_j0(double z) {
     z = fabs(z);
     arg_t a = arg_plain(z);
     return j0_arg(&a);
+}
+
+/* J_nu at a plain argument, integer 0 <= nu <= 12 */
+double or_jn(int nu, double z) {
+    if (nu < 0 || nu > 12) return NAN;
+    z = fabs(z);
+    arg_t a = arg_plain(z);
+    return jn_arg(nu, &a);
 }
 
 double or_j0_phase(int64_t I, int64_t D, double dhi, double dlo) {
@@ -397,6 +418,8 @@ enum { T_SCHL = 0, T_FB = 1, T_DHT = 2, T_SCHL_PG = 3, T_FB_PG = 4 };
 
 typedef struct {
     int task;
+    int nu;        /* Bessel order (Schlomilch tasks; 0 otherwise) */
+    int64_t shift; /* w_n = (n + shift) pi (Schlomilch tasks) */
     int64_t N;
     const double* c;
     const double* b; /* root offsets b_1..b_{N+1} (tasks 1, 2, 4) */
@@ -414,13 +437,13 @@ static arg_t make_arg(const job_t* J, int64_t k, int64_t n) {
     int64_t N = J->N;
     arg_t a;
     switch (J->task) {
-    case T_SCHL: /* (k-1) n pi / (N-1) */
-        a.I = (k - 1) * n;
+    case T_SCHL: /* (k-1) (n + shift) pi / (N-1) */
+        a.I = (k - 1) * (n + J->shift);
         a.D = N - 1;
         a.delta = dd_from(0.0);
         break;
-    case T_SCHL_PG: /* k n pi / N */
-        a.I = k * n;
+    case T_SCHL_PG: /* k (n + shift) pi / N */
+        a.I = k * (n + J->shift);
         a.D = N;
         a.delta = dd_from(0.0);
         break;
@@ -455,7 +478,7 @@ static double row_sum(const job_t* J, int64_t k) {
         int64_t n = J->nz[i];
         double cn = J->c[n - 1];
         arg_t a = make_arg(J, k, n);
-        double t = cn * j0_arg(&a);
+        double t = cn * jn_arg(J->nu, &a);
         double u = s + t;
         if (fabs(s) >= fabs(t))
             comp += (s - u) + t;
@@ -483,12 +506,15 @@ int or_default_threads(void) {
     return n > 0 ? (int)n : 1;
 }
 
-/* f_k for the 1-based rows[i], written to out[i].  b holds b_1..b_{N+1}
- * (ignored by the Schlomilch tasks, may be NULL there).  Returns 0, or -1 on
- * bad arguments. */
-int or_eval_rows(int task, int64_t N, const double* c, const double* b, int64_t nrows,
-                 const int64_t* rows, double* out, int nthreads) {
+/* f_k for the 1-based rows[i], written to out[i], with J_nu in place of J_0
+ * and w_n = (n + shift) pi for the Schlomilch tasks (Sec. 4 and Remark 4.1;
+ * nu = shift = 0 for the others).  b holds b_1..b_{N+1} (ignored by the
+ * Schlomilch tasks, may be NULL there).  Returns 0, or -1 on bad arguments. */
+int or_eval_rows_nu(int task, int nu, int64_t shift, int64_t N, const double* c, const double* b,
+                    int64_t nrows, const int64_t* rows, double* out, int nthreads) {
     if (N < 1 || !c || !rows || !out || nrows < 0) return -1;
+    if (nu < 0 || nu > 12 || shift < 0 || shift > 1024) return -1;
+    if ((nu || shift) && task != T_SCHL && task != T_SCHL_PG) return -1;
     if ((task == T_SCHL || task == T_FB) && N < 2) return -1;
     if (task != T_SCHL && task != T_SCHL_PG && !b) return -1;
     if (task < 0 || task > 4) return -1;
@@ -503,6 +529,8 @@ int or_eval_rows(int task, int64_t N, const double* c, const double* b, int64_t 
     J.nz = nz;
     J.nnz = nnz;
     J.task = task;
+    J.nu = nu;
+    J.shift = shift;
     J.N = N;
     J.c = c;
     J.b = b;
@@ -521,13 +549,24 @@ int or_eval_rows(int task, int64_t N, const double* c, const double* b, int64_t 
     return 0;
 }
 
-/* J_0(r_k w_n) for one entry (used by the one-hot pins). */
-double or_entry(int task, int64_t N, const double* b, int64_t k, int64_t n) {
+int or_eval_rows(int task, int64_t N, const double* c, const double* b, int64_t nrows,
+                 const int64_t* rows, double* out, int nthreads) {
+    return or_eval_rows_nu(task, 0, 0, N, c, b, nrows, rows, out, nthreads);
+}
+
+/* J_nu(r_k w_n) for one entry (used by the one-hot pins). */
+double or_entry_nu(int task, int nu, int64_t shift, int64_t N, const double* b, int64_t k, int64_t n) {
     job_t J;
     memset(&J, 0, sizeof J);
     J.task = task;
+    J.nu = nu;
+    J.shift = shift;
     J.N = N;
     J.b = b;
     arg_t a = make_arg(&J, k, n);
-    return j0_arg(&a);
+    return jn_arg(nu, &a);
+}
+
+double or_entry(int task, int64_t N, const double* b, int64_t k, int64_t n) {
+    return or_entry_nu(task, 0, 0, N, b, k, n);
 }

@@ -183,3 +183,56 @@ def test_dht_inverse_rows_subset():
     full = oracle.dht0_inverse_rows(f)
     rows = np.array([1, 2, 150, 299, 300])
     assert np.array_equal(oracle.dht0_inverse_rows(f, rows=rows), full[rows - 1])
+
+
+@pytest.mark.parametrize("nu", [1, 2, 3, 5, 8])
+def test_jn_against_mpmath(nu):
+    """J_nu (Schlomilch of order nu, Sec. 4) against mpmath at 40 digits: dense
+    on [0, 60], on both sides of the series/Hankel switch at z = 20 + nu/2,
+    and at large arguments."""
+    mpmath.mp.dps = 40
+    zs = list(np.linspace(0.0, 60.0, 601)) + [20 + nu / 2 - 1e-9, 20 + nu / 2 + 1e-9, 347.25, 98765.4]
+    worst = max(abs(oracle.jn(nu, z)[0] - float(mpmath.besselj(nu, z))) for z in zs)
+    assert worst < 1.5e-16
+
+
+def test_jn_order_zero_matches_j0():
+    z = np.linspace(0.0, 80.0, 801)
+    assert np.array_equal(oracle.jn(0, z), oracle.j0(z))
+
+
+@pytest.mark.parametrize("task", ["schlomilch", "schlomilch_paper_grid"])
+@pytest.mark.parametrize("nu,shift", [(1, 0), (2, 2), (5, 0), (8, 8), (0, 3)])
+def test_bruteforce_order_nu_against_mpmath(task, nu, shift):
+    """f_k = sum_n c_n J_nu(r_k (n + shift) pi) (Sec. 4, Remark 4.1) at N = 2
+    and 13 against mpmath sums."""
+    mpmath.mp.dps = 40
+    for N in (2, 13):
+        c = np.random.default_rng(100 * nu + shift + N).standard_normal(N)
+        ref = []
+        for k in range(1, N + 1):
+            r = mpmath.mpf(k - 1) / (N - 1) if task == "schlomilch" else mpmath.mpf(k) / N
+            ref.append(float(mpmath.fsum(mpmath.mpf(float(c[n - 1])) * mpmath.besselj(nu, r * (n + shift) * mpmath.pi)
+                                         for n in range(1, N + 1))))
+        got = oracle.eval_rows(task, c, nu=nu, shift=shift)
+        assert np.max(np.abs(got - np.array(ref))) <= 4e-16 * np.sum(np.abs(c))
+
+
+def test_order_nu_exact_phase_at_full_size():
+    """Single order-nu entries at N = 2^20 (z up to ~3.3e6), phase reduced
+    exactly, against mpmath."""
+    mpmath.mp.dps = 40
+    N = 1 << 20
+    rng = np.random.default_rng(5)
+    for nu, shift in ((3, 3), (8, 0)):
+        for _ in range(20):
+            k, n = (int(x) for x in rng.integers(1, N + 1, 2))
+            ref = mpmath.besselj(nu, mpmath.mpf(k) * (n + shift) * mpmath.pi / N)
+            assert abs(oracle.entry("schlomilch_paper_grid", N, k, n, nu=nu, shift=shift) - float(ref)) < 2e-16
+
+
+def test_order_nu_rejected_outside_schlomilch():
+    with pytest.raises(ValueError):
+        oracle.eval_rows("dht0", np.ones(4), nu=1)
+    with pytest.raises(ValueError):
+        oracle.eval_rows("schlomilch", np.ones(4), nu=13)
