@@ -43,7 +43,7 @@ class HankError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("plan_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("direct", ctypes.c_int32), ("prefer_far", ctypes.c_int32), ("nrhs", ctypes.c_int32),
-                ("M", ctypes.c_int32)]
+                ("M", ctypes.c_int32), ("nu", ctypes.c_int32), ("shift", ctypes.c_int32)]
 
 
 class PlanSummary(ctypes.Structure):
@@ -151,8 +151,9 @@ def _task(task) -> int:
     return TASKS[task] if isinstance(task, str) else int(task)
 
 
-def _options(plan_mode=0, precision=0, direct=0, prefer_far=0, nrhs=0, M=0) -> Options:
-    return Options(int(plan_mode), int(precision), int(direct), int(prefer_far), int(nrhs), int(M))
+def _options(plan_mode=0, precision=0, direct=0, prefer_far=0, nrhs=0, M=0, nu=0, shift=0) -> Options:
+    return Options(int(plan_mode), int(precision), int(direct), int(prefer_far), int(nrhs), int(M), int(nu),
+                   int(shift))
 
 
 def _stream(stream):
@@ -174,10 +175,11 @@ def _dev_f64(t, name):
 
 
 def transform(task, c, eps: float, out=None, plan_mode: int = 0, precision: int = 0,
-              direct: int = 0, prefer_far: int = 0, stream=None, M: int = 0):
+              direct: int = 0, prefer_far: int = 0, stream=None, M: int = 0, nu: int = 0, shift: int = 0):
     """f = J_0(r w^T) c for c of shape (N,) or (nrhs, N) (one right-hand side per row).
     plan_mode 0 tuned, 1 paper, 2 paper with one far block; M overrides the
-    paper's number of asymptotic terms in modes 1 and 2."""
+    paper's number of asymptotic terms in modes 1 and 2.  Schlomilch tasks:
+    order nu (J_nu) and w_n = (n + shift) pi."""
     import torch
     c = _dev_f64(c, "c")
     if out is None:
@@ -187,7 +189,7 @@ def transform(task, c, eps: float, out=None, plan_mode: int = 0, precision: int 
         raise ValueError("out must have the shape of c")
     N = c.shape[-1]
     nrhs = 1 if c.dim() == 1 else c.shape[0]
-    opts = _options(plan_mode, precision, direct, prefer_far, 0, M)
+    opts = _options(plan_mode, precision, direct, prefer_far, 0, M, nu, shift)
     _check(lib().hank_transform(_task(task), ctypes.c_void_p(c.data_ptr()), N, nrhs, N, float(eps),
                                 ctypes.c_void_p(out.data_ptr()), N, ctypes.byref(opts), _stream(stream)))
     return out
@@ -307,27 +309,28 @@ class BatchGraph:
 
 
 def plan_info(task, N: int, eps: float, plan_mode: int = 0, precision: int = 0, direct: int = 0,
-              prefer_far: int = 0, nrhs: int = 1, M: int = 0) -> dict:
+              prefer_far: int = 0, nrhs: int = 1, M: int = 0, nu: int = 0, shift: int = 0) -> dict:
     """Parameters and costs of the plan the library would use for nrhs
     right-hand sides (host only)."""
     s = PlanSummary()
-    opts = _options(plan_mode, precision, direct, prefer_far, nrhs, M)
+    opts = _options(plan_mode, precision, direct, prefer_far, nrhs, M, nu, shift)
     _check(lib().hank_plan_info(_task(task), int(N), float(eps), ctypes.byref(opts), ctypes.byref(s)))
     return {name: getattr(s, name) for name, _ in PlanSummary._fields_}
 
 
 def plan_block(task, N: int, eps: float, k: int, plan_mode: int = 0, precision: int = 0,
-               prefer_far: int = 0, nrhs: int = 1, M: int = 0) -> dict:
+               prefer_far: int = 0, nrhs: int = 1, M: int = 0, nu: int = 0, shift: int = 0) -> dict:
     b = BlockInfo()
-    opts = _options(plan_mode, precision, 0, prefer_far, nrhs, M)
+    opts = _options(plan_mode, precision, 0, prefer_far, nrhs, M, nu, shift)
     _check(lib().hank_plan_block(_task(task), int(N), float(eps), ctypes.byref(opts), int(k), ctypes.byref(b)))
     return {name: getattr(b, name) for name, _ in BlockInfo._fields_}
 
 
 def plan_blocks(task, N: int, eps: float, plan_mode: int = 0, precision: int = 0,
-                prefer_far: int = 0, nrhs: int = 1, M: int = 0) -> list:
-    n = plan_info(task, N, eps, plan_mode, precision, prefer_far=prefer_far, nrhs=nrhs, M=M)["nblocks"]
-    return [plan_block(task, N, eps, k, plan_mode, precision, prefer_far, nrhs, M) for k in range(n)]
+                prefer_far: int = 0, nrhs: int = 1, M: int = 0, nu: int = 0, shift: int = 0) -> list:
+    n = plan_info(task, N, eps, plan_mode, precision, prefer_far=prefer_far, nrhs=nrhs, M=M, nu=nu,
+                  shift=shift)["nblocks"]
+    return [plan_block(task, N, eps, k, plan_mode, precision, prefer_far, nrhs, M, nu, shift) for k in range(n)]
 
 
 def param_s(nu: int, M: int, eps: float) -> float:

@@ -81,6 +81,7 @@ struct DevPlan {
     double* b = nullptr; // root offsets b_1..b_{N+1}
     double* e = nullptr; // DHT row perturbations e_1..e_N
     double* v = nullptr; // DHT: v_n = 2/J_1(j_{0,n})^2, n = 1..N (self-inverse weights)
+    double* nutab = nullptr; // Schlomilch of order nu > 0: the J_nu table (build_nu_table)
     std::vector<NearTile> tiles; // host copies of the near-field tiles and row tiles
     std::vector<RowTile> rts;
     NearTile* d_tiles = nullptr; // the same on the device
@@ -100,6 +101,7 @@ struct DevPlan {
         fr(b);
         fr(e);
         fr(v);
+        fr(nutab);
         fr(work);
         fr(d_tiles);
         fr(d_rts);
@@ -242,6 +244,13 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
         if ((st = dev_alloc(dp.e, size_t(N), dp.bytes))) return st;
         HIP_TRY(launch_dht_e(N, dp.b, dp.e, s));
     }
+    std::vector<double> nutab_host; // kept until the stream synchronisation below
+    if (g.nu > 0) {
+        nutab_host.resize(NU_TAB_SIZE);
+        build_nu_table(g.nu, nutab_host.data());
+        if ((st = dev_alloc(dp.nutab, size_t(NU_TAB_SIZE), dp.bytes))) return st;
+        HIP_TRY(hipMemcpyAsync(dp.nutab, nutab_host.data(), NU_TAB_SIZE * sizeof(double), hipMemcpyHostToDevice, s));
+    }
     // near-field work items: partial slots in row order, so that a row
     // tile's slots are consecutive; the tiles themselves run longest first,
     // so that the short ones fill the tail of a launch
@@ -362,8 +371,10 @@ Key plan_key(int task, int64_t N, double eps, const hank_options* o, int dev, in
     int far = o ? o->prefer_far : 0;
     uint64_t eb;
     std::memcpy(&eb, &eps, 8);
-    int M = o ? o->M : 0;
-    return Key{task, N, eb, mode + 4 * M, prec, (direct * 2 + far) * 128 + int(rhs_bucket(nrhs)), dev};
+    int M = o ? o->M : 0, nu = o ? o->nu : 0, shift = o ? o->shift : 0;
+    if (nu > 0) nrhs = 1; // order nu > 0 sums one right-hand side at a time
+    return Key{task, N, eb, mode + 4 * M + 128 * (nu + 16 * shift), prec,
+               (direct * 2 + far) * 128 + int(rhs_bucket(nrhs)), dev};
 }
 
 hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hipStream_t s, DevPlan*& out,
@@ -383,8 +394,9 @@ hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hip
     dp->device = dev;
     try {
         dp->plan = prebuilt ? *prebuilt
-                            : make_plan(task, N, eps, mode, prec, direct != 0, cost_model_for(o), rhs_bucket(nrhs),
-                                        o ? o->M : 0);
+                            : make_plan(task, N, eps, mode, prec, direct != 0, cost_model_for(o),
+                                        rhs_bucket(o && o->nu > 0 ? 1 : nrhs), o ? o->M : 0, o ? o->nu : 0,
+                                        o ? o->shift : 0);
     } catch (const std::exception& ex) {
         return fail(HANK_EINVAL, std::string("planning failed: ") + ex.what());
     }
@@ -396,9 +408,9 @@ hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hip
 }
 
 // ---- optional per-kernel timing (hank_profile) ----
-enum { K_NEAR = 0, K_NEAR_MULTI, K_NEAR_REDUCE, K_PASS_A, K_PASS_B, K_PASS_C, K_FAR_REDUCE, K_COUNT };
+enum { K_NEAR = 0, K_NEAR_MULTI, K_NEAR_REDUCE, K_PASS_A, K_PASS_B, K_PASS_C, K_FAR_REDUCE, K_NEAR_NU, K_COUNT };
 const char* const k_names[K_COUNT] = {"near",   "near_multi", "near_reduce", "pass_a",
-                                      "pass_b", "pass_c",     "far_reduce"};
+                                      "pass_b", "pass_c",     "far_reduce",  "near_nu"};
 struct Pending {
     int kind;
     hipEvent_t a, b;
@@ -552,10 +564,10 @@ struct FarLaunch {
 // descriptors, far descriptors (buf and part as offsets into the work and
 // chunk-sum buffers), launch sets and buffer sizes.
 struct Prepared {
-    std::vector<NearProb> probs;
-    int32_t nsingle = 0;
-    int64_t pbase = 0, ntiles1 = 0, ntilesm = 0, nrts = 0;
-    double near_entries = 0, multi_entries = 0;
+    std::vector<NearProb> probs; // single rhs order 0, then order nu > 0, then several rhs
+    int32_t nsingle = 0, nnu = 0;
+    int64_t pbase = 0, ntiles1 = 0, ntilesnu = 0, ntilesm = 0, nrts = 0;
+    double near_entries = 0, nu_entries = 0, multi_entries = 0;
     std::vector<FarDesc> descs;
     std::vector<FarLaunch> launches;
     size_t work_need = 0, part_need = 0;
@@ -563,22 +575,25 @@ struct Prepared {
 
 void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR) {
     // the near-field kernels take at most 64 right-hand sides: split wider jobs
+    // (order nu > 0: one right-hand side per job)
     std::vector<Job> jobs;
-    for (const Job& J : jobs_in)
-        for (int64_t j0 = 0; j0 < J.nrhs; j0 += 64) {
+    for (const Job& J : jobs_in) {
+        const int64_t w = J.dp->plan.g.nu > 0 ? 1 : 64;
+        for (int64_t j0 = 0; j0 < J.nrhs; j0 += w) {
             Job P = J;
             P.c = J.c + j0 * J.ldc;
             P.f = J.f + j0 * J.ldo;
-            P.nrhs = std::min<int64_t>(64, J.nrhs - j0);
+            P.nrhs = std::min<int64_t>(w, J.nrhs - j0);
             jobs.push_back(P);
         }
+    }
 
     // ---------- near field descriptors: single right-hand side jobs first ----------
-    std::stable_partition(jobs.begin(), jobs.end(), [](const Job& J) { return J.nrhs == 1; });
+    auto near_class = [](const Job& J) { return J.dp->plan.g.nu > 0 ? 1 : (J.nrhs == 1 ? 0 : 2); };
+    std::stable_sort(jobs.begin(), jobs.end(),
+                     [&](const Job& x, const Job& y) { return near_class(x) < near_class(y); });
     auto& probs = PR.probs;
-    int32_t& nsingle = PR.nsingle;
-    int64_t &pbase = PR.pbase, &ntiles1 = PR.ntiles1, &ntilesm = PR.ntilesm, &nrts = PR.nrts;
-    double &near_entries = PR.near_entries, &multi_entries = PR.multi_entries;
+    int64_t &pbase = PR.pbase, &nrts = PR.nrts;
     for (size_t i = 0; i < jobs.size(); ++i) {
         const Job& J = jobs[i];
         NearProb P{};
@@ -592,16 +607,20 @@ void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR) {
         P.ldc = J.ldc;
         P.ldo = J.ldo;
         P.nrhs = int32_t(J.nrhs);
+        P.nu = J.dp->plan.g.nu;
+        P.nutab = J.dp->nutab;
         P.pbase = pbase;
         const int64_t nt = int64_t(J.dp->tiles.size());
-        int64_t& count = J.nrhs == 1 ? ntiles1 : ntilesm;
+        const int cls = near_class(J);
+        int64_t& count = cls == 0 ? PR.ntiles1 : cls == 1 ? PR.ntilesnu : PR.ntilesm;
         P.tile_start = count;
         count += nt;
         P.rt_start = nrts;
         nrts += int64_t(J.dp->rts.size());
         pbase += nt * J.nrhs * 64;
-        nsingle += J.nrhs == 1;
-        (J.nrhs == 1 ? near_entries : multi_entries) += double(J.dp->plan.near_entries) * double(J.nrhs);
+        (cls == 0 ? PR.nsingle : PR.nnu) += cls < 2;
+        (cls == 0 ? PR.near_entries : cls == 1 ? PR.nu_entries : PR.multi_entries) +=
+            double(J.dp->plan.near_entries) * double(J.nrhs);
         probs.push_back(P);
     }
 
@@ -737,16 +756,21 @@ hank_status enqueue_jobs(const Prepared& PR, const NearProb* dprobs, const FarDe
     hank_status st;
     hipEvent_t ev;
     const int32_t nprob = int32_t(PR.probs.size());
-    const int32_t nsingle = PR.nsingle;
+    const int32_t nsingle = PR.nsingle, nnu = PR.nnu;
     const int64_t ntiles1 = PR.ntiles1, ntilesm = PR.ntilesm, nrts = PR.nrts, pbase = PR.pbase;
     if (ntiles1 > 0) {
         if ((st = prof_begin(ev, s))) return st;
         HIP_TRY(launch_near(dprobs, nsingle, ntiles1, dpart, s));
         if ((st = prof_end(K_NEAR, ev, 8.0 * 64.0 * double(ntiles1), PR.near_entries, s))) return st;
     }
+    if (PR.ntilesnu > 0) {
+        if ((st = prof_begin(ev, s))) return st;
+        HIP_TRY(launch_near_nu(dprobs + nsingle, nnu, PR.ntilesnu, dpart, s));
+        if ((st = prof_end(K_NEAR_NU, ev, 8.0 * 64.0 * double(PR.ntilesnu), PR.nu_entries, s))) return st;
+    }
     if (ntilesm > 0) {
         if ((st = prof_begin(ev, s))) return st;
-        HIP_TRY(launch_near_multi(dprobs + nsingle, nprob - nsingle, ntilesm, dpart, s));
+        HIP_TRY(launch_near_multi(dprobs + nsingle + nnu, nprob - nsingle - nnu, ntilesm, dpart, s));
         if ((st = prof_end(K_NEAR_MULTI, ev, 0.0, PR.multi_entries, s))) return st;
     }
     if ((st = prof_begin(ev, s))) return st;
@@ -1548,7 +1572,8 @@ static hank_status host_plan(int32_t task, int64_t N, double eps, const hank_opt
     if (!valid_task(task)) return fail(HANK_EINVAL, "unknown task");
     try {
         p = make_plan(task, N, eps, o ? o->plan_mode : 0, o ? o->precision : 0, o && o->direct,
-                      cost_model_for(o), rhs_bucket(o && o->nrhs > 1 ? o->nrhs : 1), o ? o->M : 0);
+                      cost_model_for(o), rhs_bucket(o && o->nrhs > 1 && o->nu == 0 ? o->nrhs : 1), o ? o->M : 0,
+                      o ? o->nu : 0, o ? o->shift : 0);
     } catch (const std::exception& ex) {
         return fail(HANK_EINVAL, ex.what());
     }

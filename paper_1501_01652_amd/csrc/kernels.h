@@ -65,7 +65,8 @@ struct NearProb {
     const NearTile* tiles;
     const RowTile* rts;
     int64_t ldc, ldo, tile_start, rt_start, pbase;
-    int32_t nrhs, pad;
+    int32_t nrhs, nu;      // nu > 0: Schlomilch of order nu (k_near_nu, one right-hand side)
+    const double* nutab;   // the plan's J_nu table (build_nu_table), nu > 0 only
 };
 
 struct GroupDev {
@@ -128,6 +129,8 @@ hipError_t launch_j0(const double* z, int64_t n, double* out, hipStream_t s);
 // sides (k_near_multi: J_0 evaluated once per entry as the A operand of
 // FP64 MFMA); then f = sum of the partials, nrt row tiles in all.
 hipError_t launch_near(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s);
+// near field of order nu > 0 (one right-hand side per problem)
+hipError_t launch_near_nu(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s);
 hipError_t launch_near_multi(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s);
 hipError_t launch_near_reduce(const NearProb* probs, int32_t nprob, int64_t nrt, const double* partial,
                               hipStream_t s);

@@ -514,6 +514,89 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // side: 4 waves take every 4th tile and their sums are combined in a fixed
 // order; several: wave w sums right-hand sides w, w+4, ... over the tiles in
 // order.
+// ---------------------------------------------------------------------------
+// Near field of order nu > 0 (Schlomilch, Sec. 4): J_nu at each entry from the
+// plan's table (tables.h).  Below z = 20 + nu/2 the series (z < 2) or the
+// Taylor pieces, with z carried as hi + lo so that the offset from the
+// piece's centre is exact; above it 12 Hankel pairs, the phase z - (2nu+1)pi/4
+// reduced exactly: z = pi K N_n / D with i_n = K N_n mod 2D advanced in
+// integers by K 4 ac per step of the wave's column.  Same tiles, partial
+// slots and reduction as k_near.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double jnu_small(const double* __restrict__ tab, int nu, double hi, double lo) {
+    const double z = hi + lo;
+    if (z < J0_TAYLOR_Z0) {
+        const double h = 0.5 * z, w = h * h;
+        double p = tab[NU_TAB_SER + NU_SERIES_TERMS - 1];
+        for (int t = NU_SERIES_TERMS - 2; t >= 0; --t) p = fma(p, w, tab[NU_TAB_SER + t]);
+        for (int i = 0; i < nu; ++i) p *= h;
+        return p;
+    }
+    int i = (int)((z - J0_TAYLOR_Z0) * (1.0 / J0_TAYLOR_H));
+    i = i < 0 ? 0 : (i >= NU_TAYLOR_INTERVALS ? NU_TAYLOR_INTERVALS - 1 : i);
+    const double dz = (hi - (J0_TAYLOR_Z0 + (i + 0.5) * J0_TAYLOR_H)) + lo;
+    const double* t = tab + NU_TAB_TAY + J0_TAYLOR_DEG * i;
+    double p = t[J0_TAYLOR_DEG - 1];
+#pragma unroll
+    for (int u = J0_TAYLOR_DEG - 2; u >= 0; --u) p = fma(p, dz, t[u]);
+    return p;
+}
+
+__global__ __launch_bounds__(256) void k_near_nu(const NearProb* __restrict__ probs, int nprob,
+                                                 double* __restrict__ partial) {
+    __shared__ double cs[NEAR_TILE_COLS];
+    __shared__ double red[4][64];
+    const NearProb& P = probs[find_desc<NearProb, &NearProb::tile_start>(probs, nprob, blockIdx.x)];
+    const NearTile T = P.tiles[blockIdx.x - P.tile_start];
+    double* out = partial + P.pbase + T.slot * 64;
+    const GridArgs G = P.G;
+    const double* tab = P.nutab;
+    const int nu = P.nu;
+    const int ncol = (int)(T.n1 - T.n0);
+    for (int i = threadIdx.x; i < ncol; i += 256) cs[i] = P.c[T.n0 - 1 + i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool active = lane < T.nk;
+    const int64_t k = T.k0 + (active ? lane : 0);
+    const int64_t K = G.ar * k + G.br;
+    const int64_t D2 = 2 * G.D;
+    int64_t n = T.n0 + wave;
+    int64_t Nn = G.ac * n + G.bc;
+    int64_t ir = (K * Nn) % D2;
+    const int64_t step = (K * 4 * G.ac) % D2;
+    const double zsw = 20.0 + 0.5 * nu, ph0 = -0.25 * (2 * nu + 1);
+    double acc = 0.0;
+    for (; n < T.n1; n += 4) {
+        const double I = (double)K * (double)Nn; // exact: K N_n < 2^53
+        const double hi = I * G.piD_hi;
+        const double lo = fma(I, G.piD_hi, -hi) + I * G.piD_lo;
+        const double z = hi + lo;
+        double J;
+        if (z < zsw) {
+            J = jnu_small(tab, nu, hi, lo);
+        } else {
+            double s, c;
+            sincospi(fma((double)ir, G.invD, ph0), &s, &c);
+            const double zi = 1.0 / z, zi2 = zi * zi;
+            double Pv = tab[NU_TAB_P + NU_HANKEL_PAIRS - 1], Qv = tab[NU_TAB_Q + NU_HANKEL_PAIRS - 1];
+#pragma unroll
+            for (int m = NU_HANKEL_PAIRS - 2; m >= 0; --m) {
+                Pv = fma(Pv, zi2, tab[NU_TAB_P + m]);
+                Qv = fma(Qv, zi2, tab[NU_TAB_Q + m]);
+            }
+            J = sqrt(0.63661977236758134308 * zi) * fma(c, Pv, -s * (Qv * zi)); // sqrt(2/(pi z))
+        }
+        acc = fma(cs[n - T.n0], J, acc);
+        Nn += 4 * G.ac;
+        ir += step;
+        if (ir >= D2) ir -= D2;
+    }
+    red[wave][lane] = active ? acc : 0.0;
+    __syncthreads();
+    if (wave == 0) out[lane] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
 __global__ __launch_bounds__(256) void k_near_reduce(const NearProb* __restrict__ probs, int nprob,
                                                      const double* __restrict__ partial) {
     __shared__ double red[4][64];
@@ -936,6 +1019,11 @@ hipError_t launch_j0(const double* z, int64_t n, double* out, hipStream_t s) {
 
 hipError_t launch_near(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s) {
     if (ntiles > 0) hipLaunchKernelGGL(k_near, dim3((unsigned)ntiles), dim3(256), 0, s, probs, (int)nprob, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_near_nu(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s) {
+    if (ntiles > 0) hipLaunchKernelGGL(k_near_nu, dim3((unsigned)ntiles), dim3(256), 0, s, probs, (int)nprob, partial);
     return hipGetLastError();
 }
 

@@ -25,8 +25,14 @@ enum Task { T_SCHL = 0, T_FB = 1, T_DHT = 2, T_SCHL_PG = 3, T_FB_PG = 4 };
 //   N_n = ac*n + bc  (column integer), w^_n = pi * N_n / Qc,   D = Dr*Qc
 // and delta_kn = e_k * lambda_n + r^_k * b_n, where lambda_n = w^_n + b_n = j_{0,n}
 // (Lemma 3.2: j_{0,n} = (n - 1/4) pi + b_n and j_{0,k}/j_{0,N+1} = r^_k + e_k).
+// The Schlomilch tasks may be of integer order nu (J_nu in place of J_0) with
+// w_n = (n + shift) pi (Sec. 4, Remark 4.1): shift enters as N_n = n + shift.
+constexpr int HANK_NU_MAX = 8;
+constexpr int64_t HANK_SHIFT_MAX = 1024;
 struct Grid {
     int task = 0;
+    int nu = 0;
+    int64_t shift = 0;
     int64_t N = 0;
     int64_t ar = 1, br = 0, ac = 1, bc = 0, Dr = 1, Qc = 1, D = 1;
     bool row_pert = false, col_pert = false;
@@ -36,7 +42,7 @@ struct Grid {
     double ztilde(int64_t k, int64_t n) const;
 };
 
-Grid make_grid(int task, int64_t N);
+Grid make_grid(int task, int64_t N, int nu = 0, int64_t shift = 0);
 
 // Input-side term of a group: coefficient K times
 //   (lambda_n/lref)^a (b_n/bref)^b (w^_n/w0)^(-m-1/2)
@@ -125,9 +131,10 @@ double emax(int64_t k, int64_t N);
 // Build a plan.  Throws std::invalid_argument on bad input.
 // nrhs: the number of right-hand sides the tuned partition is balanced for.
 // mode: 0 tuned, 1 paper, 2 paper with P = 0 (single partition).
-// Mpaper: M in modes 1 and 2 (0: Table 4's rule).
+// Mpaper: M in modes 1 and 2 (0: Table 4's rule).  nu, shift: order and
+// frequency shift of the Schlomilch tasks (0 for the others).
 Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool direct,
-               const CostModel& cm, int64_t nrhs = 1, int Mpaper = 0);
+               const CostModel& cm, int64_t nrhs = 1, int Mpaper = 0, int nu = 0, int64_t shift = 0);
 
 // Fill terms/groups of a block; returns false if the truncation would exceed
 // the supported term count.

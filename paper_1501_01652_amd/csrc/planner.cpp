@@ -29,13 +29,19 @@ double Grid::ztilde(int64_t k, int64_t n) const {
     return M_PI * (double(ar * k + br) * double(ac * n + bc)) / double(D);
 }
 
-Grid make_grid(int task, int64_t N) {
+Grid make_grid(int task, int64_t N, int nu, int64_t shift) {
+    if (nu < 0 || nu > HANK_NU_MAX || shift < 0 || shift > HANK_SHIFT_MAX)
+        throw std::invalid_argument("nu must lie in [0, 8] and shift in [0, 1024]");
+    if ((nu != 0 || shift != 0) && task != T_SCHL && task != T_SCHL_PG)
+        throw std::invalid_argument("nu and shift apply to the Schlomilch tasks only");
     Grid g;
     g.task = task;
+    g.nu = nu;
+    g.shift = shift;
     g.N = N;
     switch (task) {
-    case T_SCHL: // r_k = (k-1)/(N-1), w_n = n pi
-        g.ar = 1; g.br = -1; g.Dr = N - 1; g.ac = 1; g.bc = 0; g.Qc = 1;
+    case T_SCHL: // r_k = (k-1)/(N-1), w_n = (n + shift) pi
+        g.ar = 1; g.br = -1; g.Dr = N - 1; g.ac = 1; g.bc = shift; g.Qc = 1;
         break;
     case T_FB: // r_k = (k-1)/(N-1), w_n = j_{0,n} = (n-1/4)pi + b_n
         g.ar = 1; g.br = -1; g.Dr = N - 1; g.ac = 4; g.bc = -1; g.Qc = 4;
@@ -45,8 +51,8 @@ Grid make_grid(int task, int64_t N) {
         g.ar = 4; g.br = -1; g.Dr = 4 * N + 3; g.ac = 4; g.bc = -1; g.Qc = 4;
         g.row_pert = g.col_pert = true;
         break;
-    case T_SCHL_PG: // r_k = k/N, w_n = n pi
-        g.ar = 1; g.br = 0; g.Dr = N; g.ac = 1; g.bc = 0; g.Qc = 1;
+    case T_SCHL_PG: // r_k = k/N, w_n = (n + shift) pi
+        g.ar = 1; g.br = 0; g.Dr = N; g.ac = 1; g.bc = shift; g.Qc = 1;
         break;
     case T_FB_PG: // r_k = k/N, w_n = j_{0,n}
         g.ar = 1; g.br = 0; g.Dr = N; g.ac = 4; g.bc = -1; g.Qc = 4;
@@ -203,6 +209,14 @@ static std::map<int, double> order_mix(int a, int b, bool paper, int K, int T) {
     return w;
 }
 
+// the same mix for J_nu in place of J_0: every order mu becomes mu + nu
+static std::map<int, double> shift_orders(const std::map<int, double>& w, int nu) {
+    if (nu == 0) return w;
+    std::map<int, double> out;
+    for (auto& kv : w) out[kv.first + nu] = kv.second;
+    return out;
+}
+
 static cplx ipow(int p) { // i^p
     switch (((p % 4) + 4) % 4) {
     case 0: return {1, 0};
@@ -256,7 +270,7 @@ bool build_block_terms(const Grid& g, Block& bk, double eps, int mode, int Mpape
         int amax = g.row_pert ? U - 1 : 0, bmx = g.col_pert ? U - 1 : 0;
         for (int a = 0; a <= amax; ++a)
             for (int b = 0; b <= bmx; ++b) {
-                Pair p{a, b, Mpaper, 0.0, order_mix(a, b, true, K, T)};
+                Pair p{a, b, Mpaper, 0.0, shift_orders(order_mix(a, b, true, K, T), g.nu)};
                 bool any = false;
                 for (auto& kv : p.mix) any |= kv.second != 0.0;
                 if (any) pairs.push_back(p);
@@ -280,7 +294,7 @@ bool build_block_terms(const Grid& g, Block& bk, double eps, int mode, int Mpape
         while (keep < all.size() && suffix[keep] > eps_trunc) ++keep;
         for (size_t i = 0; i < keep; ++i) {
             Pair p{all[i].second.first, all[i].second.second, 0, all[i].first,
-                   order_mix(all[i].second.first, all[i].second.second, false, 0, 0)};
+                   shift_orders(order_mix(all[i].second.first, all[i].second.second, false, 0, 0), g.nu)};
             pairs.push_back(p);
         }
         // fewest asymptotic terms per pair: w * E_u(M, zmin) <= eps_asy / |S|,
@@ -530,7 +544,7 @@ static double plan_cost(const Plan& p, const CostModel& cm) {
 }
 
 Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool direct, const CostModel& cm,
-               int64_t nrhs, int Mpaper) {
+               int64_t nrhs, int Mpaper, int nu, int64_t shift) {
     if (!(eps >= 1e-15 && eps < 1.0) || !std::isfinite(eps)) throw std::invalid_argument("eps out of range");
     if (mode < 0 || mode > 2) throw std::invalid_argument("plan_mode must be 0, 1 or 2");
     if (Mpaper < 0 || Mpaper > 20 || (Mpaper > 0 && mode == 0))
@@ -538,7 +552,7 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
     int64_t Nmin = (task == T_SCHL || task == T_FB) ? 2 : 1;
     if (N < Nmin || N > (int64_t(1) << 24)) throw std::invalid_argument("N out of range");
     Plan p;
-    p.g = make_grid(task, N);
+    p.g = make_grid(task, N, nu, shift);
     p.eps = eps;
     p.mode = mode;
     p.direct = direct;
@@ -547,7 +561,7 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
 
     // paper parameters (reported in both modes)
     p.M = Mpaper > 0 ? Mpaper : paper_M(eps);
-    int numax = 0;
+    int numax = nu; // Schlomilch of order nu: only J_nu
     if (p.g.col_pert || p.g.row_pert) {
         double f = (task == T_DHT) ? 1.01 : 1.0;
         p.K = 1;
@@ -557,7 +571,9 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
         p.first_direct = int(std::floor(f * std::max(param_pK(p.K, eps), param_qT(p.T, eps))));
         numax = (task == T_DHT) ? 2 * p.K - 2 : p.K - 1;
     }
-    // the remainder bound of eq. (errorBound) holds for orders mu <= 2M + 1/2
+    // the remainder bound of eq. (errorBound) holds for orders mu <= 2M + 1/2:
+    // Table 4's M is raised to that where the orders need it (an explicit M is not)
+    if (Mpaper == 0) p.M = std::max(p.M, int(std::ceil(numax / 2.0 - 0.25)));
     if (mode != 0 && 2 * p.M + 0.5 < numax)
         throw std::invalid_argument("M too small for the Bessel orders of this plan");
     p.s = param_s(numax, p.M, eps);
@@ -623,7 +639,8 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
     finish(best);
     const double betas[] = {0.06, 0.1, 0.15, 0.22, 0.3, 0.4, 0.55};
     for (int Mc = 2; Mc <= 14; ++Mc) {
-        double s = param_s(0, Mc, eps / 8.0);
+        if (2 * Mc + 0.5 < nu) continue; // the remainder bound needs M >= nu/2 - 1/4
+        double s = param_s(nu, Mc, eps / 8.0);
         if (s < 2.0) continue;
         double R0 = std::sqrt(s / M_PI) / std::sqrt(double(N));
         for (double beta : betas)

@@ -16,7 +16,7 @@
 
 namespace hank {
 
-// J_0 .. J_mmax at x by Miller's algorithm.
+// J_0 .. J_mmax at x by Miller's algorithm (mmax < 64).
 static void miller(long double x, int mmax, long double* J) {
     int start = 2 * (int(x) + 40 + mmax / 2);
     long double jp1 = 0.0L, j = 1e-40L;
@@ -37,6 +37,46 @@ static long double lbinom(int n, int k) {
     long double r = 1.0L;
     for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
     return r;
+}
+
+// Taylor coefficients J_nu^(u)(x)/u!, u < J0_TAYLOR_DEG, from
+// J_nu^(u) = 2^-u sum_j (-1)^j C(u,j) J_{nu-u+2j} (DLMF 10.6.1 applied u times)
+// and J_{-m} = (-1)^m J_m
+static void taylor_coeffs(int nu, long double x, double* out) {
+    long double J[64];
+    miller(x, nu + J0_TAYLOR_DEG + 2, J);
+    long double fact = 1.0L;
+    for (int u = 0; u < J0_TAYLOR_DEG; ++u) {
+        if (u > 0) fact *= u;
+        long double d = 0.0L;
+        for (int j = 0; j <= u; ++j) {
+            int mu = nu - u + 2 * j;
+            long double Jm = J[std::abs(mu)];
+            if (mu < 0 && (std::abs(mu) & 1)) Jm = -Jm;
+            d += ((j & 1) ? -1.0L : 1.0L) * lbinom(u, j) * Jm;
+        }
+        out[u] = double(std::ldexp(d, -u) / fact);
+    }
+}
+
+void build_nu_table(int nu, double* out) {
+    long double a = 1.0L; // a_m(nu)
+    for (int m = 0; m < 2 * NU_HANKEL_PAIRS; ++m) {
+        if (m > 0) a *= (4.0L * nu * nu - (long double)(2 * m - 1) * (2 * m - 1)) / (8.0L * m);
+        const long double sg = ((m / 2) & 1) ? -1.0L : 1.0L;
+        out[(m & 1 ? NU_TAB_Q : NU_TAB_P) + m / 2] = double(sg * a);
+    }
+    long double f = 1.0L, g = 1.0L; // t!, (t+nu)!
+    for (int i = 1; i <= nu; ++i) g *= i;
+    for (int t = 0; t < NU_SERIES_TERMS; ++t) {
+        if (t > 0) {
+            f *= t;
+            g *= t + nu;
+        }
+        out[NU_TAB_SER + t] = double(((t & 1) ? -1.0L : 1.0L) / (f * g));
+    }
+    for (int i = 0; i < NU_TAYLOR_INTERVALS; ++i)
+        taylor_coeffs(nu, J0_TAYLOR_Z0 + (i + 0.5L) * J0_TAYLOR_H, out + NU_TAB_TAY + J0_TAYLOR_DEG * i);
 }
 
 void build_tables(DeviceTables& t) {

@@ -26,4 +26,22 @@ struct DeviceTables {
 
 void build_tables(DeviceTables& t);
 
+// Per-order table of J_nu for the Schlomilch tasks of order nu = 1..8 (device
+// memory of the plan), NU_TAB_SIZE doubles:
+//   [NU_TAB_P + m]  (-1)^m a_2m(nu),   [NU_TAB_Q + m]  (-1)^m a_2m+1(nu),  m < 12
+//       (Hankel expansion, Sec. 3.1: 12 pairs keep the remainder below 1e-17
+//        for z >= 20 + nu/2, eq. (errorBound))
+//   [NU_TAB_SER + t] (-1)^t / (t! (t+nu)!), t < 14  (series, z < 2)
+//   [NU_TAB_TAY + 14 i + u]  Taylor coefficients of J_nu about 2.25 + i/2,
+//       i < NU_TAYLOR_INTERVALS  (pieces on [2, 24), degree 13)
+constexpr int NU_HANKEL_PAIRS = 12;
+constexpr int NU_SERIES_TERMS = 14;
+constexpr int NU_TAYLOR_INTERVALS = 44;
+constexpr int NU_TAB_P = 0;
+constexpr int NU_TAB_Q = NU_HANKEL_PAIRS;
+constexpr int NU_TAB_SER = 2 * NU_HANKEL_PAIRS;
+constexpr int NU_TAB_TAY = NU_TAB_SER + NU_SERIES_TERMS;
+constexpr int NU_TAB_SIZE = NU_TAB_TAY + NU_TAYLOR_INTERVALS * J0_TAYLOR_DEG;
+void build_nu_table(int nu, double* out);
+
 } // namespace hank

@@ -107,6 +107,23 @@ def test_dht0_inverse_2pow20():
     assert ratio <= 1.0
 
 
+@pytest.mark.parametrize("nu,shift,eps", [(3, 3, 1e-8), (8, 0, 1e-14)])
+def test_schlomilch_order_nu_2pow20(nu, shift, eps):
+    """Schlomilch of order nu on the paper grid (Sec. 4, Remark 4.1) at N = 2^20,
+    sampled rows."""
+    task, N = "schlomilch_paper_grid", 1 << 20
+    c = inputs.coefficients("gauss", N, 424242)
+    rows = inputs.sampled_rows(N, 24, boundary_rows(task, N, eps, nu=nu, shift=shift))
+    f = host(hank.transform(task, dev(c), eps, nu=nu, shift=shift))
+    ref = oracle.eval_rows(task, c, rows=rows, nu=nu, shift=shift)
+    err = float(np.max(np.abs(f[rows - 1] - ref)))
+    Cm = err / (eps * float(np.sum(np.abs(c))))
+    info = hank.plan_info(task, N, eps, nu=nu, shift=shift)
+    print("schlomilch order %d shift %d N=2^20 eps=%g blocks=%d rows=%d measured C=%.3g" %
+          (nu, shift, eps, info["nblocks"], len(rows), Cm))
+    assert Cm <= C_TOL
+
+
 def test_dht0_2pow20_one_hot_columns():
     """c = e_n at the columns bordering every block: f_k = J_0(r_k w_n) for all k."""
     N, eps = 1 << 20, 1e-8

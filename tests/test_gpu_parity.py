@@ -354,3 +354,82 @@ def test_dht0_inverse_errors_leave_output_untouched():
     assert L.hank_dht0_inverse(None, 64, 1e-8, ctypes.c_void_p(out.data_ptr()), None) == 1
     assert L.hank_dht0_weights(0, ctypes.c_void_p(out.data_ptr()), None) == 1
     assert np.all(np.isnan(host(out)))
+
+
+# ---- Schlomilch expansions of order nu > 0 and shifted frequencies (Sec. 4, Remark 4.1) ----
+_nu_cache = {}
+
+
+def oracle_nu(task, N, nu, shift):
+    key = (task, N, nu, shift)
+    if key not in _nu_cache:
+        c = inputs.coefficients("gauss", N, 3000 + 10 * nu + shift + N)
+        _nu_cache[key] = (c, oracle.eval_rows(task, c, nu=nu, shift=shift))
+    return _nu_cache[key]
+
+
+@pytest.mark.parametrize("task", ["schlomilch", "schlomilch_paper_grid"])
+@pytest.mark.parametrize("nu,shift", [(1, 0), (2, 2), (5, 0), (8, 8), (0, 3)])
+@pytest.mark.parametrize("N", [2, 17, 300, 1500])
+@pytest.mark.parametrize("eps", [1e-4, 1e-8, 1e-14])
+@pytest.mark.parametrize("mode", ["tuned", "far", "paper"])
+def test_order_nu_parity(task, nu, shift, N, eps, mode):
+    c, ref = oracle_nu(task, N, nu, shift)
+    kw = {"tuned": {}, "far": {"prefer_far": 1}, "paper": {"plan_mode": 1}}[mode]
+    f = host(hank.transform(task, dev(c), eps, nu=nu, shift=shift, **kw))
+    Cm = measured_C(f, ref, eps, c)
+    nb = hank.plan_info(task, N, eps, nu=nu, shift=shift, **kw)["nblocks"]
+    print("%s nu=%d shift=%d N=%d eps=%g %s blocks=%d measured C=%.3g" % (task, nu, shift, N, eps, mode, nb, Cm))
+    assert Cm <= C_TOL
+
+
+@pytest.mark.parametrize("nu,shift,eps", [(3, 3, 1e-14), (8, 0, 1e-8), (1, 1, 1e-4)])
+@pytest.mark.parametrize("mode", ["far", "paper"])
+def test_order_nu_one_hot_columns(nu, shift, eps, mode):
+    """c = e_n: f_k = J_nu(r_k (n + shift) pi) for every k, per entry, at the
+    edges of every block's columns."""
+    task, N = "schlomilch_paper_grid", 3000
+    kw = {"far": {"prefer_far": 1}, "paper": {"plan_mode": 1}}[mode]
+    cols = {1, 2, N}
+    for b in hank.plan_blocks(task, N, eps, nu=nu, shift=shift, **kw):
+        cols |= {b["col0"] - 1, b["col0"], b["col0"] + 1, b["col1"]}
+    worst = 0.0
+    for n in sorted(x for x in cols if 1 <= x <= N):
+        c = np.zeros(N)
+        c[n - 1] = 1.0
+        f = host(hank.transform(task, dev(c), eps, nu=nu, shift=shift, **kw))
+        ref = oracle.eval_rows(task, c, nu=nu, shift=shift)
+        worst = max(worst, float(np.max(np.abs(f - ref))))
+    print("order %d shift %d eps=%g %s: worst entry error %.3g (%.3g eps)" % (nu, shift, eps, mode, worst, worst / eps))
+    assert worst <= C_TOL * eps
+
+
+@pytest.mark.parametrize("nu", [1, 4, 8])
+def test_order_nu_direct_is_the_plain_sum(nu):
+    """The direct option sums every entry with the order-nu near kernel: tight."""
+    N = 700
+    c, ref = oracle_nu("schlomilch", N, nu, nu)
+    f = host(hank.transform("schlomilch", dev(c), 1e-14, direct=1, nu=nu, shift=nu))
+    assert np.max(np.abs(f - ref)) <= 1e-15 * np.sum(np.abs(c))
+
+
+def test_order_nu_several_right_hand_sides():
+    """With nu > 0 several right-hand sides run column by column: each column
+    equals its single call bitwise."""
+    N, eps, nu = 900, 1e-8, 2
+    C = np.random.default_rng(8).standard_normal((5, N))
+    F = host(hank.transform("schlomilch", dev(C), eps, nu=nu, shift=nu))
+    for j in range(5):
+        f = host(hank.transform("schlomilch", dev(C[j]), eps, nu=nu, shift=nu))
+        assert np.array_equal(F[j], f)
+
+
+def test_order_nu_rejected_where_undefined():
+    c = dev(np.ones(64))
+    out = dev(np.full(64, np.nan))
+    for kw in ({"nu": 1}, {"shift": 2}):
+        with pytest.raises(hank.HankError):
+            hank.transform("dht0", c, 1e-8, out=out, **kw)
+    with pytest.raises(hank.HankError):
+        hank.transform("schlomilch", c, 1e-8, out=out, nu=9)
+    assert np.all(np.isnan(host(out)))
