@@ -152,6 +152,7 @@ CostModel cost_model_for(const hank_options* o) {
         cm.near_entry *= 1000.0;
         cm.near_multi_entry *= 1000.0;
         cm.near_rhs *= 1000.0;
+        cm.near_nu_entry *= 1000.0;
         cm.block = 0.0;
     }
     return cm;
