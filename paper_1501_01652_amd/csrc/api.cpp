@@ -82,6 +82,7 @@ struct DevPlan {
     double* e = nullptr; // DHT row perturbations e_1..e_N
     double* v = nullptr; // DHT: v_n = 2/J_1(j_{0,n})^2, n = 1..N (self-inverse weights)
     double* nutab = nullptr; // Schlomilch of order nu > 0: the J_nu table (build_nu_table)
+    int32_t mnu = NU_HANKEL_PAIRS; // Hankel pairs of the order-nu near field
     std::vector<NearTile> tiles; // host copies of the near-field tiles and row tiles
     std::vector<RowTile> rts;
     NearTile* d_tiles = nullptr; // the same on the device
@@ -153,6 +154,7 @@ CostModel cost_model_for(const hank_options* o) {
         cm.near_multi_entry *= 1000.0;
         cm.near_rhs *= 1000.0;
         cm.near_nu_entry *= 1000.0;
+        cm.near_plain_entry *= 1000.0;
         cm.block = 0.0;
     }
     return cm;
@@ -247,6 +249,14 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
     }
     std::vector<double> nutab_host; // kept until the stream synchronisation below
     if (g.nu > 0) {
+        // fewest Hankel pairs (valid for this order) whose remainder at the
+        // switch z = 20 + nu/2 is within the near field's budget
+        const double budget = p.direct ? 1e-17 : p.eps / 8.0, zsw = 20.0 + 0.5 * g.nu;
+        for (int M = std::max(1, int(std::ceil(g.nu / 2.0 - 0.25))); M <= NU_HANKEL_PAIRS; ++M)
+            if (rem_bound(g.nu, M, zsw) <= budget) {
+                dp.mnu = M;
+                break;
+            }
         nutab_host.resize(NU_TAB_SIZE);
         build_nu_table(g.nu, nutab_host.data());
         if ((st = dev_alloc(dp.nutab, size_t(NU_TAB_SIZE), dp.bytes))) return st;
@@ -610,6 +620,7 @@ void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR) {
         P.nrhs = int32_t(J.nrhs);
         P.nu = J.dp->plan.g.nu;
         P.nutab = J.dp->nutab;
+        P.mnu = J.dp->mnu;
         P.pbase = pbase;
         const int64_t nt = int64_t(J.dp->tiles.size());
         const int cls = near_class(J);

@@ -67,6 +67,7 @@ struct NearProb {
     int64_t ldc, ldo, tile_start, rt_start, pbase;
     int32_t nrhs, nu;      // nu > 0: Schlomilch of order nu (k_near_nu, one right-hand side)
     const double* nutab;   // the plan's J_nu table (build_nu_table), nu > 0 only
+    int32_t mnu, pad;      // Hankel pairs k_near_nu needs at z >= 20 + nu/2 (<= NU_HANKEL_PAIRS)
 };
 
 struct GroupDev {

@@ -518,10 +518,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // Near field of order nu > 0 (Schlomilch, Sec. 4): J_nu at each entry from the
 // plan's table (tables.h).  Below z = 20 + nu/2 the series (z < 2) or the
 // Taylor pieces, with z carried as hi + lo so that the offset from the
-// piece's centre is exact; above it 12 Hankel pairs, the phase z - (2nu+1)pi/4
-// reduced exactly: z = pi K N_n / D with i_n = K N_n mod 2D advanced in
-// integers by K 4 ac per step of the wave's column.  Same tiles, partial
-// slots and reduction as k_near.
+// piece's centre is exact; above it mnu Hankel pairs.  The Hankel phase
+// z - (2nu+1)pi/4 = pi (i_n/D - (2nu+1)/4), i_n = K N_n mod 2D, grows by the
+// same angle pi step/D at each of the wave's columns: the lane keeps
+// u = e^{i phase}, advances it by one complex rotation and recomputes it from
+// the exact integer i_n every 16 columns.  Same tiles, partial slots and
+// reduction as k_near.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double jnu_small(const double* __restrict__ tab, int nu, double hi, double lo) {
     const double z = hi + lo;
@@ -551,7 +553,7 @@ __global__ __launch_bounds__(256) void k_near_nu(const NearProb* __restrict__ pr
     double* out = partial + P.pbase + T.slot * 64;
     const GridArgs G = P.G;
     const double* tab = P.nutab;
-    const int nu = P.nu;
+    const int nu = P.nu, mnu = P.mnu;
     const int ncol = (int)(T.n1 - T.n0);
     for (int i = threadIdx.x; i < ncol; i += 256) cs[i] = P.c[T.n0 - 1 + i];
     __syncthreads();
@@ -564,32 +566,53 @@ __global__ __launch_bounds__(256) void k_near_nu(const NearProb* __restrict__ pr
     int64_t n = T.n0 + wave;
     int64_t Nn = G.ac * n + G.bc;
     int64_t ir = (K * Nn) % D2;
-    const int64_t step = (K * 4 * G.ac) % D2;
+    const int64_t step = (K * 4 * G.ac) % D2, step16 = (16 * step) % D2;
     const double zsw = 20.0 + 0.5 * nu, ph0 = -0.25 * (2 * nu + 1);
-    double acc = 0.0;
-    for (; n < T.n1; n += 4) {
-        const double I = (double)K * (double)Nn; // exact: K N_n < 2^53
-        const double hi = I * G.piD_hi;
-        const double lo = fma(I, G.piD_hi, -hi) + I * G.piD_lo;
-        const double z = hi + lo;
-        double J;
-        if (z < zsw) {
-            J = jnu_small(tab, nu, hi, lo);
-        } else {
-            double s, c;
-            sincospi(fma((double)ir, G.invD, ph0), &s, &c);
-            const double zi = 1.0 / z, zi2 = zi * zi;
-            double Pv = tab[NU_TAB_P + NU_HANKEL_PAIRS - 1], Qv = tab[NU_TAB_Q + NU_HANKEL_PAIRS - 1];
+    double hp[NU_HANKEL_PAIRS], hq[NU_HANKEL_PAIRS]; // wave-uniform: held in scalar registers
 #pragma unroll
-            for (int m = NU_HANKEL_PAIRS - 2; m >= 0; --m) {
-                Pv = fma(Pv, zi2, tab[NU_TAB_P + m]);
-                Qv = fma(Qv, zi2, tab[NU_TAB_Q + m]);
+    for (int m = 0; m < NU_HANKEL_PAIRS; ++m) {
+        hp[m] = tab[NU_TAB_P + m];
+        hq[m] = tab[NU_TAB_Q + m];
+    }
+    double ws, wc;
+    sincospi_ratio(step, G.D, &ws, &wc); // e^{i pi step / D}
+    double acc = 0.0;
+    while (n < T.n1) {
+        // anchor: u = e^{i pi (i_n/D - (2nu+1)/4)} from the exact integer i_n
+        double us, uc;
+        sincospi(fma((double)ir, G.invD, ph0), &us, &uc);
+        const int64_t nend = min(T.n1, n + 64);
+        for (; n < nend; n += 4) {
+            const double I = (double)K * (double)Nn; // exact: K N_n < 2^53
+            const double hi = I * G.piD_hi;
+            const double lo = fma(I, G.piD_hi, -hi) + I * G.piD_lo;
+            double J;
+            if (hi + lo < zsw) {
+                J = jnu_small(tab, nu, hi, lo);
+            } else {
+                const double z = hi + lo;
+                double y = __builtin_amdgcn_rsq(z);
+                const double h = 0.5 * z;
+                y = y * fma(-h * y, y, 1.5);
+                y = y * fma(-h * y, y, 1.5);
+                const double zi = y * y, zi2 = zi * zi;
+                double Pv = 0.0, Qv = 0.0;
+#pragma unroll
+                for (int m = NU_HANKEL_PAIRS - 1; m >= 0; --m) {
+                    if (m < mnu) { // uniform: the plan's pair count
+                        Pv = fma(Pv, zi2, hp[m]);
+                        Qv = fma(Qv, zi2, hq[m]);
+                    }
+                }
+                J = (0.79788456080286535588 * y) * fma(uc, Pv, -us * (Qv * zi)); // sqrt(2/pi)
             }
-            J = sqrt(0.63661977236758134308 * zi) * fma(c, Pv, -s * (Qv * zi)); // sqrt(2/(pi z))
+            acc = fma(cs[n - T.n0], J, acc);
+            const double t = uc * ws;
+            uc = fma(uc, wc, -us * ws);
+            us = fma(us, wc, t);
+            Nn += 4 * G.ac;
         }
-        acc = fma(cs[n - T.n0], J, acc);
-        Nn += 4 * G.ac;
-        ir += step;
+        ir += step16;
         if (ir >= D2) ir -= D2;
     }
     red[wave][lane] = active ? acc : 0.0;

@@ -180,6 +180,7 @@ CostModel cost_model_from_env() {
     if (const char* v = std::getenv("HANK_COST_NEAR_MULTI")) cm.near_multi_entry = std::atof(v);
     if (const char* v = std::getenv("HANK_COST_NEAR_RHS")) cm.near_rhs = std::atof(v);
     if (const char* v = std::getenv("HANK_COST_NEAR_NU")) cm.near_nu_entry = std::atof(v);
+    if (const char* v = std::getenv("HANK_COST_NEAR_PLAIN")) cm.near_plain_entry = std::atof(v);
     return cm;
 }
 
@@ -535,8 +536,11 @@ static bool near_segments(const Grid& g, const std::vector<Block>& blocks, std::
 
 static double plan_cost(const Plan& p, const CostModel& cm) {
     const double r = double(p.nrhs);
+    const bool plain = !p.g.col_pert && !p.g.row_pert;
     double c = double(p.near_entries) *
-               (p.g.nu > 0 ? r * cm.near_nu_entry : p.nrhs == 1 ? cm.near_entry : cm.near_multi_entry + r * cm.near_rhs);
+               (p.g.nu > 0      ? r * cm.near_nu_entry
+                : p.nrhs == 1   ? (plain ? cm.near_plain_entry : cm.near_entry)
+                                : cm.near_multi_entry + r * cm.near_rhs);
     for (auto& b : p.blocks) {
         const double g64 = double(b.g64), g32 = double(b.groups.size()) - g64;
         c += cm.block * ((g64 > 0 && g32 > 0) ? 2.0 : 1.0) +
