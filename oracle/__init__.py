@@ -149,7 +149,8 @@ def jn(nu: int, z):
 def eval_rows(task: str, c: np.ndarray, rows=None, nthreads: int = 0, nu: int = 0,
               shift: int = 0) -> np.ndarray:
     """f_k for the 1-based ``rows`` (all rows when None) by direct summation;
-    for the Schlomilch tasks optionally of order nu with w_n = (n + shift) pi."""
+    for the Schlomilch and Fourier-Bessel tasks optionally of order nu, and for
+    the Schlomilch tasks with w_n = (n + shift) pi."""
     lib = _load()
     c = np.ascontiguousarray(c, dtype=np.float64)
     N = c.shape[0]
@@ -191,7 +192,7 @@ def dht0_inverse_rows(f: np.ndarray, rows=None, nthreads: int = 0) -> np.ndarray
 
 
 def entry(task: str, N: int, k: int, n: int, nu: int = 0, shift: int = 0) -> float:
-    """J_nu(r_k w_n) for one matrix entry (nu, shift: Schlomilch tasks only)."""
+    """J_nu(r_k w_n) for one matrix entry (nu: not the DHT; shift: Schlomilch only)."""
     t = TASKS[task]
     b = root_offsets(N + 1) if t in (1, 2, 4) else None
     return _load().or_entry_nu(t, int(nu), int(shift), int(N), _ptr(b), int(k), int(n))

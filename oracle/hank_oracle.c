@@ -41,9 +41,10 @@
  *
  * Sums over n use Neumaier (compensated) summation, n ascending.
  *
- * For the Schlomilch tasks the sum may also be of order nu > 0 with
- * w_n = (n + shift) pi (Sec. 4, Remark 4.1): f_k = sum_n c_n J_nu(r_k w_n), with
- * J_nu from the same two expansions (series below z = 20 + nu/2).
+ * The Schlomilch and Fourier-Bessel sums may also be of order nu > 0,
+ * f_k = sum_n c_n J_nu(r_k w_n) (Sec. 4, eq. (FourierBessel): still at the roots
+ * of J_0), and the Schlomilch ones with w_n = (n + shift) pi (Remark 4.1); J_nu
+ * comes from the same two expansions (series below z = 20 + nu/2).
  *
  * The inverse DHT of Sec. 6 (eq. (inverseTest)), c = (1/j_{0,N+1}^2) D_v J D_v f
  * with v_n = 2/J_1(j_{0,n})^2, is this same direct sum between two diagonal
@@ -514,7 +515,8 @@ int or_eval_rows_nu(int task, int nu, int64_t shift, int64_t N, const double* c,
                     int64_t nrows, const int64_t* rows, double* out, int nthreads) {
     if (N < 1 || !c || !rows || !out || nrows < 0) return -1;
     if (nu < 0 || nu > 12 || shift < 0 || shift > 1024) return -1;
-    if ((nu || shift) && task != T_SCHL && task != T_SCHL_PG) return -1;
+    if (nu && task == T_DHT) return -1;                         /* order nu: Sec. 4 and 5 */
+    if (shift && task != T_SCHL && task != T_SCHL_PG) return -1; /* Remark 4.1 */
     if ((task == T_SCHL || task == T_FB) && N < 2) return -1;
     if (task != T_SCHL && task != T_SCHL_PG && !b) return -1;
     if (task < 0 || task > 4) return -1;

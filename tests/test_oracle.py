@@ -231,8 +231,27 @@ def test_order_nu_exact_phase_at_full_size():
             assert abs(oracle.entry("schlomilch_paper_grid", N, k, n, nu=nu, shift=shift) - float(ref)) < 2e-16
 
 
-def test_order_nu_rejected_outside_schlomilch():
+@pytest.mark.parametrize("task", ["fourier_bessel", "fourier_bessel_paper_grid"])
+@pytest.mark.parametrize("nu", [1, 4, 8])
+def test_bruteforce_fourier_bessel_order_nu(task, nu):
+    """eq. (FourierBessel): f_k = sum_n c_n J_nu(r_k j_{0,n}) (order nu at the
+    roots of J_0) at N = 2 and 13 against mpmath."""
+    mpmath.mp.dps = 40
+    for N in (2, 13):
+        c = np.random.default_rng(7 * nu + N).standard_normal(N)
+        j = [mpmath.besseljzero(0, n) for n in range(1, N + 1)]
+        ref = []
+        for k in range(1, N + 1):
+            r = mpmath.mpf(k - 1) / (N - 1) if task == "fourier_bessel" else mpmath.mpf(k) / N
+            ref.append(float(mpmath.fsum(mpmath.mpf(float(c[n])) * mpmath.besselj(nu, r * j[n]) for n in range(N))))
+        got = oracle.eval_rows(task, c, nu=nu)
+        assert np.max(np.abs(got - np.array(ref))) <= 4e-16 * np.sum(np.abs(c))
+
+
+def test_order_nu_rejected_where_undefined():
     with pytest.raises(ValueError):
         oracle.eval_rows("dht0", np.ones(4), nu=1)
+    with pytest.raises(ValueError):
+        oracle.eval_rows("fourier_bessel", np.ones(4), shift=1)
     with pytest.raises(ValueError):
         oracle.eval_rows("schlomilch", np.ones(4), nu=13)
