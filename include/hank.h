@@ -85,11 +85,13 @@ typedef struct {
                            HANK_EINVAL in mode 0, outside [0, 20], or below the
                            smallest M whose remainder bound covers the highest
                            Bessel order the plan uses (M >= mu_max/2 - 1/4)      */
-    int32_t nu;         /* Schlomilch tasks only: order of the sum, f_k = sum_n c_n
-                           J_nu(r_k w_n), 0 <= nu <= 8 (Sec. 4)                      */
+    int32_t nu;         /* Schlomilch and Fourier-Bessel tasks: order of the sum,
+                           f_k = sum_n c_n J_nu(r_k w_n), 0 <= nu <= 8 (Sec. 4, and
+                           eq. (FourierBessel): still at the roots of J_0)          */
     int32_t shift;      /* Schlomilch tasks only: w_n = (n + shift) pi, 0 <= shift <=
                            1024 (Remark 4.1; the paper's (n + nu) pi is shift = nu).
-                           nu or shift on another task, or out of range: HANK_EINVAL.
+                           nu on the DHT, shift on a task other than Schlomilch, or
+                           either out of range: HANK_EINVAL.
                            With nu > 0 the near field sums one right-hand side at a
                            time (several are accepted and run column by column)    */
 } hank_options;

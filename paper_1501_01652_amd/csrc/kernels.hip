@@ -515,7 +515,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // order; several: wave w sums right-hand sides w, w+4, ... over the tiles in
 // order.
 // ---------------------------------------------------------------------------
-// Near field of order nu > 0 (Schlomilch, Sec. 4): J_nu at each entry from the
+// Near field of order nu > 0 (Schlomilch, Sec. 4; Fourier-Bessel, Sec. 5, whose
+// z = z~ + r^_k b_n carries the root offset b_n): J_nu at each entry from the
 // plan's table (tables.h).  Below z = 20 + nu/2 the series (z < 2) or the
 // Taylor pieces, with z carried as hi + lo so that the offset from the
 // piece's centre is exact; above it mnu Hankel pairs.  The Hankel phase
@@ -546,7 +547,7 @@ __device__ __forceinline__ double jnu_small(const double* __restrict__ tab, int 
 
 __global__ __launch_bounds__(256) void k_near_nu(const NearProb* __restrict__ probs, int nprob,
                                                  double* __restrict__ partial) {
-    __shared__ double cs[NEAR_TILE_COLS];
+    __shared__ double cs[NEAR_TILE_COLS], bs[NEAR_TILE_COLS];
     __shared__ double red[4][64];
     const NearProb& P = probs[find_desc<NearProb, &NearProb::tile_start>(probs, nprob, blockIdx.x)];
     const NearTile T = P.tiles[blockIdx.x - P.tile_start];
@@ -554,14 +555,19 @@ __global__ __launch_bounds__(256) void k_near_nu(const NearProb* __restrict__ pr
     const GridArgs G = P.G;
     const double* tab = P.nutab;
     const int nu = P.nu, mnu = P.mnu;
+    const bool pert = G.col_pert != 0;
     const int ncol = (int)(T.n1 - T.n0);
-    for (int i = threadIdx.x; i < ncol; i += 256) cs[i] = P.c[T.n0 - 1 + i];
+    for (int i = threadIdx.x; i < ncol; i += 256) {
+        cs[i] = P.c[T.n0 - 1 + i];
+        bs[i] = pert ? P.b[T.n0 - 1 + i] : 0.0;
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool active = lane < T.nk;
     const int64_t k = T.k0 + (active ? lane : 0);
     const int64_t K = G.ar * k + G.br;
+    const double rk = (double)K / (double)G.Dr; // r^_k
     const int64_t D2 = 2 * G.D;
     int64_t n = T.n0 + wave;
     int64_t Nn = G.ac * n + G.bc;
@@ -585,7 +591,8 @@ __global__ __launch_bounds__(256) void k_near_nu(const NearProb* __restrict__ pr
         for (; n < nend; n += 4) {
             const double I = (double)K * (double)Nn; // exact: K N_n < 2^53
             const double hi = I * G.piD_hi;
-            const double lo = fma(I, G.piD_hi, -hi) + I * G.piD_lo;
+            const double delta = rk * bs[n - T.n0]; // z - z~ (0 without root offsets)
+            const double lo = (fma(I, G.piD_hi, -hi) + I * G.piD_lo) + delta;
             double J;
             if (hi + lo < zsw) {
                 J = jnu_small(tab, nu, hi, lo);
@@ -604,7 +611,14 @@ __global__ __launch_bounds__(256) void k_near_nu(const NearProb* __restrict__ pr
                         Qv = fma(Qv, zi2, hq[m]);
                     }
                 }
-                J = (0.79788456080286535588 * y) * fma(uc, Pv, -us * (Qv * zi)); // sqrt(2/pi)
+                double cph = uc, sph = us;
+                if (pert) { // the phase of z~ carried by u, plus delta
+                    double sd, cd;
+                    sincos_small(delta, &sd, &cd);
+                    cph = fma(uc, cd, -us * sd);
+                    sph = fma(us, cd, uc * sd);
+                }
+                J = (0.79788456080286535588 * y) * fma(cph, Pv, -sph * (Qv * zi)); // sqrt(2/pi)
             }
             acc = fma(cs[n - T.n0], J, acc);
             const double t = uc * ws;

@@ -25,8 +25,10 @@ enum Task { T_SCHL = 0, T_FB = 1, T_DHT = 2, T_SCHL_PG = 3, T_FB_PG = 4 };
 //   N_n = ac*n + bc  (column integer), w^_n = pi * N_n / Qc,   D = Dr*Qc
 // and delta_kn = e_k * lambda_n + r^_k * b_n, where lambda_n = w^_n + b_n = j_{0,n}
 // (Lemma 3.2: j_{0,n} = (n - 1/4) pi + b_n and j_{0,k}/j_{0,N+1} = r^_k + e_k).
-// The Schlomilch tasks may be of integer order nu (J_nu in place of J_0) with
-// w_n = (n + shift) pi (Sec. 4, Remark 4.1): shift enters as N_n = n + shift.
+// The Schlomilch and Fourier-Bessel tasks may be of integer order nu (J_nu in
+// place of J_0; Fourier-Bessel still at the roots of J_0, eq. (FourierBessel)),
+// and the Schlomilch ones have w_n = (n + shift) pi (Sec. 4, Remark 4.1):
+// shift enters as N_n = n + shift.
 constexpr int HANK_NU_MAX = 8;
 constexpr int64_t HANK_SHIFT_MAX = 1024;
 struct Grid {

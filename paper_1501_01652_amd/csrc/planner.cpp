@@ -32,8 +32,9 @@ double Grid::ztilde(int64_t k, int64_t n) const {
 Grid make_grid(int task, int64_t N, int nu, int64_t shift) {
     if (nu < 0 || nu > HANK_NU_MAX || shift < 0 || shift > HANK_SHIFT_MAX)
         throw std::invalid_argument("nu must lie in [0, 8] and shift in [0, 1024]");
-    if ((nu != 0 || shift != 0) && task != T_SCHL && task != T_SCHL_PG)
-        throw std::invalid_argument("nu and shift apply to the Schlomilch tasks only");
+    if (nu != 0 && task == T_DHT) throw std::invalid_argument("nu applies to the Schlomilch and Fourier-Bessel tasks");
+    if (shift != 0 && task != T_SCHL && task != T_SCHL_PG)
+        throw std::invalid_argument("shift applies to the Schlomilch tasks only");
     Grid g;
     g.task = task;
     g.nu = nu;
@@ -575,7 +576,7 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
         p.T = 1;
         while (f * param_qT(p.T, eps) > 30.0) ++p.T;
         p.first_direct = int(std::floor(f * std::max(param_pK(p.K, eps), param_qT(p.T, eps))));
-        numax = (task == T_DHT) ? 2 * p.K - 2 : p.K - 1;
+        numax = (task == T_DHT) ? 2 * p.K - 2 : nu + p.K - 1; // orders nu -+ (K-1), Sec. 5.1
     }
     // the remainder bound of eq. (errorBound) holds for orders mu <= 2M + 1/2:
     // Table 4's M is raised to that where the orders need it (an explicit M is not)

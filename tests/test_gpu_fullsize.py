@@ -124,6 +124,18 @@ def test_schlomilch_order_nu_2pow20(nu, shift, eps):
     assert Cm <= C_TOL
 
 
+def test_fourier_bessel_order_nu_65536():
+    """eq. (FourierBessel) of order 3 at N = 2^16, eps = 1e-8, sampled rows."""
+    task, N, eps, nu = "fourier_bessel", 1 << 16, 1e-8, 3
+    c = inputs.workload(task, N)
+    rows = inputs.sampled_rows(N, 48, boundary_rows(task, N, eps, nu=nu))
+    f = host(hank.transform(task, dev(c), eps, nu=nu))
+    ref = oracle.eval_rows(task, c, rows=rows, nu=nu)
+    Cm = float(np.max(np.abs(f[rows - 1] - ref))) / (eps * float(np.sum(np.abs(c))))
+    print("fourier_bessel order 3 N=2^16 eps=1e-8 rows=%d measured C=%.3g" % (len(rows), Cm))
+    assert Cm <= C_TOL
+
+
 def test_dht0_2pow20_one_hot_columns():
     """c = e_n at the columns bordering every block: f_k = J_0(r_k w_n) for all k."""
     N, eps = 1 << 20, 1e-8

@@ -383,6 +383,42 @@ def test_order_nu_parity(task, nu, shift, N, eps, mode):
     assert Cm <= C_TOL
 
 
+@pytest.mark.parametrize("task", ["fourier_bessel", "fourier_bessel_paper_grid"])
+@pytest.mark.parametrize("nu", [1, 3, 8])
+@pytest.mark.parametrize("N", [2, 17, 300, 1500])
+@pytest.mark.parametrize("eps", [1e-4, 1e-8, 1e-14])
+@pytest.mark.parametrize("mode", ["tuned", "far", "paper"])
+def test_fourier_bessel_order_nu_parity(task, nu, N, eps, mode):
+    """eq. (FourierBessel): J_nu at the roots of J_0, root offsets in z."""
+    c, ref = oracle_nu(task, N, nu, 0)
+    kw = {"tuned": {}, "far": {"prefer_far": 1}, "paper": {"plan_mode": 1}}[mode]
+    f = host(hank.transform(task, dev(c), eps, nu=nu, **kw))
+    Cm = measured_C(f, ref, eps, c)
+    nb = hank.plan_info(task, N, eps, nu=nu, **kw)["nblocks"]
+    print("%s nu=%d N=%d eps=%g %s blocks=%d measured C=%.3g" % (task, nu, N, eps, mode, nb, Cm))
+    assert Cm <= C_TOL
+
+
+@pytest.mark.parametrize("nu,eps", [(2, 1e-14), (8, 1e-8)])
+@pytest.mark.parametrize("mode", ["far", "paper"])
+def test_fourier_bessel_order_nu_one_hot_columns(nu, eps, mode):
+    task, N = "fourier_bessel", 3000
+    kw = {"far": {"prefer_far": 1}, "paper": {"plan_mode": 1}}[mode]
+    info = hank.plan_info(task, N, eps, nu=nu, **kw)
+    cols = {1, 2, N, max(1, info["first_direct"]), min(N, info["first_direct"] + 1)}
+    for b in hank.plan_blocks(task, N, eps, nu=nu, **kw):
+        cols |= {b["col0"] - 1, b["col0"], b["col0"] + 1, b["col1"]}
+    worst = 0.0
+    for n in sorted(x for x in cols if 1 <= x <= N):
+        c = np.zeros(N)
+        c[n - 1] = 1.0
+        f = host(hank.transform(task, dev(c), eps, nu=nu, **kw))
+        ref = oracle.eval_rows(task, c, nu=nu)
+        worst = max(worst, float(np.max(np.abs(f - ref))))
+    print("FB order %d eps=%g %s: worst entry error %.3g (%.3g eps)" % (nu, eps, mode, worst, worst / eps))
+    assert worst <= C_TOL * eps
+
+
 @pytest.mark.parametrize("nu,shift,eps", [(3, 3, 1e-14), (8, 0, 1e-8), (1, 1, 1e-4)])
 @pytest.mark.parametrize("mode", ["far", "paper"])
 def test_order_nu_one_hot_columns(nu, shift, eps, mode):
@@ -430,6 +466,8 @@ def test_order_nu_rejected_where_undefined():
     for kw in ({"nu": 1}, {"shift": 2}):
         with pytest.raises(hank.HankError):
             hank.transform("dht0", c, 1e-8, out=out, **kw)
+    with pytest.raises(hank.HankError):
+        hank.transform("fourier_bessel", c, 1e-8, out=out, shift=1)
     with pytest.raises(hank.HankError):
         hank.transform("schlomilch", c, 1e-8, out=out, nu=9)
     assert np.all(np.isnan(host(out)))
