@@ -204,6 +204,7 @@ size_t group_batch(size_t bytes_per_group, size_t ngroups) {
 struct NearRule {
     double zM[6]; // s_{0,M} for M = 2, 3, 4, 6, 8, 12
     bool mix6;    // 6 pairs suffice at z = 20
+    bool small8;  // 8 terms of the small-argument pieces suffice (budget >= 1.25e-9)
 };
 
 NearRule near_rule(const Plan& p) {
@@ -212,6 +213,7 @@ NearRule near_rule(const Plan& p) {
     NearRule r{};
     for (int i = 0; i < 6; ++i) r.zM[i] = param_s(0, Ms[i], e);
     r.mix6 = r.zM[3] <= J0_ASY_Z;
+    r.small8 = e >= 1.25e-9;
     return r;
 }
 
@@ -220,8 +222,8 @@ NearRule near_rule(const Plan& p) {
 // z <= z~ + 0.25.
 int near_block_variant(const Grid& g, const NearRule& r, int64_t k0, int64_t k1, int64_t n0, int64_t n1) {
     const double zlo = g.ztilde(k0, n0), zhi = g.ztilde(k1, n1) + 0.25;
-    if (!(zhi >= J0_ASY_Z)) return NV_SMALL;
-    if (zlo < J0_ASY_Z) return r.mix6 ? NV_MIX6 : NV_MIX12;
+    if (!(zhi >= J0_ASY_Z)) return r.small8 ? NV_SMALL8 : NV_SMALL;
+    if (zlo < J0_ASY_Z) return r.mix6 ? (r.small8 ? NV_MIX6_8 : NV_MIX6) : (r.small8 ? NV_MIX12_8 : NV_MIX12);
     const int codes[6] = {NV_M2, NV_M3, NV_M4, NV_M6, NV_M8, NV_M12};
     for (int i = 0; i < 6; ++i)
         if (r.zM[i] <= zlo) return codes[i];
@@ -230,7 +232,7 @@ int near_block_variant(const Grid& g, const NearRule& r, int64_t k0, int64_t k1,
 
 // relative cost per entry of each variant (VALU operations, measured from the
 // compiled loops)
-constexpr double NV_COST[NV_COUNT] = {0.9, 1.9, 1.7, 0.85, 0.9, 1.0, 1.1, 1.2, 1.35};
+constexpr double NV_COST[NV_COUNT] = {0.9, 1.9, 1.7, 0.85, 0.9, 1.0, 1.1, 1.2, 1.35, 0.7, 1.7, 1.5};
 
 hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
     const Plan& p = dp.plan;

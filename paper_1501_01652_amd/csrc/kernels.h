@@ -32,7 +32,13 @@ constexpr int NEAR_TILE_COLS = 2048;
 // error budget: NV_SMALL only z < 20 (tabulated Taylor pieces), NV_MIX* both
 // branches (each lane takes its own; the Hankel side with 12 or 6 pairs),
 // NV_M* only z >= 20 with 2..12 Hankel pairs.
-enum NearVariant { NV_SMALL = 0, NV_MIX12, NV_MIX6, NV_M2, NV_M3, NV_M4, NV_M6, NV_M8, NV_M12, NV_COUNT };
+// NV_*8: the same with the tabulated small-argument pieces truncated to 8 terms
+// (error below 6.2e-10, for per-entry budgets from 1.25e-9 up; the
+// multiple-right-hand-side kernel runs them in full).
+enum NearVariant {
+    NV_SMALL = 0, NV_MIX12, NV_MIX6, NV_M2, NV_M3, NV_M4, NV_M6, NV_M8, NV_M12,
+    NV_SMALL8, NV_MIX12_8, NV_MIX6_8, NV_COUNT
+};
 
 // near-field work item of a plan: rows [k0, k0+nk) x columns [n0, n1).  Its
 // partial sums (nrhs x 64) sit in slot `slot` of the transform's partial

@@ -270,17 +270,17 @@ __device__ __forceinline__ double near_z_exact(const GridArgs& G, const NearLane
 // J_0 at the lane's current column, then one step on
 // (both branches: each lane takes its own, so a wave pays for both only where
 // its rows straddle z = 20)
-template <int M, bool SMALL, bool ASY, bool PERT>
+template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG>
 __device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, double bn) {
     double J;
     if (SMALL && ASY) {
         const double z = near_z_exact(G, r, bn);
         if (z < J0_ASY_Z)
-            J = j0_small(z);
+            J = j0_small<NT>(z);
         else
             J = near_asy<M, PERT>(G, r, bn);
     } else if (SMALL) {
-        J = j0_small(near_z_exact(G, r, bn));
+        J = j0_small<NT>(near_z_exact(G, r, bn));
     } else {
         J = near_asy<M, PERT>(G, r, bn);
     }
@@ -316,13 +316,13 @@ __device__ __forceinline__ int tile_block_variant(const NearTile& T, int64_t nb)
 }
 
 // One 64-column block of a sweep: the lane's columns p[0], p[4], ... (cnt of them)
-template <int M, bool SMALL, bool ASY, bool PERT>
+template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG>
 __device__ __forceinline__ void near_block(const GridArgs& G, const ColCB* p, int cnt, NearLane& r, double& acc) {
     if (ASY) near_anchor(G, r);
     HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
     for (int i = 0; i < cnt; ++i) {
         const ColCB v = p[4 * i];
-        acc = fma(v.c, near_step<M, SMALL, ASY, PERT>(G, r, PERT ? v.b : 0.0), acc);
+        acc = fma(v.c, near_step<M, SMALL, ASY, PERT, NT>(G, r, PERT ? v.b : 0.0), acc);
     }
 }
 
@@ -339,10 +339,14 @@ __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb,
         const int cnt = (int)min<int64_t>(16, (T.n1 - nw + 3) / 4);
         const ColCB* p = cb + (nw - T.n0);
 #define BLOCK(M_, S_, A_) near_block<M_, S_, A_, PERT>(G, p, cnt, r, acc); break
+#define BLOCK8(M_, A_) near_block<M_, true, A_, PERT, 8>(G, p, cnt, r, acc); break
         switch (tile_block_variant(T, nb)) {
         case NV_SMALL: BLOCK(3, true, false);
         case NV_MIX12: BLOCK(12, true, true);
         case NV_MIX6: BLOCK(6, true, true);
+        case NV_SMALL8: BLOCK8(3, false);
+        case NV_MIX12_8: BLOCK8(12, true);
+        case NV_MIX6_8: BLOCK8(6, true);
         case NV_M2: BLOCK(2, false, true);
         case NV_M3: BLOCK(3, false, true);
         case NV_M4: BLOCK(4, false, true);
@@ -350,6 +354,7 @@ __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb,
         case NV_M8: BLOCK(8, false, true);
         default: BLOCK(12, false, true);
         }
+#undef BLOCK8
 #undef BLOCK
         near_skip16(r);
     }
@@ -470,7 +475,10 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
         }
         __syncthreads();
 #define BLOCK(M_, S_, A_) near_multi_block<M_, S_, A_, PERT>(G, R, Cs, Bs, nb, T.n1, kq, lane, nblk, acc); break
-        switch (tile_block_variant(T, nb)) {
+        // the 8-term small-argument codes run in full here
+        int var = tile_block_variant(T, nb);
+        var = var == NV_SMALL8 ? NV_SMALL : var == NV_MIX12_8 ? NV_MIX12 : var == NV_MIX6_8 ? NV_MIX6 : var;
+        switch (var) {
         case NV_SMALL: BLOCK(3, true, false);
         case NV_MIX12: BLOCK(12, true, true);
         case NV_MIX6: BLOCK(6, true, true);
