@@ -12,7 +12,9 @@
  *                            w_n = j_{0,n},     r_k = j_{0,k}/j_{0,N+1} (Sec. 6, eq. (DHT))
  *
  * with j_{0,n} the n-th positive root of J_0.  The Schlomilch and
- * Fourier-Bessel tasks also exist on the paper's own grid r_k = k/N.
+ * Fourier-Bessel tasks also exist on the paper's own grid r_k = k/N, and both
+ * may be of integer order nu <= 8 (J_nu in place of J_0; hank_options.nu).
+ * The inverse DHT is hank_dht0_inverse.
  *
  * The result is accurate to O(eps * sum_n |c_n|) (Sec. 1): the library picks
  * every algorithmic parameter (number of asymptotic terms, block partition,
