@@ -131,6 +131,8 @@ typedef struct {
     double eps;
     const double* c;
     double* out;
+    int32_t nu;    /* as hank_options.nu (order; Schlomilch and Fourier-Bessel) */
+    int32_t shift; /* as hank_options.shift (Schlomilch)                         */
 } hank_request;
 
 hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t stream);

@@ -70,7 +70,8 @@ class KernelStat(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("task", ctypes.c_int32), ("precision", ctypes.c_int32), ("N", ctypes.c_int64),
                 ("nrhs", ctypes.c_int64), ("ldc", ctypes.c_int64), ("ldo", ctypes.c_int64),
-                ("eps", ctypes.c_double), ("c", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+                ("eps", ctypes.c_double), ("c", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("nu", ctypes.c_int32), ("shift", ctypes.c_int32)]
 
 
 _lib = None
@@ -255,13 +256,14 @@ def _requests(requests):
         N = c.shape[-1]
         nrhs = 1 if c.dim() == 1 else c.shape[0]
         arr[i] = Request(_task(r["task"]), int(r.get("precision", 0)), N, nrhs, N, N, float(r["eps"]),
-                         c.data_ptr(), o.data_ptr())
+                         c.data_ptr(), o.data_ptr(), int(r.get("nu", 0)), int(r.get("shift", 0)))
     return arr, len(reqs)
 
 
 def batch(requests, stream=None):
     """Submit many transforms at once.  requests: iterable of dicts with keys
-    task, c, out, eps and optionally precision (c, out of shape (N,) or (nrhs, N))."""
+    task, c, out, eps and optionally precision, nu, shift (c, out of shape (N,)
+    or (nrhs, N))."""
     arr, n = _requests(requests)
     _check(lib().hank_batch(arr, n, _stream(stream)))
 
@@ -430,7 +432,7 @@ def _request(r) -> Request:
     N = c.shape[-1]
     nrhs = 1 if c.dim() == 1 else c.shape[0]
     return Request(_task(r["task"]), int(r.get("precision", 0)), N, nrhs, N, N, float(r["eps"]),
-                   c.data_ptr(), o.data_ptr())
+                   c.data_ptr(), o.data_ptr(), int(r.get("nu", 0)), int(r.get("shift", 0)))
 
 
 class Server:

@@ -1060,6 +1060,8 @@ hank_status hank_server_warm(hank_server* srv, const hank_request* r) {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
     hank_options o{};
     o.precision = r->precision;
+    o.nu = r->nu;
+    o.shift = r->shift;
     DevPlan* dp = nullptr;
     return get_plan(r->task, r->N, r->eps, &o, srv->stream, dp, r->nrhs);
 }
@@ -1074,6 +1076,8 @@ hank_status hank_server_submit(hank_server* srv, const hank_request* r, double a
         std::lock_guard<std::recursive_mutex> lk(g_mu);
         hank_options o{};
         o.precision = r->precision;
+        o.nu = r->nu;
+        o.shift = r->shift;
         DevPlan* dp = nullptr;
         if ((st = get_plan(r->task, r->N, r->eps, &o, srv->stream, dp, r->nrhs))) return st;
         bytes = request_bytes(*dp, r->nrhs);
@@ -1260,6 +1264,8 @@ static hank_status batch_jobs(const hank_request* reqs, int64_t count, hipStream
     for (int64_t i = 0; i < count; ++i) {
         hank_options o{};
         o.precision = reqs[i].precision;
+        o.nu = reqs[i].nu;
+        o.shift = reqs[i].shift;
         Key k = plan_key(reqs[i].task, reqs[i].N, reqs[i].eps, &o, dev, reqs[i].nrhs);
         if (!g_cache.count(k) && !fresh.count(k)) fresh[k] = {i, Plan()};
     }
@@ -1273,9 +1279,11 @@ static hank_status batch_jobs(const hank_request* reqs, int64_t count, hipStream
                 const hank_request& r = reqs[todo[t]->second.first];
                 hank_options o{};
                 o.precision = r.precision;
+                o.nu = r.nu;
+                o.shift = r.shift;
                 try {
                     todo[t]->second.second = make_plan(r.task, r.N, r.eps, 0, r.precision, false, cost_model_for(&o),
-                                                       rhs_bucket(r.nrhs));
+                                                       rhs_bucket(r.nu > 0 ? 1 : r.nrhs), 0, r.nu, r.shift);
                 } catch (...) {
                     bad = true;
                 }
@@ -1292,6 +1300,8 @@ static hank_status batch_jobs(const hank_request* reqs, int64_t count, hipStream
         const hank_request& r = reqs[i];
         hank_options o{};
         o.precision = r.precision;
+        o.nu = r.nu;
+        o.shift = r.shift;
         DevPlan* dp = nullptr;
         auto it = fresh.find(plan_key(r.task, r.N, r.eps, &o, dev, r.nrhs));
         const Plan* pre = (fresh.size() > 1 && it != fresh.end()) ? &it->second.second : nullptr;

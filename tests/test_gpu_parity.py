@@ -471,3 +471,37 @@ def test_order_nu_rejected_where_undefined():
     with pytest.raises(hank.HankError):
         hank.transform("schlomilch", c, 1e-8, out=out, nu=9)
     assert np.all(np.isnan(host(out)))
+
+
+def test_batch_with_order_nu_requests():
+    """Order-nu and shifted requests in a batch (and in a captured graph) give
+    bitwise the results of single calls, next to order-0 requests."""
+    rng = np.random.default_rng(77)
+    specs = [("schlomilch", 1500, 1e-8, 3, 3, 1), ("fourier_bessel_paper_grid", 900, 1e-14, 2, 0, 3),
+             ("dht0", 1200, 1e-8, 0, 0, 2), ("schlomilch_paper_grid", 700, 1e-4, 0, 5, 1)]
+    reqs = []
+    for task, N, eps, nu, shift, nrhs in specs:
+        c = rng.standard_normal((nrhs, N) if nrhs > 1 else N)
+        reqs.append({"task": task, "c": dev(c), "out": dev(np.full(c.shape, np.nan)), "eps": eps, "nu": nu,
+                     "shift": shift})
+    hank.batch(reqs)
+    for r in reqs:
+        alone = host(hank.transform(r["task"], r["c"], r["eps"], nu=r["nu"], shift=r["shift"]))
+        assert np.array_equal(host(r["out"]), alone)
+    for r in reqs:
+        r["out"].fill_(float("nan"))
+    g = hank.BatchGraph(reqs)
+    g.launch()
+    torch.cuda.synchronize()
+    for r in reqs:
+        alone = host(hank.transform(r["task"], r["c"], r["eps"], nu=r["nu"], shift=r["shift"]))
+        assert np.array_equal(host(r["out"]), alone)
+    g.close()
+
+
+def test_batch_rejects_order_nu_on_dht():
+    c = dev(np.ones(64))
+    out = dev(np.full(64, np.nan))
+    with pytest.raises(hank.HankError):
+        hank.batch([{"task": "dht0", "c": c, "out": out, "eps": 1e-8, "nu": 1}])
+    assert np.all(np.isnan(host(out)))
