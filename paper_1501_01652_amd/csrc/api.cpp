@@ -85,6 +85,7 @@ struct DevPlan {
     int32_t mnu = NU_HANKEL_PAIRS; // Hankel pairs of the order-nu near field
     std::vector<NearTile> tiles; // host copies of the near-field tiles and row tiles
     std::vector<RowTile> rts;
+    int64_t rt_max_tiles = 0;    // most tiles of one row tile
     NearTile* d_tiles = nullptr; // the same on the device
     RowTile* d_rts = nullptr;
     std::vector<DevBlock> blocks;
@@ -291,6 +292,7 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
                 tiles.push_back(t);
             }
             r.ntiles = int64_t(tiles.size()) - r.slot0;
+            dp.rt_max_tiles = std::max(dp.rt_max_tiles, r.ntiles);
             rts.push_back(r);
         }
     // relative cost of a tile: its 64-column blocks priced by their variant
@@ -580,6 +582,8 @@ struct Prepared {
     std::vector<NearProb> probs; // single rhs order 0, then order nu > 0, then several rhs
     int32_t nsingle = 0, nnu = 0;
     int64_t pbase = 0, ntiles1 = 0, ntilesnu = 0, ntilesm = 0, nrts = 0;
+    int64_t nrts1 = 0; // row tiles of the problems with one right-hand side (the first ones)
+    int64_t nwv1 = 0;  // waves of their reduce
     double near_entries = 0, nu_entries = 0, multi_entries = 0;
     std::vector<FarDesc> descs;
     std::vector<FarLaunch> launches;
@@ -631,6 +635,16 @@ void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR) {
         count += nt;
         P.rt_start = nrts;
         nrts += int64_t(J.dp->rts.size());
+        if (J.nrhs == 1) {
+            PR.nrts1 = nrts;
+            P.wpr = J.dp->rt_max_tiles > 4 ? 4 : 1;
+            if (P.wpr == 4) PR.nwv1 = (PR.nwv1 + 3) & ~int64_t(3);
+            P.wv_start = PR.nwv1;
+            PR.nwv1 += int64_t(J.dp->rts.size()) * P.wpr;
+        } else {
+            P.wpr = 1;
+            P.wv_start = PR.nwv1; // after every wave of the reduce of single right-hand sides
+        }
         pbase += nt * J.nrhs * 64;
         (cls == 0 ? PR.nsingle : PR.nnu) += cls < 2;
         (cls == 0 ? PR.near_entries : cls == 1 ? PR.nu_entries : PR.multi_entries) +=
@@ -788,7 +802,7 @@ hank_status enqueue_jobs(const Prepared& PR, const NearProb* dprobs, const FarDe
         if ((st = prof_end(K_NEAR_MULTI, ev, 0.0, PR.multi_entries, s))) return st;
     }
     if ((st = prof_begin(ev, s))) return st;
-    HIP_TRY(launch_near_reduce(dprobs, nprob, nrts, dpart, s));
+    HIP_TRY(launch_near_reduce(dprobs, nprob, PR.nwv1, PR.nrts1, nrts, dpart, s));
     if ((st = prof_end(K_NEAR_REDUCE, ev, 8.0 * double(pbase), 0.0, s))) return st;
 
     for (auto& Ln : PR.launches) {

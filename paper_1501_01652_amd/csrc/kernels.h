@@ -61,7 +61,9 @@ struct RowTile {
 // perturbations e, the plan's tiles and row tiles (device), the grid offsets
 // of its first tile (tile_start, within the launch) and first row tile
 // (rt_start), and the start of its partial area (pbase; slot s of it at
-// pbase + s*nrhs*64).
+// pbase + s*nrhs*64).  With one right-hand side the reduce gives each row
+// tile wpr waves (1, or 4 when a row tile has more than 4 tiles), the first
+// of them at wave wv_start of its launch (a multiple of 4 when wpr = 4).
 struct NearProb {
     GridArgs G;
     const double* c;
@@ -70,10 +72,11 @@ struct NearProb {
     double* f;
     const NearTile* tiles;
     const RowTile* rts;
-    int64_t ldc, ldo, tile_start, rt_start, pbase;
+    int64_t ldc, ldo, tile_start, rt_start, pbase, wv_start;
     int32_t nrhs, nu;      // nu > 0: Schlomilch of order nu (k_near_nu, one right-hand side)
     const double* nutab;   // the plan's J_nu table (build_nu_table), nu > 0 only
-    int32_t mnu, pad;      // Hankel pairs k_near_nu needs at z >= 20 + nu/2 (<= NU_HANKEL_PAIRS)
+    int32_t mnu;           // Hankel pairs k_near_nu needs at z >= 20 + nu/2 (<= NU_HANKEL_PAIRS)
+    int32_t wpr;
 };
 
 struct GroupDev {
@@ -134,13 +137,15 @@ hipError_t launch_j0(const double* z, int64_t n, double* out, hipStream_t s);
 // Near field of nprob transforms with ntiles tiles in all: single
 // right-hand-side transforms (k_near) and transforms of 2..64 right-hand
 // sides (k_near_multi: J_0 evaluated once per entry as the A operand of
-// FP64 MFMA); then f = sum of the partials, nrt row tiles in all.
+// FP64 MFMA); then f = sum of the partials, nrt row tiles in all: those of
+// the problems with one right-hand side (the first ones) in nwv1 waves, the
+// others from row tile nrt1 on.
 hipError_t launch_near(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s);
 // near field of order nu > 0 (one right-hand side per problem)
 hipError_t launch_near_nu(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s);
 hipError_t launch_near_multi(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s);
-hipError_t launch_near_reduce(const NearProb* probs, int32_t nprob, int64_t nrt, const double* partial,
-                              hipStream_t s);
+hipError_t launch_near_reduce(const NearProb* probs, int32_t nprob, int64_t nwv1, int64_t nrt1, int64_t nrt,
+                              const double* partial, hipStream_t s);
 hipError_t launch_chirp_spectrum(const FarArgs& A, bool fp32, void* work, void* H, hipStream_t s);
 // Columns per workgroup of the column passes (A, C) for column FFTs of L2
 // points: 128-byte row segments (8 FP64 or 16 FP32 columns) for

@@ -642,32 +642,103 @@ __global__ __launch_bounds__(256) void k_near_nu(const NearProb* __restrict__ pr
     if (wave == 0) out[lane] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
-__global__ __launch_bounds__(256) void k_near_reduce(const NearProb* __restrict__ probs, int nprob,
-                                                     const double* __restrict__ partial) {
+// Row tiles of the single-right-hand-side problems (the first ones, row
+// tiles [0, nrt1)), wpr waves each from wave wv_start of the problem on:
+// wave sub of a row tile sums its tiles sub, sub + wpr, ... and with wpr = 4
+// the four sums (one workgroup) are added in wave order.  Waves past a
+// problem's last row tile (alignment padding) and past nwv write nothing.
+__global__ __launch_bounds__(256) void k_near_reduce1(const NearProb* __restrict__ probs, int nprob, int64_t nwv,
+                                                      int64_t nrt1, const double* __restrict__ partial) {
     __shared__ double red[4][64];
-    const NearProb& P = probs[find_desc<NearProb, &NearProb::rt_start>(probs, nprob, blockIdx.x)];
-    const RowTile R = P.rts[blockIdx.x - P.rt_start];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t per_tile = (int64_t)P.nrhs * 64;
-    const double* base = partial + P.pbase + R.slot0 * per_tile;
-    if (P.nrhs > 1) {
-        for (int j = wave; j < P.nrhs; j += 4) {
-            const double* q = base + (int64_t)j * 64 + lane;
-            double s = 0.0;
-            for (int64_t t = 0; t < R.ntiles; ++t) s += q[t * per_tile];
-            if (lane < R.nk) P.f[(int64_t)j * P.ldo + R.k0 + lane - 1] = s;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
+    const int pi = find_desc<NearProb, &NearProb::wv_start>(probs, nprob, gw < nwv ? gw : 0);
+    const NearProb& P = probs[pi];
+    const int wpr = P.wpr;
+    const int64_t local = gw - P.wv_start, rt_end = pi + 1 < nprob ? probs[pi + 1].rt_start : nrt1;
+    const int64_t rt = P.rt_start + local / wpr;
+    const int sub = (int)(local % wpr);
+    const bool valid = gw < nwv && rt < rt_end;
+    // wpr = 4 problems start at a multiple of 4 waves, so `four' is the same
+    // for every wave of a workgroup
+    const bool four = valid && wpr == 4;
+    double s = 0.0;
+    RowTile R{};
+    if (valid) {
+        R = P.rts[rt - P.rt_start];
+        const double* q = partial + P.pbase + R.slot0 * 64 + lane;
+        // four tiles per step, loads unconditional (clamped to the last tile)
+        // so that they are in flight together; the sum stays in tile order
+        const int64_t last = R.ntiles - 1;
+        for (int64_t t = sub; t <= last; t += 4 * wpr) {
+            double v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = q[min(t + i * wpr, last) * 64];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (t + i * wpr <= last) s += v[i];
         }
-        return;
     }
-    for (int j = 0; j < P.nrhs; ++j) {
-        double s = 0.0;
-        for (int64_t t = wave; t < R.ntiles; t += 4) s += base[t * per_tile + (int64_t)j * 64 + lane];
+    if (four) {
         red[wave][lane] = s;
         __syncthreads();
         if (wave == 0 && lane < R.nk)
-            P.f[(int64_t)j * P.ldo + R.k0 + lane - 1] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-        __syncthreads();
+            P.f[R.k0 + lane - 1] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    } else if (valid && lane < R.nk) {
+        P.f[R.k0 + lane - 1] = s;
     }
+}
+
+// A row tile's sums for nrhs > 1: its partials are E = nrhs x 64 contiguous
+// values per tile (right-hand side j, lane l at j*64 + l); thread i sums
+// elements i, i + 256, ... (PER of them, PER*256 >= E) over the tiles in
+// tile order.  The loads of one tile are unconditional (indices past E read
+// element E-1, and those sums are dropped), so they are all in flight at once.
+template <int PER>
+__device__ __forceinline__ void near_reduce_multi(const NearProb& P, const RowTile& R, const double* __restrict__ base,
+                                                  int E) {
+    double s[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) s[i] = 0.0;
+    for (int64_t t = 0; t < R.ntiles; ++t) {
+        const double* q = base + t * E;
+        double v[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) v[i] = q[min((int)threadIdx.x + 256 * i, E - 1)];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) s[i] += v[i];
+        // issue every load of the tile before the first add
+        __builtin_amdgcn_sched_group_barrier(0x020, PER, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, PER, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = (int)threadIdx.x + 256 * i, l = e & 63;
+        if (e < E && l < R.nk) P.f[(int64_t)(e >> 6) * P.ldo + R.k0 + l - 1] = s[i];
+    }
+}
+
+// One workgroup per row tile of a problem with several right-hand sides (row
+// tiles from rt0 on); up to 128 registers, so that 16 loads per thread fit
+// in flight.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_near_reduce(const NearProb* __restrict__ probs, int nprob, int64_t rt0,
+                                                     const double* __restrict__ partial) {
+    const int64_t rt = rt0 + blockIdx.x;
+    const NearProb& P = probs[find_desc<NearProb, &NearProb::rt_start>(probs, nprob, rt)];
+    const RowTile R = P.rts[rt - P.rt_start];
+    const int E = P.nrhs * 64; // nrhs <= 64
+    const double* base = partial + P.pbase + R.slot0 * E;
+    const int per = (E + 255) >> 8;
+    if (per <= 1)
+        near_reduce_multi<1>(P, R, base, E);
+    else if (per <= 2)
+        near_reduce_multi<2>(P, R, base, E);
+    else if (per <= 4)
+        near_reduce_multi<4>(P, R, base, E);
+    else if (per <= 8)
+        near_reduce_multi<8>(P, R, base, E);
+    else
+        near_reduce_multi<16>(P, R, base, E);
 }
 
 // ---------------------------------------------------------------------------
@@ -1078,9 +1149,15 @@ hipError_t launch_near_multi(const NearProb* probs, int32_t nprob, int64_t ntile
     return hipGetLastError();
 }
 
-hipError_t launch_near_reduce(const NearProb* probs, int32_t nprob, int64_t nrt, const double* partial,
-                              hipStream_t s) {
-    if (nrt > 0) hipLaunchKernelGGL(k_near_reduce, dim3((unsigned)nrt), dim3(256), 0, s, probs, (int)nprob, partial);
+hipError_t launch_near_reduce(const NearProb* probs, int32_t nprob, int64_t nwv1, int64_t nrt1, int64_t nrt,
+                              const double* partial, hipStream_t s) {
+    if (nrt1 < 0 || nrt1 > nrt || nwv1 < nrt1) return hipErrorInvalidValue;
+    if (nwv1 > 0)
+        hipLaunchKernelGGL(k_near_reduce1, dim3((unsigned)((nwv1 + 3) / 4)), dim3(256), 0, s, probs, (int)nprob, nwv1,
+                           nrt1, partial);
+    if (nrt > nrt1)
+        hipLaunchKernelGGL(k_near_reduce, dim3((unsigned)(nrt - nrt1)), dim3(256), 0, s, probs, (int)nprob, nrt1,
+                           partial);
     return hipGetLastError();
 }
 
