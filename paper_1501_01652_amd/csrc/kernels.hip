@@ -404,11 +404,13 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // (columns x nrhs) product on v_mfma_f64_16x16x4f64 whose A operand is J_0
 // evaluated in place.  Wave w owns rows 16w..16w+15; in a step of 4 columns
 // lane l evaluates J_0 for row 16w + l%16 and column l/16 -- exactly the A
-// layout (lane -> row l%16, k l/16) -- so J never goes through LDS, and each
-// lane sweeps its columns with stride 4 like k_near.  The coefficients of 64
-// columns at a time are staged in LDS as the B operand (lane -> k l/16,
-// right-hand side l%16); several workgroups per compute unit hide the
-// staging latency.
+// layout (lane -> row l%16, k l/16) -- so no lane needs another's J, and
+// each lane sweeps its columns with stride 4 like k_near.  Per 64-column
+// block a lane evaluates its 16 values (kept in its own slots of an LDS
+// buffer, so that the unrolled evaluations overlap) and then feeds them to
+// the MFMAs.  The coefficients of 64 columns at a time are staged in LDS as
+// the B operand (lane -> k l/16, right-hand side l%16); several workgroups
+// per compute unit hide the staging latency.
 // the fields of a NearProb that the sweeps use, held in scalar registers
 struct NearJob {
     GridArgs G;
@@ -431,14 +433,41 @@ __device__ __forceinline__ NearJob near_job(const NearProb& P) {
 }
 
 constexpr int CS_LD = 80; // row stride of the coefficient tile (16 mod 32 banks)
+#ifndef HANK_MULTI_UNROLL
+#define HANK_MULTI_UNROLL 1
+#endif
 
-// 16 steps of 4 columns (one 64-column block) of the multi right-hand-side product
+// 16 steps of 4 columns (one 64-column block) of the multi right-hand-side
+// product.  With HANK_MULTI_STAGE the lane first evaluates its 16 values of J
+// (steps unrolled like k_near, so that their chains overlap) into its wave's
+// LDS slice Js and then feeds them to the MFMAs; otherwise each J goes
+// straight into its MFMA.
+#ifndef HANK_MULTI_STAGE
+#define HANK_MULTI_STAGE 1
+#endif
 template <int M, bool SMALL, bool ASY, bool PERT>
 __device__ __forceinline__ void near_multi_block(const GridArgs& G, NearLane& R, const double (*Cs)[CS_LD],
-                                                 const double* Bs, int64_t nb, int64_t n1, int kq, int lane, int nblk,
-                                                 v4d (&acc)[4]) {
+                                                 const double* Bs, double* Js, int64_t nb, int64_t n1, int kq,
+                                                 int lane, int nblk, v4d (&acc)[4]) {
     if (ASY) near_anchor(G, R);
+#if HANK_MULTI_STAGE
+    HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
+    for (int i = 0; i < 16; ++i) {
+        const int col = 4 * i + kq;
+        const double J = near_step<M, SMALL, ASY, PERT>(G, R, PERT ? Bs[col] : 0.0);
+        Js[64 * i + lane] = (R.active && nb + col < n1) ? J : 0.0;
+    }
 #pragma unroll 1
+    for (int i = 0; i < 16; ++i) {
+        const int col = 4 * i + kq;
+        const double J = Js[64 * i + lane]; // written by this lane
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+            if (jb < nblk) acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(J, Cs[col][16 * jb + (lane & 15)], acc[jb], 0, 0, 0);
+    }
+#else
+    (void)Js;
+    HANK_PRAGMA(unroll HANK_MULTI_UNROLL)
     for (int i = 0; i < 16; ++i) {
         const int col = 4 * i + kq;
         double J = near_step<M, SMALL, ASY, PERT>(G, R, PERT ? Bs[col] : 0.0);
@@ -447,11 +476,12 @@ __device__ __forceinline__ void near_multi_block(const GridArgs& G, NearLane& R,
         for (int jb = 0; jb < 4; ++jb)
             if (jb < nblk) acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(J, Cs[col][16 * jb + (lane & 15)], acc[jb], 0, 0, 0);
     }
+#endif
 }
 
 template <bool PERT>
 __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile& T, double (*Cs)[CS_LD],
-                                                double* Bs, double* __restrict__ out) {
+                                                double* Bs, double* Js, double* __restrict__ out) {
     const GridArgs& G = P.G;
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -474,7 +504,7 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
             if (PERT && t < 64) Bs[t] = n < T.n1 ? P.b[n - 1] : 0.0;
         }
         __syncthreads();
-#define BLOCK(M_, S_, A_) near_multi_block<M_, S_, A_, PERT>(G, R, Cs, Bs, nb, T.n1, kq, lane, nblk, acc); break
+#define BLOCK(M_, S_, A_) near_multi_block<M_, S_, A_, PERT>(G, R, Cs, Bs, Js + 1024 * wave, nb, T.n1, kq, lane, nblk, acc); break
         // the 8-term small-argument codes run in full here
         int var = tile_block_variant(T, nb);
         var = var == NV_SMALL8 ? NV_SMALL : var == NV_MIX12_8 ? NV_MIX12 : var == NV_MIX6_8 ? NV_MIX6 : var;
@@ -508,20 +538,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                     double* __restrict__ partial) {
     __shared__ double Cs[64][CS_LD];
     __shared__ double Bs[64];
+#if HANK_MULTI_STAGE
+    __shared__ double Js[4 * 1024]; // per wave: J of its 16 steps x 64 lanes
+#else
+    double* Js = nullptr;
+#endif
     const NearProb& Pr = probs[find_desc<NearProb, &NearProb::tile_start>(probs, nprob, blockIdx.x)];
     const NearTile T = Pr.tiles[blockIdx.x - Pr.tile_start];
     const NearJob P = near_job(Pr); // by value: scalar registers, loaded once
     double* out = partial + Pr.pbase + T.slot * (int64_t)P.nrhs * 64;
     if (P.G.col_pert)
-        near_multi_body<true>(P, T, Cs, Bs, out);
+        near_multi_body<true>(P, T, Cs, Bs, Js, out);
     else
-        near_multi_body<false>(P, T, Cs, Bs, out);
+        near_multi_body<false>(P, T, Cs, Bs, Js, out);
 }
 
-// f_k = sum of the row's tile partials, per right-hand side.  One right-hand
-// side: 4 waves take every 4th tile and their sums are combined in a fixed
-// order; several: wave w sums right-hand sides w, w+4, ... over the tiles in
-// order.
 // ---------------------------------------------------------------------------
 // Near field of order nu > 0 (Schlomilch, Sec. 4; Fourier-Bessel, Sec. 5, whose
 // z = z~ + r^_k b_n carries the root offset b_n): J_nu at each entry from the
