@@ -85,9 +85,11 @@ struct DevPlan {
     int32_t mnu = NU_HANKEL_PAIRS; // Hankel pairs of the order-nu near field
     std::vector<NearTile> tiles; // host copies of the near-field tiles and row tiles
     std::vector<RowTile> rts;
-    int64_t rt_max_tiles = 0;    // most tiles of one row tile
-    NearTile* d_tiles = nullptr; // the same on the device
+    std::vector<RowTile> rts_red; // the row tiles that do not have exactly one tile
+    int64_t rt_max_tiles = 0;     // most tiles of one row tile
+    NearTile* d_tiles = nullptr;  // the same on the device
     RowTile* d_rts = nullptr;
+    RowTile* d_rts_red = nullptr;
     std::vector<DevBlock> blocks;
     void* work = nullptr; // chirp-spectrum scratch during the build
     size_t bytes = 0;
@@ -107,6 +109,7 @@ struct DevPlan {
         fr(work);
         fr(d_tiles);
         fr(d_rts);
+        fr(d_rts_red);
         for (auto& d : blocks) {
             fr(d.H);
             fr(d.H32);
@@ -293,6 +296,10 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
             }
             r.ntiles = int64_t(tiles.size()) - r.slot0;
             dp.rt_max_tiles = std::max(dp.rt_max_tiles, r.ntiles);
+            if (r.ntiles == 1)
+                tiles.back().sole = 1;
+            else
+                dp.rts_red.push_back(r);
             rts.push_back(r);
         }
     // relative cost of a tile: its 64-column blocks priced by their variant
@@ -306,10 +313,14 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
                      [&](const NearTile& a, const NearTile& b) { return tile_cost(a) > tile_cost(b); });
     if ((st = dev_alloc(dp.d_tiles, tiles.size(), dp.bytes))) return st;
     if ((st = dev_alloc(dp.d_rts, rts.size(), dp.bytes))) return st;
+    if ((st = dev_alloc(dp.d_rts_red, dp.rts_red.size(), dp.bytes))) return st;
     if (!tiles.empty())
         HIP_TRY(hipMemcpyAsync(dp.d_tiles, tiles.data(), tiles.size() * sizeof(NearTile), hipMemcpyHostToDevice, s));
     if (!rts.empty())
         HIP_TRY(hipMemcpyAsync(dp.d_rts, rts.data(), rts.size() * sizeof(RowTile), hipMemcpyHostToDevice, s));
+    if (!dp.rts_red.empty())
+        HIP_TRY(hipMemcpyAsync(dp.d_rts_red, dp.rts_red.data(), dp.rts_red.size() * sizeof(RowTile),
+                               hipMemcpyHostToDevice, s));
 
     // far-field blocks (the scratch only holds one chirp kernel at a time)
     size_t work_elems = 0;
@@ -620,7 +631,11 @@ void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR) {
         P.e = J.dp->e;
         P.f = J.f;
         P.tiles = J.dp->d_tiles;
-        P.rts = J.dp->d_rts;
+        // k_near writes the rows of sole tiles itself: its problems reduce
+        // only the other row tiles
+        const bool own = near_class(J) == 0;
+        P.rts = own ? J.dp->d_rts_red : J.dp->d_rts;
+        const int64_t nrt = int64_t(own ? J.dp->rts_red.size() : J.dp->rts.size());
         P.ldc = J.ldc;
         P.ldo = J.ldo;
         P.nrhs = int32_t(J.nrhs);
@@ -634,13 +649,13 @@ void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR) {
         P.tile_start = count;
         count += nt;
         P.rt_start = nrts;
-        nrts += int64_t(J.dp->rts.size());
+        nrts += nrt;
         if (J.nrhs == 1) {
             PR.nrts1 = nrts;
             P.wpr = J.dp->rt_max_tiles > 4 ? 4 : 1;
             if (P.wpr == 4) PR.nwv1 = (PR.nwv1 + 3) & ~int64_t(3);
             P.wv_start = PR.nwv1;
-            PR.nwv1 += int64_t(J.dp->rts.size()) * P.wpr;
+            PR.nwv1 += nrt * P.wpr;
         } else {
             P.wpr = 1;
             P.wv_start = PR.nwv1; // after every wave of the reduce of single right-hand sides

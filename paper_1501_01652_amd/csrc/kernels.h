@@ -46,7 +46,8 @@ enum NearVariant {
 // 4(b%8).. of bvar[b/8].
 struct NearTile {
     int64_t k0, n0, n1, slot;
-    int32_t nk, pad;
+    int32_t nk;
+    int32_t sole; // the only tile of its rows: k_near writes f itself (the other kernels ignore it)
     uint32_t bvar[4];
 };
 

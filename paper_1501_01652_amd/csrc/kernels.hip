@@ -395,7 +395,13 @@ void k_near(const NearProb* __restrict__ probs, int nprob, double* __restrict__ 
     const double acc = G.col_pert ? near_sweep<true>(G, cb, T, n, R) : near_sweep<false>(G, cb, T, n, R);
     red[wave][lane] = R.active ? acc : 0.0;
     __syncthreads();
-    if (wave == 0) out[lane] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    if (wave == 0) {
+        const double v = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        if (!T.sole)
+            out[lane] = v;
+        else if (lane < T.nk)
+            P.f[T.k0 + lane - 1] = v; // what the reduce would write: 0 + v
+    }
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
