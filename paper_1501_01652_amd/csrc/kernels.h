@@ -140,7 +140,9 @@ hipError_t launch_j0(const double* z, int64_t n, double* out, hipStream_t s);
 // sides (k_near_multi: J_0 evaluated once per entry as the A operand of
 // FP64 MFMA); then f = sum of the partials, nrt row tiles in all: those of
 // the problems with one right-hand side (the first ones) in nwv1 waves, the
-// others from row tile nrt1 on.
+// others from row tile nrt1 on.  k_near writes the rows of a tile that is the
+// only one of its row tile (NearTile::sole) itself, and the order-0
+// single-right-hand-side problems list only their other row tiles.
 hipError_t launch_near(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s);
 // near field of order nu > 0 (one right-hand side per problem)
 hipError_t launch_near_nu(const NearProb* probs, int32_t nprob, int64_t ntiles, double* partial, hipStream_t s);

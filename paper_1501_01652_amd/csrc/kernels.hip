@@ -363,9 +363,10 @@ __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb,
 
 // One workgroup = 64 rows (one per lane) x a column range of at most
 // NEAR_TILE_COLS; its 4 waves take every 4th column (the column data are
-// wave-uniform LDS reads) and their sums are added in a fixed order.  One
-// kernel serves every variant, so that tiles of all kinds share a launch and
-// fill the chip together.
+// wave-uniform LDS reads) and their sums are added in a fixed order, into the
+// tile's partial slot or, for the only tile of its rows, into f.  One kernel
+// serves every variant, so that tiles of all kinds share a launch and fill
+// the chip together.
 __global__ __launch_bounds__(256)
 #if HANK_NEAR_WPE
 __attribute__((amdgpu_waves_per_eu(HANK_NEAR_WPE)))
