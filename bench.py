@@ -101,7 +101,8 @@ def parse():
     ap.add_argument("--N", type=int, default=1 << 20)
     ap.add_argument("--eps", type=float, default=1e-8)
     ap.add_argument("--plan-mode", type=int, default=0)
-    ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--precision", type=int, default=1,
+                    help="1: every far transform in FP64 (the headline); 0: the library's automatic choice")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -109,8 +110,13 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=1024, help="requests of the batched workload (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--only", choices=["all", "headline", "batched", "serve", "copy", "ablation"], default="all")
+    ap.add_argument("--only", choices=["all", "headline", "batched", "serve", "copy", "ablation", "configs"],
+                    default="all")
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workloads (configs block)")
+    ap.add_argument("--oracle-rows", type=int, default=48,
+                    help="sampled output rows per large workload on which the CPU oracle is timed and "
+                         "the GPU result is compared")
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write the HBM traffic summary from rocprofv3 counter csv files and exit")
     return ap.parse_args()
@@ -186,7 +192,7 @@ def _median_ms(hank, torch, task, c, eps, out, reps, **kw):
     return sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(reps))[reps // 2]
 
 
-def run_ablation(hank, inputs, torch, task, N, eps, c_host):
+def run_ablation(hank, inputs, torch, task, N, eps, c_host, precision=1):
     """Cost-model ablations: the tuned partition against the paper's (Table 4)
     and against one far block (P = 0, Sec. 3.3) on the headline workload; and
     the M sweep of Sec. 4.3 (Schlomilch, N = 5000, paper plan, M = 1..20)."""
@@ -194,8 +200,8 @@ def run_ablation(hank, inputs, torch, task, N, eps, c_host):
     out = torch.empty_like(c)
     part = {}
     for name, mode in (("tuned", 0), ("paper", 1), ("single_partition", 2)):
-        info = hank.plan_info(task, N, eps, plan_mode=mode)
-        ms = _median_ms(hank, torch, task, c, eps, out, 5, plan_mode=mode)
+        info = hank.plan_info(task, N, eps, plan_mode=mode, precision=precision)
+        ms = _median_ms(hank, torch, task, c, eps, out, 5, plan_mode=mode, precision=precision)
         part[name] = {"ms": ms, "points_per_s": N / (ms * 1e-3), "M": info["M"], "P": info["P"],
                       "blocks": info["nblocks"], "near_entries": info["near_entries"],
                       "far_transforms": info["far_transforms"], "fft_bytes": info["fft_bytes"]}
@@ -254,6 +260,101 @@ def run_serve(hank, inputs, torch, seconds, rate, max_batch):
     return st
 
 
+def step_times(hank, torch, task, c, eps, out, steps, warmup, **kw):
+    """Per-step durations (ms) of `steps` transforms after `warmup` untimed
+    ones (the first call builds the plan), with events between steps only."""
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    hank.transform(task, c, eps, out=out, **kw)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        hank.transform(task, c, eps, out=out, **kw)
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for i in range(steps):
+        hank.transform(task, c, eps, out=out, stream=stream, **kw)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)], wall, plan_s
+
+
+def quantile(xs, q):
+    ys = sorted(xs)
+    return ys[min(len(ys) - 1, int(q * (len(ys) - 1) + 0.5))]
+
+
+class CpuBaseline:
+    """The CPU leg: the oracle (plain FP64 direct sums on the host cores) timed
+    on bounded row samples of each workload.  Its rows also give the measured
+    error constant C = max|f - f_oracle| / (eps sum|c|) of the GPU results on
+    the same rows."""
+
+    def __init__(self, nthreads=None):
+        import oracle
+        self.oracle = oracle
+        self.nthreads = nthreads or oracle.default_threads()
+        self.cache = {}
+
+    def rows(self, task, c_host, rows):
+        key = (task, c_host.shape[0], float(c_host[0]), np_bytes(rows))
+        if key not in self.cache:
+            self.oracle.eval_rows(task, c_host, rows=rows[:1], nthreads=1)  # roots set-up off the clock
+            t0 = time.perf_counter()
+            ref = self.oracle.eval_rows(task, c_host, rows=rows, nthreads=self.nthreads)
+            self.cache[key] = (ref, time.perf_counter() - t0)
+        return self.cache[key]
+
+
+def np_bytes(a):
+    import hashlib
+    return hashlib.sha256(a.tobytes()).hexdigest()
+
+
+def error_stats(np, f_rows, ref, c_host, eps):
+    err = float(np.max(np.abs(f_rows - ref)))
+    return {"max_abs_err": err, "C_l1": err / (eps * float(np.sum(np.abs(c_host)))),
+            "C_l2": err / (eps * float(np.sqrt(np.sum(c_host * c_host))))}
+
+
+def sample_rows(hank, inputs, task, N, eps, count, **kw):
+    """Rows to check: first and last rows, +-2 around every far block's first
+    row, and uniform ones (seeded)."""
+    info = hank.plan_info(task, N, eps, **kw)
+    bounds = []
+    for k in range(info["nblocks"]):
+        b = hank.plan_block(task, N, eps, k, **kw)
+        bounds += [b["row0"], b["row1"]]
+    return inputs.sampled_rows(N, count, boundaries=bounds, seed=inputs.SEED_SAMPLED_ROWS)
+
+
+def run_config(hank, inputs, torch, np, cpu, task, N, eps, precision, c_host, rows, steps=10, warmup=2):
+    """One workload: median/p90 time, points/s, the plan, and (with a CPU leg)
+    the measured error on the sampled rows."""
+    c = torch.from_numpy(c_host).to("cuda")
+    out = torch.empty_like(c)
+    kw = dict(precision=precision)
+    ts, _, plan_s = step_times(hank, torch, task, c, eps, out, steps, warmup, **kw)
+    info = hank.plan_info(task, N, eps, **kw)
+    rec = {"task": task, "N": N, "eps": eps, "precision": {0: "auto", 1: "fp64", 2: "fp32"}[precision],
+           "ms": quantile(ts, 0.5), "ms_p90": quantile(ts, 0.9), "points_per_s": N / (quantile(ts, 0.5) * 1e-3),
+           "plan_build_s": plan_s,
+           "plan": {"blocks": info["nblocks"], "near_entries": info["near_entries"],
+                    "far_transforms": info["far_transforms"], "fp32_transforms": info["fp32_transforms"],
+                    "fft_bytes": info["fft_bytes"]}}
+    if cpu is not None:
+        ref, tcpu = cpu.rows(task, c_host, rows)
+        f = out.cpu().numpy()[rows - 1]
+        rec["error"] = error_stats(np, f, ref, c_host, eps)
+        rec["error"]["rows_checked"] = int(len(rows))
+        rec["cpu_oracle_rows_per_s"] = len(rows) / tcpu
+    del c, out
+    return rec
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -272,6 +373,7 @@ def main():
     from paper_1501_01652_amd import inputs
 
     extra = {}
+    cpu = None if args.no_cpu else CpuBaseline()
 
     def run_extra():
         if args.only in ("all", "batched") and args.batch_count > 0:
@@ -284,6 +386,27 @@ def main():
                 "continuous_batching": run_serve(hank, inputs, torch, args.serve_seconds, args.serve_rate, 64),
                 "one_at_a_time": run_serve(hank, inputs, torch, args.serve_seconds, args.serve_rate, 1)}
 
+    def run_configs():
+        """The other workloads: Schlomilch N=4096 at 1e-14 (latency); Fourier-
+        Bessel N=2^16 at 1e-14 and 1e-8 with an FP64 and an FP32 transform bulk
+        side by side; the DHT at N=2^20 for eps 1e-4 (FP32 bulk, the automatic
+        choice at eps >= 1e-6) and 1e-14 (FP64)."""
+        out = []
+        cs = inputs.workload("schlomilch", 4096)
+        out.append(run_config(hank, inputs, torch, np, cpu, "schlomilch", 4096, 1e-14, 1, cs,
+                              np.arange(1, 4097, dtype=np.int64), steps=50, warmup=5))
+        cf = inputs.workload("fourier_bessel", 1 << 16)
+        for e in (1e-14, 1e-8):
+            rows = sample_rows(hank, inputs, "fourier_bessel", 1 << 16, e, 4 * args.oracle_rows, precision=1)
+            for prec in (1, 2):
+                out.append(run_config(hank, inputs, torch, np, cpu, "fourier_bessel", 1 << 16, e, prec, cf, rows))
+        cd = inputs.workload("dht0", 1 << 20)
+        for e, prec in ((1e-4, 0), (1e-14, 1)):
+            rows = sample_rows(hank, inputs, "dht0", 1 << 20, e, args.oracle_rows, precision=prec)
+            out.append(run_config(hank, inputs, torch, np, cpu, "dht0", 1 << 20, e, prec, cd, rows))
+        hank.cache_clear()
+        return out
+
     if args.only in ("batched", "serve"):
         run_extra()
         print(json.dumps(extra))
@@ -295,6 +418,9 @@ def main():
     if args.only == "copy":
         print(json.dumps(run_copy(torch)))
         return
+    if args.only == "configs":
+        print(json.dumps({"configs": run_configs()}))
+        return
 
     task, N, eps = args.task, args.N, args.eps
     c_host = inputs.workload(task, N)
@@ -303,24 +429,9 @@ def main():
     stream = torch.cuda.current_stream()
     kw = dict(plan_mode=args.plan_mode, precision=args.precision)
 
-    t0 = time.perf_counter()
-    hank.transform(task, c, eps, out=out, **kw)  # builds the plan
-    torch.cuda.synchronize()
-    plan_s = time.perf_counter() - t0
-    for _ in range(args.warmup):
-        hank.transform(task, c, eps, out=out, **kw)
-    torch.cuda.synchronize()
-
     # timed region: K steps with events between steps only
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    evs[0].record(stream)
-    for i in range(args.steps):
-        hank.transform(task, c, eps, out=out, stream=stream, **kw)
-        evs[i + 1].record(stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    step_ms, elapsed, plan_s = step_times(hank, torch, task, c, eps, out, args.steps, args.warmup, **kw)
+    f_head = out.cpu().numpy()
     # per-kernel durations: a second pass of K steps with HIP events around
     # every launch on the launch stream (kept out of the timed region above,
     # whose rate they would lower by about 4%)
@@ -335,9 +446,9 @@ def main():
     hank.profile(False)
     ms_per_step = 1e3 * elapsed / args.steps
     value = N * args.steps / elapsed
-    step_ms = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
-    step_q = lambda q: step_ms[min(len(step_ms) - 1, int(q * (len(step_ms) - 1) + 0.5))]
+    step_q = lambda q: quantile(step_ms, q)
     info = hank.plan_info(task, N, eps, **kw)
+    all_fp64 = info["fp32_transforms"] == 0 and not info["bulk_fp32"]
 
     # measured device copy bandwidth (read + write of COPY_BYTES), the
     # practical HBM ceiling beside the nominal peak
@@ -370,6 +481,16 @@ def main():
         if s["name"] == "near":
             k["entries_per_s"] = s["work"] / (s["total_ms"] * 1e-3) if s["total_ms"] > 0 else None
         kernels[s["name"]] = k
+    # the per-phase roofline of the plan: far-field passes against HBM, the
+    # near field against the FP64 vector peak, summed
+    far_bytes = sum(s["bytes"] for s in stats if s["name"].startswith("pass")) / args.steps
+    far_ms = sum(s["total_ms"] for s in stats if s["name"].startswith("pass")) / args.steps
+    near_s = [s for s in stats if s["name"] == "near"]
+    near_flops = near_s[0]["work"] * NEAR_FLOPS_PER_ENTRY / args.steps if near_s else 0.0
+    plan_roofline["phase_roofline_ms"] = 1e3 * (far_bytes / (HBM_PEAK_GBS * 1e9) +
+                                                near_flops / (FP64_VECTOR_TFLOPS * 1e12))
+    plan_roofline["far_passes_ms"] = far_ms
+    plan_roofline["far_passes_GBps"] = far_bytes / (far_ms * 1e-3) / 1e9 if far_ms > 0 else None
     dom = max(stats, key=lambda s: s["total_ms"]) if stats else None
     roofline = None
     if dom is not None:
@@ -399,6 +520,18 @@ def main():
         td = time.perf_counter() - t0
         direct = {"points_per_s": N / td, "ms": td * 1e3, "speedup_fast_vs_direct": value / (N / td)}
 
+    # the library's automatic precision choice on the same workload: FP64
+    # bulk with the transforms whose contribution is small enough in FP32
+    mixed = None
+    if args.precision != 0 and args.only == "all":
+        ts, _, _ = step_times(hank, torch, task, c, eps, out, args.steps, args.warmup, plan_mode=args.plan_mode,
+                              precision=0)
+        mi = hank.plan_info(task, N, eps, plan_mode=args.plan_mode, precision=0)
+        mixed = {"ms": quantile(ts, 0.5), "points_per_s": N / (quantile(ts, 0.5) * 1e-3),
+                 "fp32_transforms": mi["fp32_transforms"], "far_transforms": mi["far_transforms"],
+                 "near_entries": mi["near_entries"], "blocks": mi["nblocks"]}
+        f_mixed = out.cpu().numpy()
+
     inverse = None
     if task == "dht0" and args.only == "all":
         # the inverse DHT of Sec. 6 on the same plan, and the self-inverse
@@ -420,10 +553,11 @@ def main():
                    "c_max_abs": float(torch.max(torch.abs(c)).item())}
         del back
 
-    cpu = None
-    if not args.no_cpu:
+    cpu_line = None
+    head_err = None
+    if cpu is not None:
         import oracle
-        nthreads = oracle.default_threads()
+        nthreads = cpu.nthreads
         probe = inputs.sampled_rows(N, 4 * nthreads, seed=inputs.SEED_SAMPLED_ROWS)[:3 * nthreads]
         oracle.eval_rows(task, c_host, rows=probe[:1], nthreads=1)  # one-time set-up (roots) off the clock
         # marginal cost per row from two sample sizes (each call also has a fixed set-up)
@@ -438,30 +572,41 @@ def main():
         rows = np.sort(np.random.default_rng(inputs.SEED_SAMPLED_ROWS).choice(
             np.arange(1, N + 1), size=nrows, replace=False))
         t0 = time.perf_counter()
-        oracle.eval_rows(task, c_host, rows=rows, nthreads=nthreads)
+        ref = oracle.eval_rows(task, c_host, rows=rows, nthreads=nthreads)
         tc = time.perf_counter() - t0
-        cpu = {"value": nrows / tc, "unit": "points/s", "cores": nthreads, "kind": "oracle",
-               "sample": "%d of %d output rows (uniform, seed %d), each a full %d-term FP64 direct sum; "
-                         "%.1f s" % (nrows, N, inputs.SEED_SAMPLED_ROWS, N, tc)}
+        cpu_line = {"value": nrows / tc, "unit": "points/s", "cores": nthreads, "kind": "oracle",
+                    "sample": "%d of %d output rows (uniform, seed %d), each a full %d-term FP64 direct sum; "
+                              "%.1f s" % (nrows, N, inputs.SEED_SAMPLED_ROWS, N, tc)}
+        # the same rows measure the error of the timed results
+        head_err = error_stats(np, f_head[rows - 1], ref, c_host, eps)
+        head_err["rows_checked"] = int(nrows)
+        if mixed is not None:
+            mixed["error"] = error_stats(np, f_mixed[rows - 1], ref, c_host, eps)
+            mixed["error"]["rows_checked"] = int(nrows)
 
+    prec_desc = ("every one of the %d far transforms in FP64" % info["far_transforms"] if all_fp64 else
+                 "%d of %d far transforms in FP32" % (info["fp32_transforms"], info["far_transforms"]))
     line = {
         "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if info["bulk_fp32"] else "f64", "data": "synthetic",
-        "config": {"workload": "%s N=%d eps=%g, c_n iid N(0,1) seed %d, %s plan, %s transform bulk" % (
+        "vs_baseline": None, "dtype": "f64" if all_fp64 else "f64+f32", "data": "synthetic",
+        "config": {"workload": "%s N=%d eps=%g, c_n iid N(0,1) seed %d, %s plan, %s; FP64 near field and roots" % (
             task, N, eps, inputs.SEED_DHT0 if task == "dht0" else 0,
-            "paper" if args.plan_mode == 1 else "tuned", "fp32" if info["bulk_fp32"] else "fp64"),
+            "paper" if args.plan_mode == 1 else "tuned", prec_desc),
             "task": task, "N": N, "eps": eps, "blocks": info["nblocks"],
             "near_entries": info["near_entries"], "far_transforms": info["far_transforms"],
-            "plan_build_s": plan_s},
-        "roofline": roofline, "cpu_baseline": cpu, "direct_gpu": direct, "inverse_dht": inverse, "kernels": kernels,
-        "step_ms": {"median": step_q(0.5), "p90": step_q(0.9), "min": step_ms[0], "max": step_ms[-1]},
+            "fp32_transforms": info["fp32_transforms"], "plan_build_s": plan_s},
+        "roofline": roofline, "cpu_baseline": cpu_line, "error": head_err, "direct_gpu": direct,
+        "mixed_precision": mixed, "inverse_dht": inverse, "kernels": kernels,
+        "step_ms": {"median": step_q(0.5), "p90": step_q(0.9), "min": min(step_ms), "max": max(step_ms)},
         "profiled_ms_per_step": profiled_ms_per_step,
         "plan_roofline": plan_roofline,
     }
+    del c, out
+    if args.only == "all" and not args.no_configs:
+        line["configs"] = run_configs()
     if args.only == "all" and not args.no_ablation:
-        del c, out
-        line["ablation"] = run_ablation(hank, inputs, torch, task, N, eps, c_host)
+        line["ablation"] = run_ablation(hank, inputs, torch, task, N, eps, c_host, precision=args.precision)
     run_extra()
     line.update(extra)
     print(json.dumps(line))
