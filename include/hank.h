@@ -117,6 +117,29 @@ hank_status hank_transform(int32_t task, const double* c, int64_t N, int64_t nrh
                            int64_t ldc, double eps, double* out, int64_t ldo,
                            const hank_options* options, hank_stream_t stream);
 
+/* ---- Allocation-free form of hank_transform ---------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * transform as hank_transform, with its workspace (descriptors, near-field
+ * partial sums, far-field chunk sums and work buffer) taken from a static
+ * device array of HANK_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * GPU it runs on until the process ends.  It calls no hipMalloc, hipFree or
+ * other allocating routine, so it builds no plan: the plan for (task, N, eps,
+ * options, nrhs rounded up to a power of two) must be cached already, e.g. by
+ * one hank_transform call with the same arguments; otherwise it returns
+ * HANK_EUNSUPPORTED.  A transform whose workspace does not fit the array, even
+ * with the far field cut into single-group waves, also returns
+ * HANK_EUNSUPPORTED (large nrhs at large N).  Far-field groups may be summed
+ * in other waves than by hank_transform, so results agree with it to rounding,
+ * not bitwise.  Every call on a GPU shares that GPU's array: calls that can
+ * overlap on one GPU (different streams, several threads) race and must be
+ * ordered by the caller; calls on one stream are ordered by it.  Other
+ * arguments, errors and the effect on out as for hank_transform. */
+#define HANK_NOALLOC_SCRATCH_BYTES (256ll << 20)
+hank_status hank_transform_noalloc(int32_t task, const double* c, int64_t N, int64_t nrhs, int64_t ldc,
+                                   double eps, double* out, int64_t ldo, const hank_options* options,
+                                   hank_stream_t stream);
+
 /* ---- Batched submission ---------------------------------------------------
  * Enqueue many independent transforms (different tasks, N, eps, nrhs) at once;
  * their work is merged into shared launches.  Each request follows the

@@ -31,7 +31,8 @@ EXPORTS = ["hank_schlomilch", "hank_fourier_bessel", "hank_dht0", "hank_transfor
            "hank_server_create", "hank_server_warm", "hank_server_submit", "hank_server_start",
            "hank_server_drain", "hank_server_status", "hank_server_stats", "hank_server_destroy",
            "hank_batch_graph_create", "hank_batch_graph_launch", "hank_batch_graph_destroy",
-           "hank_autotune", "hank_autotune_reset", "hank_dht0_inverse", "hank_dht0_weights"]
+           "hank_autotune", "hank_autotune_reset", "hank_dht0_inverse", "hank_dht0_weights",
+           "hank_transform_noalloc"]
 
 
 class HankError(RuntimeError):
@@ -94,6 +95,8 @@ def lib():
                 f.argtypes = [p, i64, d, p, p]
             L.hank_transform.restype = i32
             L.hank_transform.argtypes = [i32, p, i64, i64, i64, d, p, i64, ctypes.POINTER(Options), p]
+            L.hank_transform_noalloc.restype = i32
+            L.hank_transform_noalloc.argtypes = [i32, p, i64, i64, i64, d, p, i64, ctypes.POINTER(Options), p]
             L.hank_batch.restype = i32
             L.hank_batch.argtypes = [ctypes.POINTER(Request), i64, p]
             L.hank_batch_graph_create.restype = i32
@@ -193,6 +196,23 @@ def transform(task, c, eps: float, out=None, plan_mode: int = 0, precision: int 
     opts = _options(plan_mode, precision, direct, prefer_far, 0, M, nu, shift)
     _check(lib().hank_transform(_task(task), ctypes.c_void_p(c.data_ptr()), N, nrhs, N, float(eps),
                                 ctypes.c_void_p(out.data_ptr()), N, ctypes.byref(opts), _stream(stream)))
+    return out
+
+
+def transform_noalloc(task, c, eps: float, out, plan_mode: int = 0, precision: int = 0, direct: int = 0,
+                      prefer_far: int = 0, stream=None, M: int = 0, nu: int = 0, shift: int = 0):
+    """transform() through hank_transform_noalloc: no device allocation in the
+    library (workspace from its static scratch array); the plan must be cached
+    by an earlier transform() with the same arguments, and `out` is required."""
+    c = _dev_f64(c, "c")
+    out = _dev_f64(out, "out")
+    if out.shape != c.shape:
+        raise ValueError("out must have the shape of c")
+    N = c.shape[-1]
+    nrhs = 1 if c.dim() == 1 else c.shape[0]
+    opts = _options(plan_mode, precision, direct, prefer_far, 0, M, nu, shift)
+    _check(lib().hank_transform_noalloc(_task(task), ctypes.c_void_p(c.data_ptr()), N, nrhs, N, float(eps),
+                                        ctypes.c_void_p(out.data_ptr()), N, ctypes.byref(opts), _stream(stream)))
     return out
 
 

@@ -545,14 +545,6 @@ hank_status ensure(Scratch& b, size_t bytes, hipStream_t s) {
     return HANK_OK;
 }
 
-template <typename T>
-hank_status upload(Scratch& b, const std::vector<T>& v, hipStream_t s) {
-    hank_status st = ensure(b, v.size() * sizeof(T), s);
-    if (st) return st;
-    if (!v.empty()) HIP_TRY(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    return HANK_OK;
-}
-
 // Workspace budget of one far-field wave (HANK_WAVE_MB, default 4096 MB).
 size_t wave_budget() {
     static const size_t b = [] {
@@ -601,7 +593,7 @@ struct Prepared {
     size_t work_need = 0, part_need = 0;
 };
 
-void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR) {
+void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR, size_t budget = wave_budget()) {
     // the near-field kernels take at most 64 right-hand sides: split wider jobs
     // (order nu > 0: one right-hand side per job)
     std::vector<Job> jobs;
@@ -673,7 +665,6 @@ void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR) {
     auto& launches = PR.launches;
     size_t maxblocks = 0;
     for (auto& J : jobs) maxblocks = std::max(maxblocks, J.dp->blocks.size());
-    const size_t budget = wave_budget();
     size_t& work_need = PR.work_need;
     for (size_t bi = 0; bi < maxblocks; ++bi) {
         // (job, group range) items of this wave
@@ -839,6 +830,25 @@ hank_status enqueue_jobs(const Prepared& PR, const NearProb* dprobs, const FarDe
     return HANK_OK;
 }
 
+// Copy the near and far descriptors of PR to dprobs and ddescs on stream s.
+// The host copies live in a ring of four slots, each reused only after the
+// copy that read it has completed.
+hank_status upload_descriptors(const Prepared& PR, void* dprobs, void* ddescs, hipStream_t s) {
+    UploadSlot& u = g_ex.slots[g_ex.next_slot];
+    g_ex.next_slot = (g_ex.next_slot + 1) % 4;
+    if (!u.done) HIP_TRY(hipEventCreateWithFlags(&u.done, hipEventDisableTiming));
+    if (u.pending) HIP_TRY(hipEventSynchronize(u.done));
+    u.probs = PR.probs;
+    u.descs = PR.descs;
+    if (!u.probs.empty())
+        HIP_TRY(hipMemcpyAsync(dprobs, u.probs.data(), u.probs.size() * sizeof(NearProb), hipMemcpyHostToDevice, s));
+    if (!u.descs.empty())
+        HIP_TRY(hipMemcpyAsync(ddescs, u.descs.data(), u.descs.size() * sizeof(FarDesc), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(u.done, s));
+    u.pending = true;
+    return HANK_OK;
+}
+
 hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
     hank_status st;
     Prepared PR;
@@ -863,16 +873,9 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
     add(PR.probs.data(), PR.probs.size() * sizeof(NearProb));
     add(PR.descs.data(), PR.descs.size() * sizeof(FarDesc));
     if (sig != g_ex.sig) {
-        UploadSlot& u = g_ex.slots[g_ex.next_slot];
-        g_ex.next_slot = (g_ex.next_slot + 1) % 4;
-        if (!u.done) HIP_TRY(hipEventCreateWithFlags(&u.done, hipEventDisableTiming));
-        if (u.pending) HIP_TRY(hipEventSynchronize(u.done));
-        u.probs = PR.probs;
-        u.descs = PR.descs;
-        if ((st = upload(g_ex.probs, u.probs, s))) return st;
-        if ((st = upload(g_ex.descs, u.descs, s))) return st;
-        HIP_TRY(hipEventRecord(u.done, s));
-        u.pending = true;
+        if ((st = ensure(g_ex.probs, PR.probs.size() * sizeof(NearProb), s))) return st;
+        if ((st = ensure(g_ex.descs, PR.descs.size() * sizeof(FarDesc), s))) return st;
+        if ((st = upload_descriptors(PR, g_ex.probs.p, g_ex.descs.p, s))) return st;
         g_ex.sig.swap(sig);
     }
     const NearProb* dprobs = static_cast<const NearProb*>(g_ex.probs.p);
@@ -1679,6 +1682,63 @@ hank_status hank_plan_block(int32_t task, int64_t N, double eps, const hank_opti
     out->terms = int32_t(b.terms.size());
     out->zmin = b.s0;
     return HANK_OK;
+}
+
+// ---- the allocation-free form of hank_transform ----
+// Workspace from the library's static device array (noalloc_scratch): near and
+// far descriptors, near-field partials, far-field chunk sums and the far work
+// buffer, in that order; the far field goes in as many group waves as the
+// array needs.  The plan must already be cached.
+hank_status hank_transform_noalloc(int32_t task, const double* c, int64_t N, int64_t nrhs, int64_t ldc, double eps,
+                                   double* out, int64_t ldo, const hank_options* options, hank_stream_t stream) {
+    hank_status st = check_args(task, c, N, nrhs, ldc, eps, out, ldo);
+    if (st) return st;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    void* base = nullptr;
+    HIP_TRY(noalloc_scratch(&base));
+    auto it = g_cache.find(plan_key(task, N, eps, options, dev, nrhs));
+    if (it == g_cache.end()) {
+        Plan p;
+        if ((st = host_plan(task, N, eps, options, p))) return st; // invalid options
+        return fail(HANK_EUNSUPPORTED,
+                    "hank_transform_noalloc: no plan for these arguments is cached on this device (it builds "
+                    "none); one hank_transform call with the same task, N, eps, options and nrhs builds it");
+    }
+    std::vector<Job> jobs{Job{it->second.get(), c, ldc, out, ldo, nrhs}};
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    Prepared PR;
+    size_t budget = NOALLOC_SCRATCH_BYTES, need = 0;
+    for (;;) { // smaller far-field waves until the workspace fits
+        PR = Prepared();
+        prepare_jobs(jobs, PR, budget);
+        need = al(PR.probs.size() * sizeof(NearProb)) + al(PR.descs.size() * sizeof(FarDesc)) +
+               al(size_t(PR.pbase) * sizeof(double)) + al(PR.part_need) + al(PR.work_need);
+        if (need <= NOALLOC_SCRATCH_BYTES || budget < (size_t(1) << 20)) break;
+        budget /= 2;
+    }
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(HANK_EUNSUPPORTED, "hank_transform_noalloc: the transform needs " + std::to_string(need) +
+                                           " bytes of workspace, more than the " +
+                                           std::to_string(NOALLOC_SCRATCH_BYTES) + " of the static scratch");
+    char* p = static_cast<char*>(base);
+    void* dprobs = p;
+    p += al(PR.probs.size() * sizeof(NearProb));
+    void* ddescs = p;
+    p += al(PR.descs.size() * sizeof(FarDesc));
+    double* dpart = reinterpret_cast<double*>(p);
+    p += al(size_t(PR.pbase) * sizeof(double));
+    char* fpart = p;
+    p += al(PR.part_need);
+    char* work = p;
+    for (auto& D : PR.descs) {
+        D.buf = work + reinterpret_cast<size_t>(D.buf);
+        if (D.nchunk > 1) D.part = reinterpret_cast<double*>(fpart + reinterpret_cast<size_t>(D.part));
+    }
+    if ((st = upload_descriptors(PR, dprobs, ddescs, s))) return st;
+    return enqueue_jobs(PR, static_cast<const NearProb*>(dprobs), static_cast<const FarDesc*>(ddescs), dpart, s);
 }
 
 hank_status hank_root_offsets(int64_t nmax, double* b, hank_stream_t stream) {

@@ -126,6 +126,11 @@ struct FarDesc {
 };
 
 hipError_t upload_tables(const DeviceTables& t);
+
+// Size of the static device workspace of the allocation-free entry point, and
+// its address on the current device (hipGetSymbolAddress, once per device).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(256) << 20; // HANK_NOALLOC_SCRATCH_BYTES of hank.h
+hipError_t noalloc_scratch(void** ptr);
 // b[n-1] = j_{0,n} - (n-1/4) pi for n <= nmax (b may be null) and, if v is
 // given, v[n-1] = 2/J_1(j_{0,n})^2 for n <= nv (nv <= nmax)
 hipError_t launch_roots(int64_t nmax, double* b, int64_t nv, double* v, hipStream_t s);

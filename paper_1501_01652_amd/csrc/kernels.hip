@@ -15,11 +15,39 @@
 //                contribution to f.
 #include "kernels.h"
 
+#include <map>
+#include <mutex>
+
 #include "fft_device.h"
 
 namespace hank {
 
 __device__ DeviceTables g_tab;
+
+// Workspace of the allocation-free entry point: a file-scope device array
+// (each GPU holds its own copy, at its own address, until the process ends).
+// Host code never passes its name to a kernel or a copy: it takes the address
+// that noalloc_scratch returns for the current device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(void** ptr) {
+    static std::mutex mu;
+    static std::map<int, void*> addr; // device -> address of its copy of scratch
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        it = addr.emplace(dev, p).first;
+    }
+    *ptr = it->second;
+    return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // Roots
