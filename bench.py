@@ -19,13 +19,27 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector peak
-# measured HBM traffic per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
-# a plain copy of known size), valid while the kernel sources are unchanged
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+# counters per launch of each kernel from rocprofv3 --pmc runs of the headline
+# (HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by a plain copy of known
+# size; FP64 VALU instruction counts), valid while the kernel sources are
+# unchanged
+COUNTER_FILE = os.path.join(ROOT, "profiles", "kernel_counters.json")
 KERNEL_SOURCES = ["paper_1501_01652_amd/csrc/kernels.hip", "paper_1501_01652_amd/csrc/fft_device.h",
                   "paper_1501_01652_amd/csrc/device_common.h", "paper_1501_01652_amd/csrc/kernels.h"]
 COPY_BYTES = 1 << 30           # the calibration copy (--only copy)
 METRIC = "DHT0 points/sec at N=2^20, ε=1e-8 vs direct; batched p50/p99 latency"
+# the counter passes (each its own rocprofv3 run; -d <dir>/p<i> -o p --output-format csv)
+PMC_PASSES = [
+    "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SMEM SQ_INSTS",
+    "SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_WAIT_INST_LDS SQ_ACTIVE_INST_VALU "
+    "SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_ANY",
+    "SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64 "
+    "SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_INT64 SQ_INSTS_VALU_CVT",
+    "SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE SQ_THREAD_CYCLES_VALU SQ_LEVEL_WAVES SQ_BUSY_CU_CYCLES "
+    "SQ_ACTIVE_INST_VMEM SQ_INSTS_VALU_FLOPS_FP64 GRBM_GUI_ACTIVE",
+    "FETCH_SIZE", "WRITE_SIZE"]
+PMC_HEADLINE = "python3 bench.py --only headline --steps 2 --warmup 1 --no-cpu --no-direct"
+PMC_COPY = "python3 bench.py --only copy"
 
 
 def kernel_source_hash():
@@ -37,18 +51,24 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None if there is none or the kernel sources changed since."""
+def kernel_counters(kernel):
+    """Counters per launch of `kernel` (the name up to its template
+    arguments) from the committed summary, or None if there is none or the
+    kernel sources changed since it was taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(COUNTER_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    k = t.get("kernels", {}).get(kernel)
-    if k is None or t.get("source_hash") != kernel_source_hash():
+    if t.get("source_hash") != kernel_source_hash():
         return None
-    return 1024.0 * (k["fetch_kib"] * t["fetch_scale"] + k["write_kib"] * t["write_scale"])
+    return t.get("kernels", {}).get(kernel)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the counter summary, or None."""
+    k = kernel_counters(kernel)
+    return None if k is None or "hbm_bytes" not in k else k["hbm_bytes"]
 
 
 def run_copy(torch):
@@ -61,33 +81,56 @@ def run_copy(torch):
     return {"copy_bytes": COPY_BYTES, "copies": 3}
 
 
-def write_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, command):
-    """Build TRAFFIC_FILE from rocprofv3 --pmc counter collections (csv):
-    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the headline run and of
-    the calibration copy (--only copy), whose true traffic is COPY_BYTES each way."""
+def write_counters(pmc_dir):
+    """Build COUNTER_FILE from the rocprofv3 --pmc runs under pmc_dir: p1..p6
+    the counter passes PMC_PASSES of the headline (PMC_HEADLINE), p7 and p8
+    FETCH_SIZE and WRITE_SIZE of the calibration copy (PMC_COPY), whose true
+    traffic is COPY_BYTES each way.  Values are per dispatch, averaged over
+    the dispatches of each kernel (instantiations of one template summed per
+    launch set are kept apart by their full names)."""
     import csv
 
-    def per_kernel(path, counter):
+    def per_kernel(path):
         acc = {}
         with open(path) as fh:
             for r in csv.DictReader(fh):
-                if r["Counter_Name"] != counter:
-                    continue
-                name = r["Kernel_Name"].split("(")[0].split("<")[0].replace("void ", "").replace("hank::", "")
-                acc.setdefault(name.strip(), []).append(float(r["Counter_Value"]))
-        return {k: sum(v) / len(v) for k, v in acc.items()}
+                name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("hank::", "").strip()
+                acc.setdefault(name, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        return acc
 
-    def copy_kib(path, counter):
-        vals = per_kernel(path, counter)
-        return max(vals.values())  # the copy is the largest dispatch of that run
+    runs = {i: per_kernel(os.path.join(pmc_dir, "p%d" % i, "p_counter_collection.csv")) for i in range(1, 9)}
 
-    fscale = (COPY_BYTES / 1024.0) / copy_kib(copy_fetch_csv, "FETCH_SIZE")
-    wscale = (COPY_BYTES / 1024.0) / copy_kib(copy_write_csv, "WRITE_SIZE")
-    f, w = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
-    kernels = {k: {"fetch_kib": f[k], "write_kib": w.get(k, 0.0)} for k in f if k.startswith("k_")}
+    def copy_kib(i, counter):
+        return max(sum(v[counter]) / len(v[counter]) for v in runs[i].values() if counter in v)
+
+    fscale = (COPY_BYTES / 1024.0) / copy_kib(7, "FETCH_SIZE")
+    wscale = (COPY_BYTES / 1024.0) / copy_kib(8, "WRITE_SIZE")
+    kernels = {}
+    for i in range(1, 7):
+        for name, cs in runs[i].items():
+            if not name.startswith("k_"):
+                continue
+            k = kernels.setdefault(name, {})
+            for cn, v in cs.items():
+                k[cn] = sum(v) / len(v)
+    for k in kernels.values():
+        if "FETCH_SIZE" in k and "WRITE_SIZE" in k:
+            k["hbm_bytes"] = 1024.0 * (k["FETCH_SIZE"] * fscale + k["WRITE_SIZE"] * wscale)
+        if "SQ_INSTS_VALU_FMA_F64" in k:
+            # FP64 operations: 64 lanes per wave instruction, an FMA two
+            k["fp64_flops"] = 64.0 * (k["SQ_INSTS_VALU_ADD_F64"] + k["SQ_INSTS_VALU_MUL_F64"] +
+                                      2.0 * k["SQ_INSTS_VALU_FMA_F64"] + k["SQ_INSTS_VALU_TRANS_F64"]) + \
+                512.0 * k.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)
+            k["fp64_wave_insts"] = (k["SQ_INSTS_VALU_ADD_F64"] + k["SQ_INSTS_VALU_MUL_F64"] +
+                                    k["SQ_INSTS_VALU_FMA_F64"] + k["SQ_INSTS_VALU_TRANS_F64"])
+    cmds = ["cd /tmp && rocprofv3 --pmc %s --output-format csv -d <dir>/p%d -o p -- %s" % (c, i + 1, PMC_HEADLINE)
+            for i, c in enumerate(PMC_PASSES)]
+    cmds += ["cd /tmp && rocprofv3 --pmc %s --output-format csv -d <dir>/p%d -o p -- %s" % (c, i + 7, PMC_COPY)
+             for i, c in enumerate(["FETCH_SIZE", "WRITE_SIZE"])]
     out = {"source_hash": kernel_source_hash(), "fetch_scale": fscale, "write_scale": wscale,
-           "command": command, "kernels": kernels}
-    with open(TRAFFIC_FILE, "w") as fh:
+           "workload": "the headline: dht0 N=2^20 eps=1e-8, every far transform in FP64",
+           "commands": cmds, "kernels": kernels}
+    with open(COUNTER_FILE, "w") as fh:
         json.dump(out, fh, indent=1, sort_keys=True)
     return out
 
@@ -108,7 +151,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--batch-count", type=int, default=1024, help="requests of the batched workload (0: skip)")
-    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving run (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="arrival window of the serving run (0: skip)")
+    ap.add_argument("--serve-low-seconds", type=float, default=20.0,
+                    help="arrival window of the second serving trace, at 0.8 x the plain form's capacity (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--only", choices=["all", "headline", "batched", "serve", "copy", "ablation", "configs"],
                     default="all")
@@ -117,22 +162,31 @@ def parse():
     ap.add_argument("--oracle-rows", type=int, default=48,
                     help="sampled output rows per large workload on which the CPU oracle is timed and "
                          "the GPU result is compared")
-    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
-                    help="write the HBM traffic summary from rocprofv3 counter csv files and exit")
+    ap.add_argument("--write-counters", metavar="PMC_DIR",
+                    help="write the kernel counter summary from the rocprofv3 --pmc runs under PMC_DIR and exit")
     return ap.parse_args()
 
 
-def run_batched(hank, inputs, torch, count):
-    """1024 uneven transforms in one hank_batch call against the same requests
-    one call at a time; throughput and per-request completion latency (all
-    submitted at t = 0)."""
+def run_batched(hank, inputs, torch, count, stages=8):
+    """The batched workload (1024 uneven requests, FFT splits from the
+    autotuner): in one hank_batch call (its makespan), replayed as a HIP
+    graph, and as `stages` consecutive hank_batch calls of requests sorted by
+    the planner's modelled cost (cheapest first), each request's completion
+    stamped by an event after its stage -- against the same requests one call
+    at a time in the same order (completion stamped per call)."""
+    import concurrent.futures
+    tuned = hank.autotune()
     specs = inputs.batch_specs(count)
+    with concurrent.futures.ThreadPoolExecutor(16) as ex:  # host planning only
+        model_s = list(ex.map(lambda sp: hank.plan_info(sp["task"], sp["N"], sp["eps"], nrhs=sp["nrhs"])["model_s"],
+                              specs))
     reqs = []
-    for sp in specs:
+    for sp, m in zip(specs, model_s):
         g = torch.Generator(device="cuda").manual_seed(sp["seed"])
         shape = (sp["nrhs"], sp["N"]) if sp["nrhs"] > 1 else (sp["N"],)
         c = torch.rand(shape, generator=g, dtype=torch.float64, device="cuda") * 2.0 - 1.0
-        reqs.append({"task": sp["task"], "c": c, "out": torch.empty_like(c), "eps": sp["eps"]})
+        reqs.append({"task": sp["task"], "c": c, "out": torch.empty_like(c), "eps": sp["eps"],
+                     "cost": m * sp["nrhs"] / (1 << (sp["nrhs"] - 1).bit_length())})
     t0 = time.perf_counter()
     hank.batch(reqs)  # builds every plan, then runs
     torch.cuda.synchronize()
@@ -154,29 +208,53 @@ def run_batched(hank, inputs, torch, count):
     torch.cuda.synchronize()
     tg = (time.perf_counter() - t0) / reps
     graph.close()
-    # one request at a time, same stream, completion stamped by events
-    for r in reqs:
-        hank.transform(r["task"], r["c"], r["eps"], out=r["out"])
+    # staged: cheapest first, one event per stage
+    order = sorted(range(count), key=lambda i: reqs[i]["cost"])
+    bounds = [round(k * count / stages) for k in range(stages + 1)]
+    stage_reqs = [[reqs[i] for i in order[bounds[k]:bounds[k + 1]]] for k in range(stages)]
+    for sr in stage_reqs:
+        hank.batch(sr)
+    torch.cuda.synchronize()
+    lat_st, ts_st = [], []
+    for _ in range(reps):
+        start = torch.cuda.Event(enable_timing=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(stages)]
+        start.record()
+        for sr, e in zip(stage_reqs, evs):
+            hank.batch(sr)
+            e.record()
+        torch.cuda.synchronize()
+        done = [start.elapsed_time(e) for e in evs]
+        lat_st = sorted(done[k] for k in range(stages) for _ in range(bounds[k + 1] - bounds[k]))
+        ts_st.append(done[-1] / 1e3)
+    tst = sorted(ts_st)[len(ts_st) // 2]
+    # one request at a time in the same order, completion stamped per call
+    for i in order:
+        hank.transform(reqs[i]["task"], reqs[i]["c"], reqs[i]["eps"], out=reqs[i]["out"])
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     evs = [torch.cuda.Event(enable_timing=True) for _ in reqs]
     start.record()
-    for r, e in zip(reqs, evs):
-        hank.transform(r["task"], r["c"], r["eps"], out=r["out"])
+    for i, e in zip(order, evs):
+        hank.transform(reqs[i]["task"], reqs[i]["c"], reqs[i]["eps"], out=reqs[i]["out"])
         e.record()
     torch.cuda.synchronize()
     lat = sorted(start.elapsed_time(e) for e in evs)
     ts = lat[-1] / 1e3
-    pct = lambda q: lat[min(len(lat) - 1, int(q * (len(lat) - 1) + 0.5))]
     return {"requests": count, "rhs_total": int(sum(sp["nrhs"] for sp in specs)),
             "workload": "task 40/40/20, N log-uniform [2^8, 2^16], 1-64 rhs, eps {1e-4,1e-8,1e-14}, "
-                        "c ~ U[-1,1], seed %d" % inputs.SEED_BATCH,
-            "batched_transforms_per_s": count / tb, "batched_ms": tb * 1e3,
+                        "c ~ U[-1,1], seed %d; FFT splits from hank_autotune" % inputs.SEED_BATCH,
+            "autotuned_l2": tuned,
+            "one_call_transforms_per_s": count / tb, "one_call_makespan_ms": tb * 1e3,
             "graph_transforms_per_s": count / tg, "graph_ms": tg * 1e3,
-            "batched_latency_p50_ms": tb * 1e3, "batched_latency_p99_ms": tb * 1e3,
+            "staged": {"stages": stages, "order": "modelled cost, cheapest first",
+                       "transforms_per_s": count / tst, "makespan_ms": tst * 1e3,
+                       "latency_p50_ms": quantile(lat_st, 0.5), "latency_p99_ms": quantile(lat_st, 0.99)},
+            "batched_transforms_per_s": count / tst,
+            "batched_latency_p50_ms": quantile(lat_st, 0.5), "batched_latency_p99_ms": quantile(lat_st, 0.99),
             "sequential_transforms_per_s": count / ts, "sequential_ms": ts * 1e3,
-            "sequential_latency_p50_ms": pct(0.5), "sequential_latency_p99_ms": pct(0.99),
-            "speedup": ts / tb, "first_call_incl_planning_s": warm_s}
+            "sequential_latency_p50_ms": quantile(lat, 0.5), "sequential_latency_p99_ms": quantile(lat, 0.99),
+            "speedup": ts / tst, "first_call_incl_planning_s": warm_s}
 
 
 def _median_ms(hank, torch, task, c, eps, out, reps, **kw):
@@ -227,37 +305,138 @@ def run_ablation(hank, inputs, torch, task, N, eps, c_host, precision=1):
                         "by_eps": sweep, "direct_ms": direct_ms}}
 
 
-def run_serve(hank, inputs, torch, seconds, rate, max_batch):
-    """Open-loop Poisson arrivals through the continuous-batching server."""
-    trace = inputs.serve_trace(rate=rate, seconds=seconds)
-    sizes = sorted({t["N"] for t in trace})
-    cin = {}
-    pool = {}
-    for N in sizes:
-        g = torch.Generator(device="cuda").manual_seed(inputs.SEED_SERVE + N)
-        cin[N] = torch.randn(N, generator=g, dtype=torch.float64, device="cuda")
-        pool[N] = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in range(max_batch + 1)]
-    srv = hank.Server(budget_bytes=32 << 30, max_batch=max_batch, max_pending=256)
-    seen = {}
-    for t in trace:  # plans on the device before the clock starts
-        key = (t["task"], t["N"], t["eps"])
-        if key not in seen:
-            seen[key] = True
-            srv.warm({"task": t["task"], "c": cin[t["N"]], "out": pool[t["N"]][0], "eps": t["eps"]})
-    count = {}
+def serve_buffers(torch, inputs, ring):
+    """One coefficient vector of the largest size (requests use its first N
+    entries) and a ring of output buffers."""
+    nmax = 1 << 22
+    g = torch.Generator(device="cuda").manual_seed(inputs.SEED_SERVE)
+    c_all = torch.randn(nmax, generator=g, dtype=torch.float64, device="cuda")
+    outs = [torch.empty(nmax, dtype=torch.float64, device="cuda") for _ in range(ring)]
+    return c_all, outs
+
+
+def warm_partition_tables(hank, trace):
+    """Host-side start-up of a serving process: the tuned partition search at
+    the grid sizes 2^(j/4) that the trace's sizes fall between (each later plan
+    of a size between grid points reuses it), in parallel threads."""
+    import concurrent.futures
+    import math
+    keys = set()
     for t in trace:
-        i = count.get(t["N"], 0)
-        count[t["N"]] = i + 1
-        srv.submit({"task": t["task"], "c": cin[t["N"]], "out": pool[t["N"]][i % (max_batch + 1)],
-                    "eps": t["eps"]}, arrival_s=t["arrival"])
+        j = int(math.floor(4 * math.log2(t["N"]) + 1e-9))
+        for jj in (j, j + 1):
+            keys.add((t["task"], int(round(2 ** (jj / 4.0))), t["eps"]))
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(16) as ex:
+        list(ex.map(lambda k: hank.plan_info(k[0], k[1], k[2]), sorted(keys)))
+    return {"grid_plans": len(keys), "seconds": time.perf_counter() - t0}
+
+
+def run_serve(hank, inputs, torch, trace, c_all, outs, max_batch=64, max_pending=512, budget=48 << 30):
+    """Open-loop arrivals through the continuous-batching server (planner
+    threads build unseen plans while batches run)."""
+    srv = hank.Server(budget_bytes=budget, max_batch=max_batch, max_pending=max_pending)
+    for k, t in enumerate(trace):
+        N = t["N"]
+        srv.submit({"task": t["task"], "c": c_all[:N], "out": outs[k % len(outs)][:N], "eps": t["eps"]},
+                   arrival_s=t["arrival"])
     srv.start()
     srv.drain()
     st = srv.stats()
     srv.close()
-    st["offered_rate"] = rate
-    st["window_s"] = seconds
     st["max_batch"] = max_batch
+    st["max_pending"] = max_pending
     return st
+
+
+def run_plain(hank, torch, trace, c_all, outs, max_pending=512):
+    """The plain form: hank_* calls one request at a time in arrival order on
+    one stream (plans built when first needed), at most two calls in flight; a
+    request that arrives while max_pending requests wait is rejected."""
+    import collections
+    stream = torch.cuda.current_stream()
+    n = len(trace)
+    events = [None] * n
+    rejected = 0
+    queue = collections.deque()
+    inflight = collections.deque()
+    i_arr = 0
+    start = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+
+    def arrivals():
+        nonlocal i_arr, rejected
+        now = time.perf_counter() - t0
+        while i_arr < n and trace[i_arr]["arrival"] <= now:
+            if len(queue) >= max_pending:
+                rejected += 1
+            else:
+                queue.append(i_arr)
+            i_arr += 1
+
+    while True:
+        arrivals()
+        if queue:
+            while len(inflight) >= 2:
+                inflight.popleft().synchronize()
+                arrivals()
+            k = queue.popleft()
+            t = trace[k]
+            N = t["N"]
+            hank.transform(t["task"], c_all[:N], t["eps"], out=outs[k % len(outs)][:N], stream=stream)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(stream)
+            events[k] = ev
+            inflight.append(ev)
+        elif i_arr >= n:
+            break
+        else:
+            time.sleep(max(0.0, min(1e-3, trace[i_arr]["arrival"] - (time.perf_counter() - t0))))
+    torch.cuda.synchronize()
+    lat, last = [], 0.0
+    for k in range(n):
+        if events[k] is not None:
+            done = start.elapsed_time(events[k]) / 1e3
+            last = max(last, done)
+            lat.append(1e3 * (done - trace[k]["arrival"]))
+    lat.sort()
+    wall = last - trace[0]["arrival"] if lat else 0.0
+    return {"submitted": n, "completed": len(lat), "rejected": rejected,
+            "p50_ms": quantile(lat, 0.5) if lat else None, "p90_ms": quantile(lat, 0.9) if lat else None,
+            "p99_ms": quantile(lat, 0.99) if lat else None, "wall_s": wall,
+            "throughput": len(lat) / wall if wall > 0 else 0.0, "max_pending": max_pending}
+
+
+def run_serving(hank, inputs, torch, seconds, rate, low_seconds):
+    """The serving workload: Poisson arrivals at `rate` for `seconds` (N
+    log-uniform integers in [2^10, 2^22], so most plans are new), through the
+    server and through the plain sequential form; then a second trace at 0.8 x
+    the plain form's measured capacity for `low_seconds`."""
+    c_all, outs = serve_buffers(torch, inputs, 1024)
+    trace = inputs.serve_trace(rate=rate, seconds=seconds)
+    low_rate = None
+    res = {"workload": "Poisson %g req/s for %g s, task 40/40/20, N log-uniform integers in [2^10, 2^22], "
+                       "1 rhs, eps {1e-4,1e-8,1e-14}, seed %d" % (rate, seconds, inputs.SEED_SERVE),
+           "requests": len(trace), "distinct_sizes": len({(t["task"], t["N"], t["eps"]) for t in trace})}
+    res["startup"] = warm_partition_tables(hank, trace)
+    res["continuous_batching"] = run_serve(hank, inputs, torch, trace, c_all, outs)
+    hank.cache_clear()
+    res["plain_sequential"] = run_plain(hank, torch, trace, c_all, outs)
+    hank.cache_clear()
+    cap = res["plain_sequential"]["throughput"]
+    if low_seconds > 0 and cap > 0:
+        low_rate = 0.8 * cap
+        low = inputs.serve_trace(rate=low_rate, seconds=low_seconds, seed=inputs.SEED_SERVE + 1)
+        res["at_0.8_capacity"] = {"rate": low_rate, "seconds": low_seconds, "requests": len(low),
+                                  "startup": warm_partition_tables(hank, low),
+                                  "continuous_batching": run_serve(hank, inputs, torch, low, c_all, outs)}
+        hank.cache_clear()
+        res["at_0.8_capacity"]["plain_sequential"] = run_plain(hank, torch, low, c_all, outs)
+        hank.cache_clear()
+    del c_all, outs
+    return res
 
 
 def step_times(hank, torch, task, c, eps, out, steps, warmup, **kw):
@@ -361,10 +540,10 @@ def main():
         print("bench.py runs on exactly one GPU; runs on several GPUs are not supported "
               "(got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    if args.write_traffic:
-        cmd = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- python3 bench.py "
-               "--only headline --steps 2 --warmup 1 --no-cpu --no-direct; the same for --only copy")
-        print(json.dumps(write_traffic(*args.write_traffic, command=cmd)))
+    if args.write_counters:
+        out = write_counters(args.write_counters)
+        print(json.dumps({k: {c: v for c, v in d.items() if c in ("hbm_bytes", "fp64_flops")}
+                          for k, d in out["kernels"].items()}))
         return
     import numpy as np
     import torch
@@ -379,12 +558,8 @@ def main():
         if args.only in ("all", "batched") and args.batch_count > 0:
             extra["batched"] = run_batched(hank, inputs, torch, args.batch_count)
         if args.only in ("all", "serve") and args.serve_seconds > 0:
-            extra["serving"] = {
-                "workload": "Poisson %g req/s for %g s, task 40/40/20, N in {2^10..2^22} log-uniform, 1 rhs, "
-                            "eps {1e-4,1e-8,1e-14}, seed %d" % (args.serve_rate, args.serve_seconds,
-                                                                inputs.SEED_SERVE),
-                "continuous_batching": run_serve(hank, inputs, torch, args.serve_seconds, args.serve_rate, 64),
-                "one_at_a_time": run_serve(hank, inputs, torch, args.serve_seconds, args.serve_rate, 1)}
+            extra["serving"] = run_serving(hank, inputs, torch, args.serve_seconds, args.serve_rate,
+                                           args.serve_low_seconds)
 
     def run_configs():
         """The other workloads: Schlomilch N=4096 at 1e-14 (latency); Fourier-
@@ -486,7 +661,15 @@ def main():
     far_bytes = sum(s["bytes"] for s in stats if s["name"].startswith("pass")) / args.steps
     far_ms = sum(s["total_ms"] for s in stats if s["name"].startswith("pass")) / args.steps
     near_s = [s for s in stats if s["name"] == "near"]
-    near_flops = near_s[0]["work"] * NEAR_FLOPS_PER_ENTRY / args.steps if near_s else 0.0
+    near_kc = kernel_counters("k_near") if task == "dht0" and N == 1 << 20 and eps == 1e-8 else None
+    # FP64 operations per near-field entry: counted by rocprofv3 on this
+    # workload when the counter summary matches the kernel sources, else the
+    # nominal count of one large-argument J_0 and the multiply-add
+    near_fpe, near_basis = NEAR_FLOPS_PER_ENTRY, "nominal"
+    if near_s and near_kc and "fp64_flops" in near_kc:
+        near_fpe = near_kc["fp64_flops"] / (near_s[0]["work"] / near_s[0]["launches"])
+        near_basis = "rocprofv3 FP64 VALU instruction counts"
+    near_flops = near_s[0]["work"] * near_fpe / args.steps if near_s else 0.0
     plan_roofline["phase_roofline_ms"] = 1e3 * (far_bytes / (HBM_PEAK_GBS * 1e9) +
                                                 near_flops / (FP64_VECTOR_TFLOPS * 1e12))
     plan_roofline["far_passes_ms"] = far_ms
@@ -495,13 +678,18 @@ def main():
     roofline = None
     if dom is not None:
         if dom["name"] == "near":
-            # FP64 ALU bound: priced at the operation count of one large-argument
-            # J_0 evaluation plus the multiply-add (near-field roofline)
-            flops = dom["work"] * NEAR_FLOPS_PER_ENTRY
+            # FP64 ALU bound: the kernel's FP64 operations per entry (counted, or
+            # the nominal figure) times the entries, against the FP64 vector peak
+            flops = dom["work"] * near_fpe
             ach = flops / (dom["total_ms"] * 1e-3) / 1e12
             roofline = {"kernel": "near", "bound": "alu", "achieved": ach, "peak": FP64_VECTOR_TFLOPS,
                         "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_TFLOPS,
-                        "traffic": measured_traffic("k_near")}
+                        "traffic": measured_traffic("k_near"),
+                        "flops_per_entry": near_fpe, "flops_basis": near_basis}
+            if near_kc and "fp64_wave_insts" in near_kc:
+                # FP64 issue: a wave64 FP64 instruction holds a SIMD's FP64 pipe 4 cycles
+                simd_cycles = 1024 * 2.4e9 * (dom["total_ms"] / dom["launches"]) * 1e-3
+                roofline["fp64_pipe_busy"] = 4.0 * near_kc["fp64_wave_insts"] / simd_cycles
         else:
             ach = dom["bytes"] / (dom["total_ms"] * 1e-3) / 1e9
             roofline = {"kernel": dom["name"], "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,

@@ -186,8 +186,13 @@ hank_status hank_batch_graph_destroy(hank_graph* graph);
  * completion minus arrival (host clock).  max_batch = 1 gives the plain
  * one-request-at-a-time form on the same path.  Requests follow the
  * conventions of hank_transform; their buffers must stay valid until done.
- * Plans are built (and cached) by the worker on first use; hank_server_warm
- * builds a request's plan in advance. */
+ * Plans: planner threads (HANK_SERVE_PLANNERS, default min(8, cores/2)) build
+ * the plan of each arrived request whose plan is not cached -- host planning
+ * and device tables on their own streams, while batches run -- and a request
+ * is admitted once its plan is ready; its plan stays pinned in the cache until
+ * its batch completes, and its device bytes (workspace and plan) count against
+ * budget_bytes while in flight.  A request whose plan cannot be built, or
+ * whose device bytes exceed budget_bytes, is rejected.  hank_server_warm builds a request's plan in advance. */
 typedef struct hank_server hank_server;
 
 typedef struct {
@@ -196,6 +201,7 @@ typedef struct {
     double p50_ms, p90_ms, p99_ms, max_ms, mean_ms; /* latency of completed requests */
     double wall_s;                     /* first arrival to last completion        */
     double throughput;                 /* completed requests per second of wall_s */
+    int64_t plans_built;               /* plans the planner threads built          */
 } hank_server_summary;
 
 hank_status hank_server_create(int64_t budget_bytes, int32_t max_batch, int64_t max_pending,
@@ -219,11 +225,27 @@ hank_status hank_server_destroy(hank_server* srv);
 hank_status hank_autotune(hank_stream_t stream, int32_t* chosen);
 /* Back to the default split for plans built from then on. */
 hank_status hank_autotune_reset(void);
+/* The installed splits as a text file, one "log2(L) log2(L2)" line per tuned
+ * length: hank_autotune_save writes them to path (host only); hank_autotune_load
+ * installs those of path for plans built from then on, so that a process can
+ * reuse an earlier process's tuning.  A file that cannot be read or written, or
+ * a line that is not a split the kernels support (L1 >= L2, L1 <= 8192,
+ * 2^6 <= L <= 2^23), returns HANK_EINVAL; on a bad line nothing is installed. */
+hank_status hank_autotune_save(const char* path);
+hank_status hank_autotune_load(const char* path);
 
 /* ---- Library state --------------------------------------------------------- */
 const char* hank_last_error(void);   /* message of the calling thread's last error */
 hank_status hank_cache_clear(void);  /* drop every cached plan (device sync first)  */
 int64_t hank_cache_bytes(void);      /* device bytes held by cached plans          */
+/* Limit of the plan cache in device bytes (default 16 GiB; 0 keeps nothing
+ * that is not in use).  Past it the least recently used plans are freed --
+ * not those pinned by a live batch graph or by a server request that is
+ * waiting or running, nor those of the call in progress -- down to three
+ * quarters of the limit.  Freeing synchronises the device.  A freed plan is
+ * built again on its next use, with bitwise the same results.
+ * HANK_EINVAL for a negative limit. */
+hank_status hank_cache_limit(int64_t bytes);
 
 /* ---- Kernel timing -----------------------------------------------------------
  * hank_profile(1) brackets every kernel launch of later transforms with HIP
@@ -272,6 +294,8 @@ typedef struct {
     int32_t fp32_transforms; /* transforms run in FP32 (all with bulk_fp32; with an
                               FP64 bulk, those whose contribution is small enough
                               that FP32 rounding stays within eps/8)            */
+    double model_s;        /* GPU seconds of one transform by the planner's cost
+                              model (for the nrhs the plan is balanced for)    */
 } hank_plan_summary;
 
 hank_status hank_plan_info(int32_t task, int64_t N, double eps, const hank_options* options,
@@ -285,6 +309,7 @@ typedef struct {
     int32_t groups;
     int32_t terms;
     double zmin; /* smallest z = r_k w_n inside the block */
+    int32_t fft_l1, fft_l2; /* split fft_len = l1 * l2: row FFTs of l1, column FFTs of l2 points */
 } hank_block_info;
 
 hank_status hank_plan_block(int32_t task, int64_t N, double eps, const hank_options* options,

@@ -32,7 +32,7 @@ EXPORTS = ["hank_schlomilch", "hank_fourier_bessel", "hank_dht0", "hank_transfor
            "hank_server_drain", "hank_server_status", "hank_server_stats", "hank_server_destroy",
            "hank_batch_graph_create", "hank_batch_graph_launch", "hank_batch_graph_destroy",
            "hank_autotune", "hank_autotune_reset", "hank_dht0_inverse", "hank_dht0_weights",
-           "hank_transform_noalloc"]
+           "hank_transform_noalloc", "hank_cache_limit", "hank_autotune_save", "hank_autotune_load"]
 
 
 class HankError(RuntimeError):
@@ -54,13 +54,14 @@ class PlanSummary(ctypes.Structure):
                 ("near_entries", ctypes.c_int64), ("far_transforms", ctypes.c_int64),
                 ("fft_points", ctypes.c_int64), ("fft_bytes", ctypes.c_double),
                 ("first_direct", ctypes.c_int32), ("bulk_fp32", ctypes.c_int32),
-                ("fp32_transforms", ctypes.c_int32)]
+                ("fp32_transforms", ctypes.c_int32), ("model_s", ctypes.c_double)]
 
 
 class BlockInfo(ctypes.Structure):
     _fields_ = [("row0", ctypes.c_int64), ("row1", ctypes.c_int64), ("col0", ctypes.c_int64),
                 ("col1", ctypes.c_int64), ("fft_len", ctypes.c_int64), ("groups", ctypes.c_int32),
-                ("terms", ctypes.c_int32), ("zmin", ctypes.c_double)]
+                ("terms", ctypes.c_int32), ("zmin", ctypes.c_double), ("fft_l1", ctypes.c_int32),
+                ("fft_l2", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -109,10 +110,16 @@ def lib():
             L.hank_autotune.argtypes = [p, ctypes.POINTER(i32)]
             L.hank_autotune_reset.restype = i32
             L.hank_autotune_reset.argtypes = []
+            for name in ("hank_autotune_save", "hank_autotune_load"):
+                f = getattr(L, name)
+                f.restype = i32
+                f.argtypes = [ctypes.c_char_p]
             L.hank_last_error.restype = ctypes.c_char_p
             L.hank_last_error.argtypes = []
             L.hank_cache_clear.restype = i32
             L.hank_cache_bytes.restype = i64
+            L.hank_cache_limit.restype = i32
+            L.hank_cache_limit.argtypes = [i64]
             for name in ("hank_param_s", "hank_param_t"):
                 f = getattr(L, name)
                 f.restype = d
@@ -301,6 +308,16 @@ def autotune_reset():
     _check(lib().hank_autotune_reset())
 
 
+def autotune_save(path: str):
+    """Write the installed FFT splits to a text file (host only)."""
+    _check(lib().hank_autotune_save(os.fsencode(path)))
+
+
+def autotune_load(path: str):
+    """Install the FFT splits of a file written by autotune_save (host only)."""
+    _check(lib().hank_autotune_load(os.fsencode(path)))
+
+
 class BatchGraph:
     """A batch captured once as a HIP graph (hank_batch_graph_*): launch()
     replays the same requests, reading and writing the same tensors, without
@@ -403,6 +420,11 @@ def cache_bytes() -> int:
     return int(lib().hank_cache_bytes())
 
 
+def cache_limit(nbytes: int):
+    """Device bytes the plan cache may hold before least recently used plans are freed."""
+    _check(lib().hank_cache_limit(int(nbytes)))
+
+
 def profile(enable: bool = True):
     """Start (and reset) or stop per-kernel event timing."""
     _check(lib().hank_profile(1 if enable else 0))
@@ -421,7 +443,8 @@ class ServerSummary(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("mean_batch", ctypes.c_double), ("p50_ms", ctypes.c_double),
                 ("p90_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
-                ("mean_ms", ctypes.c_double), ("wall_s", ctypes.c_double), ("throughput", ctypes.c_double)]
+                ("mean_ms", ctypes.c_double), ("wall_s", ctypes.c_double), ("throughput", ctypes.c_double),
+                ("plans_built", ctypes.c_int64)]
 
 
 def _server_fns():

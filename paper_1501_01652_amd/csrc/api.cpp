@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
@@ -94,6 +95,10 @@ struct DevPlan {
     void* work = nullptr; // chirp-spectrum scratch during the build
     size_t bytes = 0;
     GridArgs G{};
+    // cache bookkeeping (under g_mu): pins by graphs and server requests,
+    // last use for the LRU order, and the call that last fetched the plan
+    int32_t pins = 0;
+    uint64_t last_use = 0, call = 0;
 
     ~DevPlan() {
         int cur = 0;
@@ -123,6 +128,35 @@ struct DevPlan {
 using Key = std::tuple<int, int64_t, uint64_t, int, int, int, int>;
 std::map<Key, std::unique_ptr<DevPlan>> g_cache;
 std::set<int> g_tables_ready;
+// Plan cache limit (hank_cache_limit): past it the least recently used plans
+// that nothing pins and the current call did not fetch are freed.
+int64_t g_cache_limit = int64_t(16) << 30;
+uint64_t g_use_clock = 0; // advanced by every fetch
+uint64_t g_call = 0;      // advanced by every call that fetches plans
+
+int64_t cache_total() {
+    int64_t t = 0;
+    for (auto& kv : g_cache) t += int64_t(kv.second->bytes);
+    return t;
+}
+
+// Free least recently used plans until the cache holds at most `target`
+// bytes; plans pinned or fetched by the current call stay.  Freeing
+// synchronises the device (hipFree), so a plan's enqueued work completes first.
+void evict_to(int64_t target) {
+    int64_t total = cache_total();
+    while (total > target) {
+        auto victim = g_cache.end();
+        for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
+            const DevPlan& d = *it->second;
+            if (d.pins > 0 || d.call == g_call) continue;
+            if (victim == g_cache.end() || d.last_use < victim->second->last_use) victim = it;
+        }
+        if (victim == g_cache.end()) return; // everything left is in use
+        total -= int64_t(victim->second->bytes);
+        g_cache.erase(victim);
+    }
+}
 
 hank_status ensure_tables(int dev) {
     if (g_tables_ready.count(dev)) return HANK_OK;
@@ -136,11 +170,30 @@ hank_status ensure_tables(int dev) {
     return HANK_OK;
 }
 
+// Device allocation of the library.  For tests of the failure paths,
+// HANK_TEST_FAIL_ALLOC=n makes the n-th allocation from then on (counted
+// across the process) fail as out of memory.
+hipError_t hank_malloc(void** p, size_t bytes) {
+    static std::atomic<long> count{0};
+    static std::string armed;
+    const char* e = std::getenv("HANK_TEST_FAIL_ALLOC");
+    if (e && *e) {
+        static std::mutex mu;
+        std::lock_guard<std::mutex> lk(mu);
+        if (armed != e) { // a new setting restarts the count
+            armed = e;
+            count = 0;
+        }
+        if (++count == std::atol(e)) return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
 template <typename T>
 hank_status dev_alloc(T*& p, size_t count, size_t& total) {
     if (count == 0) count = 1;
     void* q = nullptr;
-    hipError_t e = hipMalloc(&q, count * sizeof(T));
+    hipError_t e = hank_malloc(&q, count * sizeof(T));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(e == hipErrorOutOfMemory ? HANK_ENOMEM : HANK_EDEVICE,
@@ -414,6 +467,8 @@ hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hip
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
         out = it->second.get();
+        out->last_use = ++g_use_clock;
+        out->call = g_call;
         return HANK_OK;
     }
     std::unique_ptr<DevPlan> dp(new DevPlan);
@@ -429,7 +484,12 @@ hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hip
     st = build_dev_plan(*dp, s);
     if (st) return st; // dp's destructor frees what was allocated
     out = dp.get();
+    out->last_use = ++g_use_clock;
+    out->call = g_call;
     g_cache[key] = std::move(dp);
+    // past the limit: down to three quarters of it, so that evictions (each a
+    // device synchronisation) come in groups
+    if (cache_total() > g_cache_limit) evict_to(g_cache_limit / 4 * 3);
     return HANK_OK;
 }
 
@@ -534,7 +594,7 @@ hank_status ensure(Scratch& b, size_t bytes, hipStream_t s) {
         b.bytes = 0;
     }
     size_t want = std::max(bytes, size_t(4096));
-    hipError_t e = hipMalloc(&b.p, want);
+    hipError_t e = hank_malloc(&b.p, want);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(e == hipErrorOutOfMemory ? HANK_ENOMEM : HANK_EDEVICE,
@@ -749,9 +809,13 @@ void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR, size_t budget =
                     const double GL = double(ng) * double(J.nrhs) * double(d.args.L);
                     off += size_t(GL * esz);
                     const double cols = double(d.args.ncols), rws = double(d.args.nrows), nr = double(J.nrhs);
-                    Ln.bytesA += GL * esz + cols * (8.0 * nr + (d.args.col_pert ? 8.0 : 0.0));
-                    Ln.bytesB += 2.0 * GL * esz + double(d.args.L) * esz;
-                    Ln.bytesC += GL * esz + rws * (d.args.row_pert ? 8.0 : 0.0);
+                    // the work buffer columns j1 < ncols carry data (pass A -> pass B) and
+                    // j1 < nrows results (pass B -> pass C); the others are not moved
+                    const double L1 = double(d.args.L1);
+                    const double fa = std::min(cols, L1) / L1, fc = std::min(rws, L1) / L1;
+                    Ln.bytesA += GL * esz * fa + cols * (8.0 * nr + (d.args.col_pert ? 8.0 : 0.0));
+                    Ln.bytesB += GL * esz * (fa + fc) + double(d.args.L) * esz;
+                    Ln.bytesC += GL * esz * fc + rws * (d.args.row_pert ? 8.0 : 0.0);
                     if (D.nchunk > 1) {
                         D.part = reinterpret_cast<double*>(part_need);
                         part_need += size_t(D.nchunk) * size_t(J.nrhs) * size_t(d.args.nrows) * sizeof(double);
@@ -910,6 +974,7 @@ hank_status transform(int32_t task, const double* c, int64_t N, int64_t nrhs, in
     hank_status st = check_args(task, c, N, nrhs, ldc, eps, out, ldo);
     if (st) return st;
     std::lock_guard<std::recursive_mutex> lk(g_mu);
+    ++g_call;
     hipStream_t s = (hipStream_t)stream;
     DevPlan* dp = nullptr;
     if ((st = get_plan(task, N, eps, o, s, dp, nrhs))) return st;
@@ -933,15 +998,26 @@ int64_t request_bytes(const DevPlan& dp, int64_t nrhs) {
 // ---------------------------------------------------------------------------
 // Continuous-batching server
 // ---------------------------------------------------------------------------
+// Requests arrive at their arrival time into a queue (or are rejected when
+// max_pending wait already).  Planner threads build the plans of arrived
+// requests (host planning and device tables on their own streams, outside the
+// library lock), so planning overlaps the batches running on the GPU; a
+// request whose plan is ready is pinned in the cache until its batch retires.
+// The worker admits ready requests in arrival order into batches of at most
+// max_batch requests and about one time slice of modelled GPU work, within
+// the device-byte budget (workspace and plan of each request in flight), and
+// keeps up to two batches in flight on its stream.
 struct hank_server {
     using clock = std::chrono::steady_clock;
     struct Rec {
         hank_request req;
         double arrival = 0; // seconds after start
         double done = -1;
-        int32_t state = 0;
-        int64_t bytes = 0;
-        double est = 0; // modelled GPU seconds (the planner's cost model)
+        int32_t state = 0;  // 0 waiting, 1 admitted, 2 done, 3 rejected
+        int32_t pstate = 0; // plan: 0 not asked for, 1 queued or building, 2 ready (pinned), 3 failed
+        DevPlan* dp = nullptr;
+        int64_t bytes = 0; // device bytes while in flight: workspace and plan
+        double est = 0;    // modelled GPU seconds (the planner's cost model)
     };
     struct Batch {
         std::vector<int64_t> tickets;
@@ -955,25 +1031,141 @@ struct hank_server {
         const char* e = std::getenv("HANK_SERVE_SLICE_MS");
         return (e ? std::atof(e) : 4.0) * 1e-3;
     }();
+    // planner threads (HANK_SERVE_PLANNERS, default min(8, cores / 2))
+    int nplanners = [] {
+        const char* e = std::getenv("HANK_SERVE_PLANNERS");
+        const int hw = int(std::max(2u, std::thread::hardware_concurrency()));
+        return std::max(1, e ? std::atoi(e) : std::min(8, hw / 2));
+    }();
     hipStream_t stream = nullptr;
     int device = 0;
     std::mutex mu;
-    std::condition_variable cv;
+    std::condition_variable cv, pcv;
     std::vector<Rec> recs;
     std::vector<int64_t> order; // tickets sorted by arrival (built at start)
     size_t next_arrival = 0;    // index into order of the next not-yet-arrived request
     std::deque<int64_t> waiting;
+    std::deque<int64_t> plan_queue;              // arrived tickets whose plan is wanted
+    std::map<Key, std::vector<int64_t>> building; // plans being built -> tickets waiting for them
     std::deque<Batch> inflight;
     int64_t inflight_bytes = 0;
     int admitting = 0; // batches taken from the queue but not yet in flight
-    int64_t batches = 0, batched = 0;
-    bool started = false, stop = false;
+    int64_t batches = 0, batched = 0, plans_built = 0;
+    bool started = false, stop = false, stop_planners = false;
     clock::time_point t0;
     std::thread worker;
+    std::vector<std::thread> planners;
     hank_status error = HANK_OK;
     std::string error_msg;
 
     double now() const { return std::chrono::duration<double>(clock::now() - t0).count(); }
+
+    static hank_options options_of(const hank_request& r) {
+        hank_options o{};
+        o.precision = r.precision;
+        o.nu = r.nu;
+        o.shift = r.shift;
+        return o;
+    }
+
+    // request tk has its plan dp (pinned for it); caller holds mu and g_mu
+    void plan_ready(int64_t tk, DevPlan* dp) {
+        Rec& r = recs[size_t(tk)];
+        r.dp = dp;
+        r.pstate = 2;
+        r.bytes = request_bytes(*dp, r.req.nrhs) + int64_t(dp->bytes);
+        r.est = dp->plan.cost * double(r.req.nrhs) / double(std::max<int64_t>(1, dp->plan.nrhs));
+    }
+
+    // release the pin of a request's plan; caller holds mu
+    void unpin(Rec& r) {
+        if (r.pstate != 2 || !r.dp) return;
+        std::lock_guard<std::recursive_mutex> g(g_mu);
+        --r.dp->pins;
+        r.dp = nullptr;
+        r.pstate = 0;
+    }
+
+    void plan_loop() {
+        (void)hipSetDevice(device);
+        hipStream_t ps = nullptr;
+        if (hipStreamCreateWithFlags(&ps, hipStreamNonBlocking) != hipSuccess) ps = nullptr;
+        std::unique_lock<std::mutex> lk(mu);
+        while (true) {
+            if (plan_queue.empty()) {
+                if (stop_planners) break;
+                pcv.wait(lk);
+                continue;
+            }
+            const int64_t tk = plan_queue.front();
+            plan_queue.pop_front();
+            const hank_request req = recs[size_t(tk)].req;
+            const hank_options o = options_of(req);
+            const Key key = plan_key(req.task, req.N, req.eps, &o, device, req.nrhs);
+            {
+                std::lock_guard<std::recursive_mutex> g(g_mu);
+                auto it = g_cache.find(key);
+                if (it != g_cache.end()) {
+                    DevPlan* dp = it->second.get();
+                    ++dp->pins;
+                    dp->last_use = ++g_use_clock;
+                    plan_ready(tk, dp);
+                    cv.notify_all();
+                    continue;
+                }
+            }
+            auto b = building.find(key);
+            if (b != building.end()) {
+                b->second.push_back(tk);
+                continue;
+            }
+            building[key] = std::vector<int64_t>{tk};
+            lk.unlock();
+            // host planning and device tables, outside both locks
+            std::unique_ptr<DevPlan> np(new DevPlan);
+            np->device = device;
+            hank_status st = HANK_OK;
+            std::string msg;
+            try {
+                np->plan = make_plan(req.task, req.N, req.eps, 0, req.precision, false, cost_model_for(&o),
+                                     rhs_bucket(req.nu > 0 ? 1 : req.nrhs), 0, req.nu, req.shift);
+            } catch (const std::exception& ex) {
+                st = HANK_EINVAL;
+                msg = std::string("planning failed: ") + ex.what();
+            }
+            if (!st && !ps) st = HANK_EDEVICE, msg = "planner stream";
+            if (!st && (st = build_dev_plan(*np, ps))) msg = hank_last_error();
+            lk.lock();
+            std::vector<int64_t> tickets;
+            tickets.swap(building[key]);
+            building.erase(key);
+            {
+                std::lock_guard<std::recursive_mutex> g(g_mu);
+                DevPlan* dp = nullptr;
+                auto it = g_cache.find(key);
+                if (it != g_cache.end()) {
+                    dp = it->second.get(); // built meanwhile by another caller
+                } else if (!st) {
+                    dp = np.get();
+                    g_cache[key] = std::move(np);
+                    ++plans_built;
+                }
+                if (dp) {
+                    dp->last_use = ++g_use_clock;
+                    dp->pins += int32_t(tickets.size());
+                    for (int64_t t : tickets) plan_ready(t, dp);
+                    if (cache_total() > g_cache_limit) evict_to(g_cache_limit / 4 * 3);
+                } else {
+                    for (int64_t t : tickets) recs[size_t(t)].pstate = 3;
+                    error = st;
+                    error_msg = msg;
+                }
+            }
+            cv.notify_all();
+        }
+        lk.unlock();
+        if (ps) (void)hipStreamDestroy(ps);
+    }
 
     void run() {
         int cur = 0;
@@ -987,46 +1179,74 @@ struct hank_server {
                 continue;
             }
             const double t = now();
-            // arrivals: into the queue, or rejected when the queue is full
+            // arrivals: into the queue (their plans wanted), or rejected when it is full
+            bool asked = false;
             while (next_arrival < order.size() && recs[size_t(order[next_arrival])].arrival <= t) {
-                Rec& r = recs[size_t(order[next_arrival])];
-                if (int64_t(waiting.size()) >= max_pending || r.bytes > budget)
+                const int64_t tk = order[next_arrival];
+                Rec& r = recs[size_t(tk)];
+                if (int64_t(waiting.size()) >= max_pending) {
                     r.state = 3;
-                else
-                    waiting.push_back(order[next_arrival]);
+                } else {
+                    waiting.push_back(tk);
+                    r.pstate = 1;
+                    plan_queue.push_back(tk);
+                    asked = true;
+                }
                 ++next_arrival;
             }
+            if (asked) pcv.notify_all();
             // retire finished batches
             while (!inflight.empty() && hipEventQuery(inflight.front().ev) == hipSuccess) {
                 const double td = now();
                 for (int64_t tk : inflight.front().tickets) {
-                    recs[size_t(tk)].state = 2;
-                    recs[size_t(tk)].done = td;
+                    Rec& r = recs[size_t(tk)];
+                    r.state = 2;
+                    r.done = td;
+                    unpin(r);
                 }
                 inflight_bytes -= inflight.front().bytes;
                 (void)hipEventDestroy(inflight.front().ev);
                 inflight.pop_front();
                 cv.notify_all();
             }
-            // admit a batch
+            // admit a batch: ready requests in arrival order
             if (inflight.size() < 2 && !waiting.empty()) {
                 Batch b;
                 std::vector<hank_request> reqs;
                 double est = 0;
-                while (!waiting.empty() && int32_t(b.tickets.size()) < max_batch) {
-                    Rec& r = recs[size_t(waiting.front())];
-                    if (!b.tickets.empty() && inflight_bytes + b.bytes + r.bytes > budget) break;
-                    // a batch holds about one time slice of modelled work, so that
-                    // large transforms run alone and small ones share launches
-                    if (!b.tickets.empty() && est + r.est > slice_s) break;
-                    if (b.tickets.empty() && inflight_bytes > 0 && inflight_bytes + r.bytes > budget) break;
-                    b.tickets.push_back(waiting.front());
+                std::deque<int64_t> keep;
+                bool full = false;
+                for (int64_t tk : waiting) {
+                    Rec& r = recs[size_t(tk)];
+                    if (full || r.pstate == 1) {
+                        keep.push_back(tk);
+                        continue;
+                    }
+                    if (r.pstate == 3) { // its plan could not be built
+                        r.state = 3;
+                        continue;
+                    }
+                    if (r.bytes > budget) { // can never run within the budget
+                        r.state = 3;
+                        unpin(r);
+                        continue;
+                    }
+                    const bool fits = b.tickets.empty() ? (inflight_bytes == 0 || inflight_bytes + r.bytes <= budget)
+                                                        : (inflight_bytes + b.bytes + r.bytes <= budget &&
+                                                           est + r.est <= slice_s); // about one time slice
+                    if (!fits) {
+                        keep.push_back(tk);
+                        full = true;
+                        continue;
+                    }
+                    b.tickets.push_back(tk);
                     b.bytes += r.bytes;
                     est += r.est;
                     r.state = 1;
                     reqs.push_back(r.req);
-                    waiting.pop_front();
+                    if (int32_t(b.tickets.size()) >= max_batch) full = true;
                 }
+                waiting.swap(keep);
                 if (!b.tickets.empty()) {
                     ++admitting;
                     lk.unlock();
@@ -1044,7 +1264,10 @@ struct hank_server {
                         --admitting;
                         error = st ? st : HANK_EDEVICE;
                         error_msg = hank_last_error();
-                        for (int64_t tk : b.tickets) recs[size_t(tk)].state = 3;
+                        for (int64_t tk : b.tickets) {
+                            recs[size_t(tk)].state = 3;
+                            unpin(recs[size_t(tk)]);
+                        }
                         cv.notify_all();
                     }
                     continue;
@@ -1057,7 +1280,7 @@ struct hank_server {
                 cv.wait_for(lk, std::chrono::milliseconds(1));
                 continue;
             }
-            // short wait: the next arrival or a batch completing
+            // short wait: the next arrival, a plan or a batch completing
             lk.unlock();
             std::this_thread::sleep_for(std::chrono::microseconds(20));
             lk.lock();
@@ -1080,7 +1303,16 @@ hank_status hank_server_create(int64_t budget_bytes, int32_t max_batch, int64_t 
         delete s;
         return fail(HANK_EDEVICE, "hipGetDevice failed");
     }
+    {
+        std::lock_guard<std::recursive_mutex> lk(g_mu);
+        hank_status st = ensure_tables(s->device);
+        if (st) {
+            delete s;
+            return st;
+        }
+    }
     s->worker = std::thread([s] { s->run(); });
+    for (int i = 0; i < s->nplanners; ++i) s->planners.emplace_back([s] { s->plan_loop(); });
     *out = s;
     return HANK_OK;
 }
@@ -1090,10 +1322,8 @@ hank_status hank_server_warm(hank_server* srv, const hank_request* r) {
     hank_status st = check_args(r->task, r->c, r->N, r->nrhs, r->ldc, r->eps, r->out, r->ldo);
     if (st) return st;
     std::lock_guard<std::recursive_mutex> lk(g_mu);
-    hank_options o{};
-    o.precision = r->precision;
-    o.nu = r->nu;
-    o.shift = r->shift;
+    ++g_call;
+    hank_options o = hank_server::options_of(*r);
     DevPlan* dp = nullptr;
     return get_plan(r->task, r->N, r->eps, &o, srv->stream, dp, r->nrhs);
 }
@@ -1102,24 +1332,15 @@ hank_status hank_server_submit(hank_server* srv, const hank_request* r, double a
     if (!srv || !r || !ticket) return fail(HANK_EINVAL, "null pointer");
     hank_status st = check_args(r->task, r->c, r->N, r->nrhs, r->ldc, r->eps, r->out, r->ldo);
     if (st) return st;
-    int64_t bytes = 0;
-    double est = 0;
-    {
-        std::lock_guard<std::recursive_mutex> lk(g_mu);
-        hank_options o{};
-        o.precision = r->precision;
-        o.nu = r->nu;
-        o.shift = r->shift;
-        DevPlan* dp = nullptr;
-        if ((st = get_plan(r->task, r->N, r->eps, &o, srv->stream, dp, r->nrhs))) return st;
-        bytes = request_bytes(*dp, r->nrhs);
-        est = dp->plan.cost * double(r->nrhs) / double(std::max<int64_t>(1, dp->plan.nrhs));
-    }
+    hank_options o = hank_server::options_of(*r);
+    if (o.nu < 0 || o.nu > HANK_NU_MAX || o.shift < 0 || o.shift > HANK_SHIFT_MAX ||
+        (o.nu > 0 && r->task == HANK_TASK_DHT0) || (o.shift > 0 && r->task != HANK_TASK_SCHLOMILCH &&
+                                                     r->task != HANK_TASK_SCHLOMILCH_PAPER_GRID) ||
+        r->precision < 0 || r->precision > 2)
+        return fail(HANK_EINVAL, "request options out of range");
     std::lock_guard<std::mutex> lk(srv->mu);
     hank_server::Rec rec;
     rec.req = *r;
-    rec.bytes = bytes;
-    rec.est = est;
     rec.arrival = (arrival_s < 0 && srv->started) ? srv->now() : std::max(0.0, arrival_s);
     *ticket = int64_t(srv->recs.size());
     srv->recs.push_back(rec);
@@ -1186,6 +1407,7 @@ hank_status hank_server_stats(hank_server* srv, hank_server_summary* out) {
     st.completed = int64_t(lat.size());
     st.batches = srv->batches;
     st.mean_batch = srv->batches ? double(srv->batched) / double(srv->batches) : 0.0;
+    st.plans_built = srv->plans_built;
     if (!lat.empty()) {
         std::sort(lat.begin(), lat.end());
         auto pct = [&](double q) { return lat[std::min(lat.size() - 1, size_t(q * double(lat.size() - 1) + 0.5))]; };
@@ -1215,6 +1437,17 @@ hank_status hank_server_destroy(hank_server* srv) {
         srv->cv.notify_all();
     }
     srv->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop_planners = true;
+        srv->plan_queue.clear();
+        srv->pcv.notify_all();
+    }
+    for (auto& t : srv->planners) t.join();
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        for (auto& r : srv->recs) srv->unpin(r); // requests that never ran
+    }
     delete srv;
     return HANK_OK;
 }
@@ -1239,6 +1472,7 @@ hank_status hank_dht0_inverse(const double* f, int64_t N, double eps, double* c,
     hank_status st = check_args(HANK_TASK_DHT0, f, N, 1, N, eps, c, N);
     if (st) return st;
     std::lock_guard<std::recursive_mutex> lk(g_mu);
+    ++g_call;
     hipStream_t s = (hipStream_t)stream;
     DevPlan* dp = nullptr;
     if ((st = get_plan(HANK_TASK_DHT0, N, eps, nullptr, s, dp, 1))) return st;
@@ -1346,6 +1580,7 @@ static hank_status batch_jobs(const hank_request* reqs, int64_t count, hipStream
 
 hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t stream) {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
+    ++g_call;
     hipStream_t s = (hipStream_t)stream;
     std::vector<Job> jobs;
     hank_status st = batch_jobs(reqs, count, s, jobs);
@@ -1356,6 +1591,7 @@ hank_status hank_batch(const hank_request* reqs, int64_t count, hank_stream_t st
 // ---- a batch captured as a HIP graph ----
 struct hank_graph {
     int device = 0;
+    std::vector<DevPlan*> plans; // pinned while the graph exists
     void *work = nullptr, *fpart = nullptr, *partial = nullptr, *probs = nullptr, *descs = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1376,6 +1612,7 @@ hank_status hank_batch_graph_create(const hank_request* reqs, int64_t count, han
     if (!out) return fail(HANK_EINVAL, "null pointer");
     *out = nullptr;
     std::lock_guard<std::recursive_mutex> lk(g_mu);
+    ++g_call;
     hipStream_t s = (hipStream_t)stream;
     std::vector<Job> jobs;
     hank_status st = batch_jobs(reqs, count, s, jobs);
@@ -1428,6 +1665,9 @@ hank_status hank_batch_graph_create(const hank_request* reqs, int64_t count, han
     (void)hipStreamDestroy(cs);
     if (st) return st;
     HIP_TRY(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    for (const Job& J : jobs)
+        if (std::find(g->plans.begin(), g->plans.end(), J.dp) == g->plans.end()) g->plans.push_back(J.dp);
+    for (DevPlan* dp : g->plans) ++dp->pins;
     ++g_graphs;
     *out = g.release();
     return HANK_OK;
@@ -1442,6 +1682,7 @@ hank_status hank_batch_graph_launch(hank_graph* g, hank_stream_t stream) {
 hank_status hank_batch_graph_destroy(hank_graph* g) {
     if (!g) return HANK_OK;
     std::lock_guard<std::recursive_mutex> lk(g_mu);
+    for (DevPlan* dp : g->plans) --dp->pins;
     delete g;
     --g_graphs;
     return HANK_OK;
@@ -1597,6 +1838,44 @@ hank_status hank_autotune(hank_stream_t stream, int32_t* chosen) {
     return st;
 }
 
+hank_status hank_autotune_save(const char* path) {
+    if (!path) return fail(HANK_EINVAL, "null path");
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    FILE* fp = std::fopen(path, "w");
+    if (!fp) return fail(HANK_EINVAL, std::string("cannot write ") + path);
+    std::fprintf(fp, "# FFT splits: log2(L) log2(L2), L = L1 x L2 (hank_autotune)\n");
+    for (int lg = 0; lg < 32; ++lg)
+        if (tuned_fft_split(lg) > 0) std::fprintf(fp, "%d %d\n", lg, tuned_fft_split(lg));
+    const bool ok = std::fclose(fp) == 0;
+    return ok ? HANK_OK : fail(HANK_EINVAL, std::string("cannot write ") + path);
+}
+
+hank_status hank_autotune_load(const char* path) {
+    if (!path) return fail(HANK_EINVAL, "null path");
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) return fail(HANK_EINVAL, std::string("cannot read ") + path);
+    std::vector<std::pair<int, int>> splits;
+    char line[256];
+    int lineno = 0;
+    while (std::fgets(line, sizeof line, fp)) {
+        ++lineno;
+        char* q = line;
+        while (*q == ' ' || *q == '\t') ++q;
+        if (*q == '#' || *q == '\n' || *q == '\0') continue;
+        int lg = 0, l2 = 0;
+        char extra = 0;
+        if (std::sscanf(q, "%d %d %c", &lg, &l2, &extra) != 2 || !valid_fft_split(lg, l2)) {
+            std::fclose(fp);
+            return fail(HANK_EINVAL, std::string(path) + ":" + std::to_string(lineno) + ": not a supported split");
+        }
+        splits.emplace_back(lg, l2);
+    }
+    std::fclose(fp);
+    for (auto& p : splits) set_fft_split(p.first, p.second);
+    return HANK_OK;
+}
+
 hank_status hank_autotune_reset(void) {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
     for (int lg = 0; lg < 32; ++lg) set_fft_split(lg, 0);
@@ -1607,15 +1886,24 @@ hank_status hank_cache_clear(void) {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
     if (g_graphs > 0) return fail(HANK_EINVAL, "batch graphs still refer to cached plans");
     (void)hipDeviceSynchronize();
-    g_cache.clear();
+    ++g_call; // no call of the past holds on to its plans
+    for (auto it = g_cache.begin(); it != g_cache.end();) // plans of running servers stay
+        it = it->second->pins > 0 ? std::next(it) : g_cache.erase(it);
     return HANK_OK;
 }
 
 int64_t hank_cache_bytes(void) {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
-    int64_t t = 0;
-    for (auto& kv : g_cache) t += int64_t(kv.second->bytes);
-    return t;
+    return cache_total();
+}
+
+hank_status hank_cache_limit(int64_t bytes) {
+    if (bytes < 0) return fail(HANK_EINVAL, "negative cache limit");
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    g_cache_limit = bytes;
+    ++g_call;
+    evict_to(bytes);
+    return HANK_OK;
 }
 
 double hank_param_s(int32_t nu, int32_t M, double eps) { return param_s(nu, M, eps); }
@@ -1654,12 +1942,17 @@ hank_status hank_plan_info(int32_t task, int64_t N, double eps, const hank_optio
     s.near_entries = p.near_entries;
     s.first_direct = p.first_direct;
     s.bulk_fp32 = p.fp32;
+    s.model_s = p.cost;
     for (auto& b : p.blocks) {
         const int64_t g32 = int64_t(b.groups.size()) - b.g64;
         s.far_transforms += int64_t(b.groups.size());
         s.fp32_transforms += int32_t(g32);
         s.fft_points += int64_t(b.groups.size()) * b.L;
-        s.fft_bytes += (16.0 * double(b.g64) + 8.0 * double(g32)) * double(b.L) * 4.0;
+        // one write and one read of each FFT point per pass boundary, only for
+        // the work-buffer columns that carry data (j1 < ncols) or results (j1 < nrows)
+        const double L1 = double(b.L1), fa = std::min(double(b.nb - b.na + 1), L1) / L1,
+                     fc = std::min(double(b.kb - b.ka + 1), L1) / L1;
+        s.fft_bytes += (16.0 * double(b.g64) + 8.0 * double(g32)) * double(b.L) * 2.0 * (fa + fc);
     }
     *out = s;
     return HANK_OK;
@@ -1681,6 +1974,8 @@ hank_status hank_plan_block(int32_t task, int64_t N, double eps, const hank_opti
     out->groups = int32_t(b.groups.size());
     out->terms = int32_t(b.terms.size());
     out->zmin = b.s0;
+    out->fft_l1 = b.L1;
+    out->fft_l2 = b.L2;
     return HANK_OK;
 }
 
@@ -1700,6 +1995,7 @@ hank_status hank_transform_noalloc(int32_t task, const double* c, int64_t N, int
     void* base = nullptr;
     HIP_TRY(noalloc_scratch(&base));
     auto it = g_cache.find(plan_key(task, N, eps, options, dev, nrhs));
+    if (it != g_cache.end()) it->second->last_use = ++g_use_clock;
     if (it == g_cache.end()) {
         Plan p;
         if ((st = host_plan(task, N, eps, options, p))) return st; // invalid options

@@ -30,6 +30,30 @@ namespace hank {
 
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
 
+// LDS slot of element i in the wave-local transforms: a permutation of the
+// low six bits (each bit XORed with higher ones, so it is invertible and keeps
+// i within its power-of-two block) under which the 16-byte elements that the
+// radix-4 and radix-8 stages, and runs of 16 consecutive lanes, access
+// together fall into distinct groups of four banks.
+// (measured: the swizzle removes most bank conflicts of the wave-local
+// stages but its index arithmetic costs registers and spills; the padded
+// layout is faster, so it is the default)
+#ifndef HANK_LDS_SWZ
+#define HANK_LDS_SWZ 0
+#endif
+__device__ __forceinline__ int lds_swz(int i) {
+#if HANK_LDS_SWZ
+    return i ^ ((i >> 2) & 15) ^ ((i >> 3) & 15);
+#else
+    return lds_pad(i);
+#endif
+}
+// LDS elements a wave-local transform of LEN points occupies
+template <int LEN>
+constexpr int wave_lds_len() {
+    return HANK_LDS_SWZ ? LEN : LEN + LEN / 8;
+}
+
 template <typename F, int SIGN>
 __device__ __forceinline__ cx<F> mul_si(cx<F> a) { // a * (SIGN i)
     return SIGN < 0 ? mk(a.y, -a.x) : mk(-a.y, a.x);
@@ -84,10 +108,23 @@ __device__ __forceinline__ const double (*opaque_tw())[2] {
     return p;
 }
 
-template <typename F, int LEN, int R, int RS, int SIGN>
+// Synchronisation of LDS data that only one wave reads and writes: the LDS
+// operations of a wave complete in issue order, so the fences only keep the
+// compiler from moving them across this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// WAVE: the LEN/R threads of the transform are one wave (LEN = 64 R), whose
+// exchanges need no workgroup barrier; its LDS slots are lds_swz(i) (LEN
+// elements), otherwise lds_pad(i) (LEN + LEN/8).
+template <typename F, int LEN, int R, int RS, int SIGN, bool WAVE = false>
 __device__ __forceinline__ void fft_stage(cx<F> (&v)[R], cx<F>* sh, int tt, int Ns, const double (*tw)[2]) {
     constexpr int NT = LEN / R;
     constexpr int NB = R / RS;
+    auto slot = [](int i) { return WAVE ? lds_swz(i) : lds_pad(i); };
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int j = tt + q * NT;
@@ -116,12 +153,12 @@ __device__ __forceinline__ void fft_stage(cx<F> (&v)[R], cx<F>* sh, int tt, int 
         dft_small<F, RS, SIGN>(a);
         const int base = (j - kk) * RS + kk;
 #pragma unroll
-        for (int s = 0; s < RS; ++s) sh[lds_pad(base + s * Ns)] = a[s];
+        for (int s = 0; s < RS; ++s) sh[slot(base + s * Ns)] = a[s];
     }
-    __syncthreads();
+    if constexpr (WAVE) wave_sync(); else __syncthreads();
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = sh[lds_pad(tt + r * NT)];
-    __syncthreads();
+    for (int r = 0; r < R; ++r) v[r] = sh[slot(tt + r * NT)];
+    if constexpr (WAVE) wave_sync(); else __syncthreads();
 }
 
 template <int N>
@@ -133,17 +170,18 @@ struct ilog2<1> {
     static constexpr int v = 0;
 };
 
-template <typename F, int LEN, int R, int SIGN>
+template <typename F, int LEN, int R, int SIGN, bool WAVE = false>
 __device__ __forceinline__ void fft_reg(cx<F> (&v)[R], cx<F>* sh, int tt) {
     constexpr int LG = ilog2<LEN>::v, LR = ilog2<R>::v;
     static_assert((1 << LG) == LEN && (1 << LR) == R && LEN >= R, "power-of-two sizes");
+    static_assert(!WAVE || LEN == 64 * R, "a wave-local transform has one point set per lane");
     int Ns = 1;
 #pragma unroll
     for (int st = 0; st < LG / LR; ++st) {
-        fft_stage<F, LEN, R, R, SIGN>(v, sh, tt, Ns, opaque_tw());
+        fft_stage<F, LEN, R, R, SIGN, WAVE>(v, sh, tt, Ns, opaque_tw());
         Ns *= R;
     }
-    if constexpr (LG % LR != 0) fft_stage<F, LEN, R, (1 << (LG % LR)), SIGN>(v, sh, tt, Ns, opaque_tw());
+    if constexpr (LG % LR != 0) fft_stage<F, LEN, R, (1 << (LG % LR)), SIGN, WAVE>(v, sh, tt, Ns, opaque_tw());
 }
 
 // e^{-2 pi i e / L} for 0 <= e < L, L = 2^lg <= 2^23, from the two-level table

@@ -334,13 +334,13 @@ struct alignas(16) ColCB {
     double c, b;
 };
 
-// variant (NearVariant) of the 64-column block starting at column nb of tile T
-__device__ __forceinline__ int tile_block_variant(const NearTile& T, int64_t nb) {
-    const int b = (int)((nb - T.n0) >> 6);
-    // selects rather than an indexed load keep the tile in registers
-    const int q = b >> 3;
-    const uint32_t w = q == 0 ? T.bvar[0] : q == 1 ? T.bvar[1] : q == 2 ? T.bvar[2] : T.bvar[3];
-    return (int)((w >> (4 * (b & 7))) & 15u);
+// variant (NearVariant) of the 64-column block starting at column nb of a
+// tile whose first column is n0; bv: the tile's bvar words, copied to LDS by
+// the kernel (read with a uniform address; a per-lane copy of the tile would
+// live in private memory)
+__device__ __forceinline__ int tile_block_variant(const uint32_t* bv, int64_t n0, int64_t nb) {
+    const int b = (int)((nb - n0) >> 6);
+    return (int)((bv[b >> 3] >> (4 * (b & 7))) & 15u);
 }
 
 // One 64-column block of a sweep: the lane's columns p[0], p[4], ... (cnt of them)
@@ -359,8 +359,8 @@ __device__ __forceinline__ void near_block(const GridArgs& G, const ColCB* p, in
 // and root offsets read from LDS (cb[i] is column T.n0 + i).  The variant is
 // chosen per block (wave-uniform).
 template <bool PERT>
-__device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb, const NearTile& T, int64_t n,
-                                             NearLane& r) {
+__device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb, const uint32_t* bv,
+                                             const NearTile& T, int64_t n, NearLane& r) {
     double acc = 0.0;
     for (int64_t nb = T.n0; nb < T.n1; nb += 64) {
         const int64_t nw = n + (nb - T.n0);
@@ -368,7 +368,7 @@ __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb,
         const ColCB* p = cb + (nw - T.n0);
 #define BLOCK(M_, S_, A_) near_block<M_, S_, A_, PERT>(G, p, cnt, r, acc); break
 #define BLOCK8(M_, A_) near_block<M_, true, A_, PERT, 8>(G, p, cnt, r, acc); break
-        switch (tile_block_variant(T, nb)) {
+        switch (tile_block_variant(bv, T.n0, nb)) {
         case NV_SMALL: BLOCK(3, true, false);
         case NV_MIX12: BLOCK(12, true, true);
         case NV_MIX6: BLOCK(6, true, true);
@@ -402,8 +402,10 @@ __attribute__((amdgpu_waves_per_eu(HANK_NEAR_WPE)))
 void k_near(const NearProb* __restrict__ probs, int nprob, double* __restrict__ partial) {
     __shared__ ColCB cb[NEAR_TILE_COLS];
     __shared__ double red[4][64];
+    __shared__ uint32_t sbv[4];
     const NearProb& P = probs[find_desc<NearProb, &NearProb::tile_start>(probs, nprob, blockIdx.x)];
     const NearTile T = P.tiles[blockIdx.x - P.tile_start];
+    if (threadIdx.x < 4) sbv[threadIdx.x] = P.tiles[blockIdx.x - P.tile_start].bvar[threadIdx.x];
     double* out = partial + P.pbase + T.slot * 64;
     const GridArgs G = P.G; // by value: scalar registers, loaded once
     const double* c = P.c;
@@ -421,7 +423,7 @@ void k_near(const NearProb* __restrict__ probs, int nprob, double* __restrict__ 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t n = T.n0 + wave;
     NearLane R = near_lane(G, evec, T, lane, n);
-    const double acc = G.col_pert ? near_sweep<true>(G, cb, T, n, R) : near_sweep<false>(G, cb, T, n, R);
+    const double acc = G.col_pert ? near_sweep<true>(G, cb, sbv, T, n, R) : near_sweep<false>(G, cb, sbv, T, n, R);
     red[wave][lane] = R.active ? acc : 0.0;
     __syncthreads();
     if (wave == 0) {
@@ -515,8 +517,9 @@ __device__ __forceinline__ void near_multi_block(const GridArgs& G, NearLane& R,
 }
 
 template <bool PERT>
-__device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile& T, double (*Cs)[CS_LD],
-                                                double* Bs, double* Js, double* __restrict__ out) {
+__device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile& T, const uint32_t* bv,
+                                                double (*Cs)[CS_LD], double* Bs, double* Js,
+                                                double* __restrict__ out) {
     const GridArgs& G = P.G;
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -541,7 +544,7 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
         __syncthreads();
 #define BLOCK(M_, S_, A_) near_multi_block<M_, S_, A_, PERT>(G, R, Cs, Bs, Js + 1024 * wave, nb, T.n1, kq, lane, nblk, acc); break
         // the 8-term small-argument codes run in full here
-        int var = tile_block_variant(T, nb);
+        int var = tile_block_variant(bv, T.n0, nb);
         var = var == NV_SMALL8 ? NV_SMALL : var == NV_MIX12_8 ? NV_MIX12 : var == NV_MIX6_8 ? NV_MIX6 : var;
         switch (var) {
         case NV_SMALL: BLOCK(3, true, false);
@@ -578,14 +581,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #else
     double* Js = nullptr;
 #endif
+    __shared__ uint32_t sbv[4];
     const NearProb& Pr = probs[find_desc<NearProb, &NearProb::tile_start>(probs, nprob, blockIdx.x)];
     const NearTile T = Pr.tiles[blockIdx.x - Pr.tile_start];
+    if (threadIdx.x < 4) sbv[threadIdx.x] = Pr.tiles[blockIdx.x - Pr.tile_start].bvar[threadIdx.x];
     const NearJob P = near_job(Pr); // by value: scalar registers, loaded once
     double* out = partial + Pr.pbase + T.slot * (int64_t)P.nrhs * 64;
     if (P.G.col_pert)
-        near_multi_body<true>(P, T, Cs, Bs, Js, out);
+        near_multi_body<true>(P, T, sbv, Cs, Bs, Js, out);
     else
-        near_multi_body<false>(P, T, Cs, Bs, Js, out);
+        near_multi_body<false>(P, T, sbv, Cs, Bs, Js, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -823,6 +828,26 @@ __device__ __forceinline__ double ipow_d(double x, int e) {
     return inv ? 1.0 / r : r;
 }
 
+// A block's group and term tables as read-only, workgroup-uniform memory
+// (constant address space from a readfirstlane'd base): their entries then
+// come through scalar loads into scalar registers, and the loops they drive
+// are uniform branches instead of masked vector loops.
+template <typename T>
+__device__ __forceinline__ T scalar_entry(const T* p, int i) {
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    typedef const __attribute__((address_space(4))) uint32_t cword;
+    const uint64_t a = reinterpret_cast<uint64_t>(p + i);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    cword* q = reinterpret_cast<cword*>(((uint64_t)hi << 32) | lo);
+    uint32_t w[sizeof(T) / 4];
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) w[k] = q[k];
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
+
 // LDS elements per column FFT buffer of the column passes: L2 + L2/8 made
 // odd, so that the W columns of a workgroup start in different banks
 template <int L2>
@@ -876,6 +901,7 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict
     const FarArgs& A = D.A;
     const int t = threadIdx.x, w = t % W, tt = t / W;
     const int64_t j1 = (int64_t)mp.wg * W + w;
+    if ((int64_t)mp.wg * W >= A.ncols) return; // columns past the block: zero input, not stored
     cx<F>* my = sh + w * col_stride<L2>();
     const int ng = A.g1 - A.g0;
     cx<F>* buf = (cx<F>*)D.buf;
@@ -916,7 +942,7 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict
         const cx<double> tws = tw_big<double>(j1 * NTC, A.twshift);
         int ecur = 0, acur = 0;
         for (int g = gs; g < ge; ++g) {
-            const GroupDev Gd = A.groups[g];
+            const GroupDev Gd = scalar_entry(A.groups, g);
             if (Gd.a != acur || g == gs) { // restart the powers
 #pragma unroll
                 for (int r = 0; r < R; ++r)
@@ -940,7 +966,7 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict
                 int bcur = 0;
                 if (nidx[r] >= 0) // zero padding otherwise
                     for (int ti = Gd.t0; ti < Gd.t1; ++ti) {
-                        const TermDev Td = A.terms[ti];
+                        const TermDev Td = scalar_entry(A.terms, ti);
                         while (bcur < Td.b) {
                             xp *= xb[r];
                             ++bcur;
@@ -1043,28 +1069,38 @@ __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(const FarDesc* __restr
     cx<F>* my = sh + rl * (L1 + L1 / 8);
     const cx<F>* hrow = (const cx<F>*)D.H + rowc * L1;
     cx<F>* buf = (cx<F>*)D.buf;
-    cx<F> hv[R], tw[R];
+    cx<F> hv[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        hv[r] = hrow[tt + r * NTR];
-        const cx<F> w = tw_big<F>((int64_t)(tt + r * NTR) * rowc, A.twshift);
-        tw[r] = mk(w.x, -w.y); // e^{+2 pi i j1 m2 / L}
-    }
+    for (int r = 0; r < R; ++r) hv[r] = hrow[tt + r * NTR];
+    // inverse four-step twiddles e^{+2 pi i j1 m2 / L}, j1 = tt + r NTR, formed
+    // per group as t0 ts^r from two table entries (holding all eight across the
+    // groups would cost 32 more registers)
+    cx<double> t0 = tw_big<double>((int64_t)tt * rowc, A.twshift);
+    cx<double> ts = tw_big<double>((int64_t)NTR * rowc, A.twshift);
+    t0.y = -t0.y;
+    ts.y = -ts.y;
     const int ng = A.g1 - A.g0;
     const int gs = mp.chunk * D.gchunk, ge = min(ng, gs + D.gchunk);
     for (int gq = gs; gq < ge; ++gq) {
         const int64_t q = (int64_t)mp.j * ng + gq;
         cx<F>* p = buf + q * A.L + rowc * L1;
         cx<F> v[R];
+        // columns j1 >= ncols hold zeros (pass A does not store them), and
+        // columns j1 >= nrows feed no output row (pass C skips them)
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = p[tt + r * NTR];
+        for (int r = 0; r < R; ++r) v[r] = tt + r * NTR < A.ncols ? p[tt + r * NTR] : mk(F(0), F(0));
         fft_reg<F, L1, R, -1>(v, my, tt);
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = cmul(v[r], hv[r]);
         fft_reg<F, L1, R, 1>(v, my, tt);
         if (okrow) {
+            cx<double> t = t0;
+            asm volatile("" : "+v"(t.x), "+v"(t.y)); // formed here, not hoisted out of the group loop
 #pragma unroll
-            for (int r = 0; r < R; ++r) p[tt + r * NTR] = cmul(v[r], tw[r]);
+            for (int r = 0; r < R; ++r) {
+                if (tt + r * NTR < A.nrows) p[tt + r * NTR] = cmul(v[r], mk(F(t.x), F(t.y)));
+                if (r + 1 < R) t = cmul(t, ts);
+            }
         }
     }
 }
@@ -1081,6 +1117,7 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict
     const FarArgs& A = D.A;
     const int t = threadIdx.x, w = t % W, tt = t / W;
     const int64_t j1 = (int64_t)mp.wg * W + w;
+    if ((int64_t)mp.wg * W >= A.nrows) return; // columns holding no output row
     cx<F>* my = sh + w * col_stride<L2>();
     const int ng = A.g1 - A.g0;
     const cx<F>* buf = (const cx<F>*)D.buf;
@@ -1107,7 +1144,7 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
         int ecur = 0, acur = 0;
         for (int g = gs; g < ge; ++g) {
-            const GroupDev Gd = A.groups[g];
+            const GroupDev Gd = scalar_entry(A.groups, g);
             if (Gd.a != acur || g == gs) {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
@@ -1153,6 +1190,366 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Column passes with one wave per column (L2 = 64 R points, W = 8 columns per
+// workgroup of 8 waves).  The column FFT is wave-local: its stages exchange
+// through the wave's own LDS region without a workgroup barrier.  The data
+// cross between the coalesced global layout (thread t: column t % 8, rows
+// t/8 + 64 r, so a wave instruction covers 8 rows x 128 bytes) and the
+// wave-per-column layout through an LDS transposition; with two LDS buffers
+// (L2 <= 256) one workgroup barrier per group suffices, with one buffer two.
+// ---------------------------------------------------------------------------
+// two workgroups per compute unit (at most 128 registers) for columns of 256
+// points; one for 512 (eight points per lane)
+#ifndef HANK_WAVE_COLS_WPE
+#define HANK_WAVE_COLS_WPE __attribute__((amdgpu_waves_per_eu(L2 <= 256 ? 4 : 2)))
+#endif
+// LDS elements per column of the wave-per-column kernels (slots lds_swz):
+// L2 + 2, so that the eight columns a wave instruction touches in the
+// transposition (two rows each) fall into distinct groups of four banks
+template <int L2>
+constexpr int wave_col_stride() {
+    return HANK_LDS_SWZ ? L2 + 2 : (L2 + L2 / 8) | 1;
+}
+template <int L2>
+constexpr int wave_col_bufs() {
+    return L2 <= 256 ? 2 : 1;
+}
+
+// Pass A: the inputs of the lane's positions n' = j1 + L1 (lane + 64 r) of the
+// wave's column j1 for every group (as k_pass_a), the column FFT, the
+// four-step twiddle, and through LDS to buf[m2][j1].
+template <typename F, int L2>
+__global__ __launch_bounds__(512) HANK_WAVE_COLS_WPE void k_pass_aw(const FarDesc* __restrict__ descs, int ndesc) {
+    constexpr int W = 8, R = L2 / 64, S = wave_col_stride<L2>(), NB = wave_col_bufs<L2>();
+    __shared__ cx<F> sh[NB][W * S];
+    const FarItem mp = far_item(descs, ndesc, 0, descs[0].A.L1 / W);
+    const FarDesc& D = descs[mp.desc];
+    const FarArgs& A = D.A;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int cw = t % W, q = t / W;
+    const int64_t jb = (int64_t)mp.wg * W, j1 = jb + wv;
+    if (jb >= A.ncols) return; // columns past the block: zero input, not stored
+    const int ng = A.g1 - A.g0;
+    cx<F>* buf = (cx<F>*)D.buf;
+
+    double vw[R], xb[R], la[R], pw[R];
+    cx<double> qb[R]; // q(n') c_n (w^_n/w0)^(-1/2); zero past the block's columns
+    const int j = mp.j;
+    const double* cj = D.c + (int64_t)j * D.ldc;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t np = j1 + (int64_t)A.L1 * (lane + 64 * r);
+        vw[r] = 1.0;
+        xb[r] = la[r] = 0.0;
+        qb[r] = mk(0.0, 0.0);
+        if (np < A.ncols) {
+            const int64_t n = A.na + np;
+            const int64_t Nn = A.ac * n + A.bc;
+            const double wn = (double)Nn * A.pi_Qc;
+            const double bn = A.col_pert ? D.b[n - 1] : 0.0;
+            vw[r] = wn / A.w0;
+            const double iw = 1.0 / vw[r];
+            xb[r] = (bn / A.bref) * iw;
+            la[r] = (wn + bn) / A.lref;
+            qb[r] = cscale(expi_ratio(2 * A.Kka * A.ac * np + A.ar * A.ac * np * np, 2 * A.D), sqrt(iw) * cj[n - 1]);
+        }
+    }
+    // four-step twiddles e^{-2 pi i j1 m2 / L} of the outputs m2 = lane + 64 r
+    const cx<double> tw0 = tw_big<double>(j1 * lane, A.twshift);
+    const cx<double> tws = tw_big<double>(j1 * 64, A.twshift);
+    const int gs = A.g0 + mp.chunk * D.gchunk, ge = min(A.g1, gs + D.gchunk);
+    int ecur = 0, acur = 0, b = 0;
+    for (int g = gs; g < ge; ++g) {
+        const GroupDev Gd = scalar_entry(A.groups, g);
+        if (Gd.a != acur || g == gs) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                pw[r] = ipow_d<double>(vw[r], Gd.e) * (Gd.a ? ipow_d<double>(la[r], Gd.a) : 1.0);
+        } else {
+            for (; ecur < Gd.e; ++ecur) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) pw[r] *= vw[r];
+            }
+            for (; ecur > Gd.e; --ecur) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) pw[r] /= vw[r];
+            }
+        }
+        ecur = Gd.e;
+        acur = Gd.a;
+        cx<F> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double xp = 1.0, Xr = 0.0, Xi = 0.0;
+            int bcur = 0;
+            for (int ti = Gd.t0; ti < Gd.t1; ++ti) {
+                const TermDev Td = scalar_entry(A.terms, ti);
+                while (bcur < Td.b) {
+                    xp *= xb[r];
+                    ++bcur;
+                }
+                Xr = fma(Td.kre, xp, Xr);
+                Xi = fma(Td.kim, xp, Xi);
+            }
+            const cx<double> y = cmul(mk(Xr * pw[r], Xi * pw[r]), qb[r]);
+            v[r] = mk(F(y.x), F(y.y));
+        }
+        cx<F>* my = &sh[b][wv * S];
+        fft_reg<F, L2, R, -1, true>(v, my, lane);
+        cx<double> tw = tw0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            my[lds_swz(lane + 64 * r)] = cmul(v[r], mk(F(tw.x), F(tw.y)));
+            if (r + 1 < R) tw = cmul(tw, tws);
+        }
+        __syncthreads();
+        cx<F>* out = buf + ((int64_t)j * ng + (g - A.g0)) * A.L;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int m2 = q + 64 * r;
+            out[(int64_t)m2 * A.L1 + jb + cw] = sh[b][cw * S + lds_swz(m2)];
+        }
+        if constexpr (NB == 1)
+            __syncthreads();
+        else
+            b ^= 1;
+    }
+}
+
+// Pass C: buf[m2][j1] through LDS to the wave of column j1, the inverse column
+// FFT, and per output position k' = j1 + L1 (lane + 64 r) the complex sum
+// acc = sum_g A_g(k) conv_g(k') over the groups (A_g real, so that the post-
+// chirp p(k') is applied once at the end: f_k += Re(p(k') acc)).  The next
+// group's data are loaded while the current one is transformed.
+template <typename F, int L2>
+__global__ __launch_bounds__(512) HANK_WAVE_COLS_WPE void k_pass_cw(const FarDesc* __restrict__ descs, int ndesc) {
+    constexpr int W = 8, R = L2 / 64, S = wave_col_stride<L2>(), NB = wave_col_bufs<L2>();
+    __shared__ cx<F> sh[NB][W * S];
+    const FarItem mp = far_item(descs, ndesc, 0, descs[0].A.L1 / W);
+    const FarDesc& D = descs[mp.desc];
+    const FarArgs& A = D.A;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int cw = t % W, q = t / W;
+    const int64_t jb = (int64_t)mp.wg * W, j1 = jb + wv;
+    if (jb >= A.nrows) return; // columns holding no output row
+    const int ng = A.g1 - A.g0;
+    const cx<F>* buf = (const cx<F>*)D.buf;
+    double rho[R], ek[R], pw[R];
+    cx<double> acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t kp = j1 + (int64_t)A.L1 * (lane + 64 * r);
+        rho[r] = 1.0;
+        ek[r] = 0.0;
+        acc[r] = mk(0.0, 0.0);
+        if (kp < A.nrows) {
+            const int64_t k = A.ka + kp;
+            rho[r] = ((double)(A.ar * k + A.br) / (double)A.Dr) / A.r0;
+            ek[r] = A.row_pert ? D.e[k - 1] / A.eref : 0.0;
+        }
+    }
+    const int j = mp.j;
+    const int gs = A.g0 + mp.chunk * D.gchunk, ge = min(A.g1, gs + D.gchunk);
+    auto load = [&](int g, cx<F>(&v)[R]) {
+        const cx<F>* p = buf + ((int64_t)j * ng + (g - A.g0)) * A.L + jb + cw;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = p[(int64_t)(q + 64 * r) * A.L1];
+    };
+    cx<F> vn[R];
+    load(gs, vn);
+    int ecur = 0, acur = 0, b = 0;
+    for (int g = gs; g < ge; ++g) {
+        cx<F> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            v[r] = vn[r];
+            sh[b][cw * S + lds_swz(q + 64 * r)] = v[r];
+        }
+        if (g + 1 < ge) load(g + 1, vn);
+        __syncthreads();
+        cx<F>* my = &sh[b][wv * S];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = my[lds_swz(lane + 64 * r)];
+        wave_sync();
+        fft_reg<F, L2, R, 1, true>(v, my, lane);
+        const GroupDev Gd = scalar_entry(A.groups, g);
+        if (Gd.a != acur || g == gs) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                pw[r] = ipow_d<double>(rho[r], Gd.e) * (Gd.a ? ipow_d<double>(ek[r], Gd.a) : 1.0);
+        } else {
+            for (; ecur < Gd.e; ++ecur) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) pw[r] *= rho[r];
+            }
+            for (; ecur > Gd.e; --ecur) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) pw[r] /= rho[r];
+            }
+        }
+        ecur = Gd.e;
+        acur = Gd.a;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double wgt = Gd.scale * pw[r];
+            acc[r].x = fma(wgt, (double)v[r].x, acc[r].x);
+            acc[r].y = fma(wgt, (double)v[r].y, acc[r].y);
+        }
+        if constexpr (NB == 1)
+            __syncthreads();
+        else
+            b ^= 1;
+    }
+    double* fj = D.nchunk == 1 ? D.f + (int64_t)j * D.ldo + A.ka - 1
+                               : D.part + ((int64_t)j * D.nchunk + mp.chunk) * A.nrows;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t kp = j1 + (int64_t)A.L1 * (lane + 64 * r);
+        if (kp < A.nrows) { // rows past the block are discarded
+            const cx<double> pk = cscale(
+                expi_ratio(2 * A.Kka * A.Nna + 2 * A.ar * A.Nna * kp + A.ar * A.ac * kp * kp, 2 * A.D),
+                1.0 / sqrt(rho[r]));
+            const double val = pk.x * acc[r].x - pk.y * acc[r].y;
+            if (D.nchunk == 1)
+                fj[kp] += val;
+            else
+                fj[kp] = val;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row pass for rows of L1 = 8 x 512 points, 8 waves per row.  With j1 = b + 512 a
+// and k = k1 + 8 k2 (a, k1 < 8; b, k2 < 512) the row DFT is
+//     X[k1 + 8 k2] = sum_b W512^{b k2} W^{b k1} sum_a x[b + 512 a] W8^{a k1},
+// W = e^{-2 pi i/L1}: thread b does the 8-point DFT over a in registers, one
+// LDS exchange hands wave k1 the values of every b, and wave k1 does the
+// 512-point DFT over b wave-locally.  The spectrum then sits in wave k1, lane
+// l, register s as X[k1 + 8 (l + 64 s)] -- the layout in which the chirp
+// spectrum of such rows is stored (k_pass_bw_fwd) -- and the inverse retraces
+// the steps.  A group costs two workgroup barriers.
+// ---------------------------------------------------------------------------
+#ifndef HANK_WAVE_ROWS
+#define HANK_WAVE_ROWS 1
+#endif
+
+template <typename F, int L1>
+constexpr bool wave_rows() {
+    return HANK_WAVE_ROWS && sizeof(F) == 8 && L1 == 4096;
+}
+
+// forward steps on v[a] = x[t + 512 a] of thread t; on return v[s] holds
+// X[wv + 8 (lane + 64 s)] of the thread's wave wv.  sh: 8 regions of SR.
+template <typename F, int SR>
+__device__ __forceinline__ void row8x512_forward(cx<F> (&v)[8], cx<F>* sh, int t, int lane, int wv) {
+    dft_small<F, 8, -1>(v);
+    cx<double> w1 = tw_big<double>(t, 23 - 12); // W^t
+    asm volatile("" : "+v"(w1.x), "+v"(w1.y));  // powers formed here, per group
+    cx<double> w = w1;
+    sh[lds_swz(t)] = v[0];
+#pragma unroll
+    for (int k1 = 1; k1 < 8; ++k1) {
+        sh[k1 * SR + lds_swz(t)] = cmul(v[k1], mk(F(w.x), F(w.y)));
+        if (k1 + 1 < 8) w = cmul(w, w1);
+    }
+    __syncthreads();
+    cx<F>* my = sh + wv * SR;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = my[lds_swz(lane + 64 * s)];
+    wave_sync();
+    fft_reg<F, 512, 8, -1, true>(v, my, lane);
+}
+
+template <typename F, int L1>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_pass_bw(
+    const FarDesc* __restrict__ descs, int ndesc, int per_b) {
+    static_assert(L1 == 4096, "rows of 8 x 512 points");
+    constexpr int SR = wave_lds_len<512>();
+    __shared__ cx<F> sh[8 * SR];
+    const FarItem mp = far_item(descs, ndesc, 1, per_b);
+    const FarDesc& D = descs[mp.desc];
+    const FarArgs& A = D.A;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int64_t row = mp.wg; // one row per workgroup: mp.wg < L2
+    cx<F>* my = sh + wv * SR;
+    // this wave's chirp spectrum (permuted layout)
+    const cx<F>* hrow = (const cx<F>*)D.H + row * L1 + wv * 512;
+    cx<F> hv[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) hv[s] = hrow[lane + 64 * s];
+    cx<F>* buf = (cx<F>*)D.buf;
+    const int ng = A.g1 - A.g0;
+    const int gs = mp.chunk * D.gchunk, ge = min(ng, gs + D.gchunk);
+    // columns j1 = t + 512 a >= ncols hold zeros (pass A does not store them),
+    // and columns j1 >= nrows feed no output row (pass C skips them): the
+    // loads and stores this thread makes, as bit masks over a
+    uint32_t lmask = 0, smask = 0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        lmask |= uint32_t(t + 512 * a < A.ncols) << a;
+        smask |= uint32_t(t + 512 * a < A.nrows) << a;
+    }
+    for (int gq = gs; gq < ge; ++gq) {
+        cx<F>* p = buf + ((int64_t)mp.j * ng + gq) * A.L + row * L1;
+        cx<F> v[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) v[a] = (lmask >> a) & 1 ? p[t + 512 * a] : mk(F(0), F(0));
+        row8x512_forward<F, SR>(v, sh, t, lane, wv);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s] = cmul(v[s], hv[s]);
+        fft_reg<F, 512, 8, 1, true>(v, my, lane);
+        {
+            // W^{-b wv} for b = lane + 64 s (base times step^s, from the table per group)
+            const cx<double> i0 = tw_big<double>((int64_t)lane * wv, 23 - 12);
+            cx<double> is = tw_big<double>((int64_t)64 * wv, 23 - 12);
+            is.y = -is.y;
+            cx<double> w = mk(i0.x, -i0.y);
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                my[lds_swz(lane + 64 * s)] = cmul(v[s], mk(F(w.x), F(w.y)));
+                if (s + 1 < 8) w = cmul(w, is);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) v[k1] = sh[k1 * SR + lds_swz(t)];
+        dft_small<F, 8, 1>(v);
+        // four-step twiddles e^{+2 pi i j1 row / L}, j1 = t + 512 a
+        const cx<double> f0 = tw_big<double>((int64_t)t * row, A.twshift);
+        cx<double> fs = tw_big<double>((int64_t)512 * row, A.twshift);
+        fs.y = -fs.y;
+        cx<double> w = mk(f0.x, -f0.y);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            if ((smask >> a) & 1) p[t + 512 * a] = cmul(v[a], mk(F(w.x), F(w.y)));
+            if (a + 1 < 8) w = cmul(w, fs);
+        }
+    }
+}
+
+// The chirp spectrum H^ = row FFT / L of such rows, stored in the permuted
+// layout H'[row][k1 * 512 + k2] = H^[row][k1 + 8 k2].
+template <typename F, int L1>
+__global__ __launch_bounds__(512) void k_pass_bw_fwd(FarArgs A, const cx<F>* __restrict__ buf, cx<F>* __restrict__ H) {
+    static_assert(L1 == 4096, "rows of 8 x 512 points");
+    constexpr int SR = wave_lds_len<512>();
+    __shared__ cx<F> sh[8 * SR];
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int64_t row = blockIdx.x;
+    cx<F> v[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) v[a] = buf[row * L1 + t + 512 * a];
+    row8x512_forward<F, SR>(v, sh, t, lane, wv);
+    const F sc = F(1.0 / (double)A.L);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) H[row * L1 + wv * 512 + lane + 64 * s] = cscale(v[s], sc);
 }
 
 // f += sum of the pass-C chunk sums, in chunk order (deterministic)
@@ -1228,17 +1625,29 @@ hipError_t launch_near_reduce(const NearProb* probs, int32_t nprob, int64_t nwv1
 }
 
 // column passes: which 0 = A on data, 1 = A on the chirp kernel, 2 = C
+#ifndef HANK_WAVE_COLS
+#define HANK_WAVE_COLS 1
+#endif
 template <typename F, int L2>
 static void pass_ac_dispatch(int which, const FarArgs* A, const FarDesc* descs, int ndesc, int64_t nwg, void* buf,
                              hipStream_t s) {
     constexpr int W = col_width(L2, sizeof(F) == 4);
     dim3 block(W * L2 / 8);
-    if (which == 0)
-        hipLaunchKernelGGL((k_pass_a<F, L2, W>), dim3((unsigned)nwg), block, 0, s, descs, ndesc);
-    else if (which == 1)
+    // FP64 columns of 256 and 512 points: the one-wave-per-column kernels
+    constexpr bool wave_cols = HANK_WAVE_COLS && sizeof(F) == 8 && (L2 == 256 || L2 == 512) && W == 8;
+    if (which == 0) {
+        if constexpr (wave_cols)
+            hipLaunchKernelGGL((k_pass_aw<F, L2>), dim3((unsigned)nwg), dim3(512), 0, s, descs, ndesc);
+        else
+            hipLaunchKernelGGL((k_pass_a<F, L2, W>), dim3((unsigned)nwg), block, 0, s, descs, ndesc);
+    } else if (which == 1) {
         hipLaunchKernelGGL((k_pass_a_kernel<F, L2, W>), dim3((unsigned)(A->L1 / W)), block, 0, s, *A, (cx<F>*)buf);
-    else
-        hipLaunchKernelGGL((k_pass_c<F, L2, W>), dim3((unsigned)nwg), block, 0, s, descs, ndesc);
+    } else {
+        if constexpr (wave_cols)
+            hipLaunchKernelGGL((k_pass_cw<F, L2>), dim3((unsigned)nwg), dim3(512), 0, s, descs, ndesc);
+        else
+            hipLaunchKernelGGL((k_pass_c<F, L2, W>), dim3((unsigned)nwg), block, 0, s, descs, ndesc);
+    }
 }
 
 template <typename F>
@@ -1269,12 +1678,20 @@ static void pass_b_dispatch(bool fwd_only, const FarArgs* A, int32_t L2, const F
                             int64_t nwg, void* buf, void* H, hipStream_t s) {
     constexpr int ROWS = rows_per_wg<L1>();
     dim3 block(ROWS * L1 / 8);
-    if (fwd_only)
+    if constexpr (wave_rows<F, L1>()) { // one row per workgroup of 512 threads, as k_pass_b's
+        static_assert(ROWS == 1, "one row per workgroup");
+        if (fwd_only)
+            hipLaunchKernelGGL((k_pass_bw_fwd<F, L1>), dim3((unsigned)A->L2), dim3(512), 0, s, *A, (const cx<F>*)buf,
+                               (cx<F>*)H);
+        else
+            hipLaunchKernelGGL((k_pass_bw<F, L1>), dim3((unsigned)nwg), dim3(512), 0, s, descs, ndesc, (int)L2);
+    } else if (fwd_only) {
         hipLaunchKernelGGL((k_pass_b_fwd<F, L1, ROWS>), dim3((unsigned)((A->L2 + ROWS - 1) / ROWS)), block, 0, s, *A,
                            (const cx<F>*)buf, (cx<F>*)H);
-    else
+    } else {
         hipLaunchKernelGGL((k_pass_b<F, L1, ROWS>), dim3((unsigned)nwg), block, 0, s, descs, ndesc,
                            (int)((L2 + ROWS - 1) / ROWS));
+    }
 }
 
 template <typename F>

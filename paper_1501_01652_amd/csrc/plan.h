@@ -105,9 +105,9 @@ struct Plan {
 // Cost-model constants (seconds); refined from measurements through the
 // environment (HANK_COST_FFT, HANK_COST_NEAR, HANK_COST_BLOCK).
 struct CostModel {
-    double fft_pt_group64 = 3.3e-11; // per FFT point per group per right-hand side, FP64 (measured)
+    double fft_pt_group64 = 2.2e-11; // per FFT point per group per right-hand side, FP64 (measured)
     double fft_pt_group32 = 1.95e-11; // same, FP32
-    double near_entry = 2.25e-12;    // per directly summed entry, one right-hand side (measured)
+    double near_entry = 1.95e-12;    // per directly summed entry, one right-hand side (measured)
     double near_plain_entry = 1.3e-12; // the same without root perturbations (Schlomilch, order 0)
     double near_nu_entry = 5.1e-12;  // the same for Schlomilch of order nu > 0 (k_near_nu, measured)
     double near_multi_entry = 4.2e-12; // per entry with several right-hand sides (J_0 once per entry)
@@ -149,6 +149,8 @@ bool build_block_terms(const Grid& g, Block& b, double eps, int mode, int Mpaper
 void fft_split(int64_t L, int32_t& L1, int32_t& L2);
 int default_fft_l2(int lg);
 void set_fft_split(int lg, int l2); // l2 = 0 restores the default
+int tuned_fft_split(int lg);        // the installed l2 (0: none)
+bool valid_fft_split(int lg, int l2); // a split the kernels support (L1 >= L2, L1 <= 8192)
 
 CostModel cost_model_from_env();
 

@@ -16,7 +16,9 @@
 #include <complex>
 #include <cstdlib>
 #include <map>
+#include <mutex>
 #include <stdexcept>
+#include <tuple>
 
 namespace hank {
 
@@ -146,12 +148,16 @@ void set_fft_split(int lg, int l2) {
     if (lg >= 0 && lg < 32) g_l2_tuned[lg] = l2;
 }
 
+int tuned_fft_split(int lg) { return (lg >= 0 && lg < 32) ? g_l2_tuned[lg] : 0; }
+
+bool valid_fft_split(int lg, int l2) { return lg >= 6 && lg <= 23 && l2 >= 3 && 2 * l2 <= lg && lg - l2 <= 13; }
+
 int default_fft_l2(int lg);
 
 void fft_split(int64_t L, int32_t& L1, int32_t& L2) {
     int lg = 0;
     while ((int64_t(1) << lg) < L) ++lg;
-    if (lg < 32 && g_l2_tuned[lg] > 0 && 2 * g_l2_tuned[lg] <= lg && lg - g_l2_tuned[lg] <= 13) {
+    if (lg < 32 && g_l2_tuned[lg] > 0 && valid_fft_split(lg, g_l2_tuned[lg])) {
         L2 = int32_t(1) << g_l2_tuned[lg];
         L1 = int32_t(1) << (lg - g_l2_tuned[lg]);
         return;
@@ -163,12 +169,15 @@ void fft_split(int64_t L, int32_t& L1, int32_t& L2) {
 
 int default_fft_l2(int lg) {
     // columns (passes A and C) of 2^l2 <= 1024 points, rows (pass B) of
-    // 2^l1 <= 2^l1max points (l1max = 13, HANK_FFT_L1MAX overrides);
-    // balanced below 2^16, columns of at least 256 above
-    static const int l1max = [] {
+    // 2^l1 <= 2^l1max points; balanced below 2^16, columns of at least 256
+    // above.  l1max = 12 up to 2^21 points (rows of 4096 points run on the
+    // eight-wave four-step row pass, measured faster than rows of 8192 with
+    // columns of 256), 13 above; HANK_FFT_L1MAX overrides
+    static const int l1max_env = [] {
         const char* e = std::getenv("HANK_FFT_L1MAX");
-        return e ? std::max(8, std::min(13, std::atoi(e))) : 13;
+        return e ? std::max(8, std::min(13, std::atoi(e))) : 0;
     }();
+    const int l1max = l1max_env ? l1max_env : (lg <= 21 ? 12 : 13);
     return (lg <= 16) ? lg / 2 : std::min(10, std::max(8, lg - l1max));
 }
 
@@ -544,10 +553,50 @@ static double plan_cost(const Plan& p, const CostModel& cm) {
                                 : cm.near_multi_entry + r * cm.near_rhs);
     for (auto& b : p.blocks) {
         const double g64 = double(b.g64), g32 = double(b.groups.size()) - g64;
+        // the passes skip the work-buffer columns without data (j1 >= ncols:
+        // pass A and pass B's loads) or results (j1 >= nrows: pass B's stores
+        // and pass C); with time shares of about 1/4, 1/2, 1/4 for passes A, B, C
+        // and pass B's transforms always run in full, the relative cost is
+        // 1/4 + 3/8 (fa + fc)
+        const double L1 = double(b.L1), fa = std::min(double(b.nb - b.na + 1), L1) / L1,
+                     fc = std::min(double(b.kb - b.ka + 1), L1) / L1;
         c += cm.block * ((g64 > 0 && g32 > 0) ? 2.0 : 1.0) +
-             double(b.L) * (g64 * cm.fft_pt_group64 + g32 * cm.fft_pt_group32) * r;
+             double(b.L) * (g64 * cm.fft_pt_group64 + g32 * cm.fft_pt_group32) * r * (0.25 + 0.375 * (fa + fc));
     }
     return c;
+}
+
+// Outcome of the tuned search at a grid size, per (task, N, eps, precision,
+// nrhs, nu, shift), computed once (by a full make_plan there) and kept.
+struct TunedParams {
+    int M = 0;
+    double beta = 0;
+    int P = 0;
+};
+static thread_local TunedParams last_search_;
+static bool tuned_params(int task, int64_t Ng, double eps, int precision, int64_t nrhs, int nu, int64_t shift,
+                         const CostModel& cm, TunedParams& out) {
+    typedef std::tuple<int, int64_t, double, int, int64_t, int, int64_t> K;
+    static std::mutex mu;
+    static std::map<K, TunedParams> cache;
+    const K key{task, Ng, eps, precision, nrhs, nu, shift};
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            out = it->second;
+            return true;
+        }
+    }
+    try {
+        (void)make_plan(task, Ng, eps, 0, precision, false, cm, nrhs, 0, nu, shift); // runs the full search
+    } catch (const std::exception&) {
+        return false;
+    }
+    out = last_search_;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = out;
+    return true;
 }
 
 Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool direct, const CostModel& cm,
@@ -644,30 +693,62 @@ Plan make_plan(int task, int64_t N, double eps, int mode, int precision, bool di
     // the plain direct sum is a candidate too
     Plan best = p;
     finish(best);
-    const double betas[] = {0.06, 0.1, 0.15, 0.22, 0.3, 0.4, 0.55};
-    for (int Mc = 2; Mc <= 14; ++Mc) {
-        if (2 * Mc + 0.5 < nu) continue; // the remainder bound needs M >= nu/2 - 1/4
-        double s = param_s(nu, Mc, eps / 8.0);
-        if (s < 2.0) continue;
-        double R0 = std::sqrt(s / M_PI) / std::sqrt(double(N));
-        for (double beta : betas)
-            for (int P = 0; P <= 10; ++P) {
-                Plan q = p;
-                q.s = s;
-                q.alpha = std::sqrt(s / M_PI);
-                q.beta = beta;
-                q.P = P;
-                q.blocks = staircase(q.g, s, R0, beta, P, 1, 1);
-                bool valid = true;
-                for (auto& b : q.blocks)
-                    if (!build(b)) {
-                        valid = false;
-                        break;
-                    }
-                if (!valid || !finish(q)) continue;
-                if (q.cost < best.cost) best = q;
-                if (P > 0 && q.blocks.size() <= size_t(1 + 2 * (P - 1))) break; // no new strip
+    int best_M = 0; // 0: the direct sum
+    // one candidate: corner value s_{nu,M}(eps/8), refinement beta, P strips;
+    // returns false when it adds no strip over P - 1
+    auto candidate = [&](int Mc, double beta, int P) -> bool {
+        const double s = param_s(nu, Mc, eps / 8.0);
+        if (s < 2.0) return true;
+        const double R0 = std::sqrt(s / M_PI) / std::sqrt(double(N));
+        Plan q = p;
+        q.s = s;
+        q.alpha = std::sqrt(s / M_PI);
+        q.beta = beta;
+        q.P = P;
+        q.blocks = staircase(q.g, s, R0, beta, P, 1, 1);
+        bool valid = true;
+        for (auto& b : q.blocks)
+            if (!build(b)) {
+                valid = false;
+                break;
             }
+        if (valid && finish(q) && q.cost < best.cost) {
+            best = q;
+            best_M = Mc;
+        }
+        return !(P > 0 && q.blocks.size() <= size_t(1 + 2 * (P - 1)));
+    };
+    // The full search costs 5-60 ms of host time, and its outcome (M, beta, P)
+    // changes slowly with N.  Off the grid N_j = round(2^(j/4)) the outcome of
+    // the search at the grid point below is reused, so that planning an
+    // unseen N costs one candidate; it depends on N alone (never on which
+    // plans were built before), so the same N always gets the same plan.
+    const bool default_cm = cm.near_entry == CostModel().near_entry && cm.fft_pt_group64 == CostModel().fft_pt_group64 &&
+                            cm.block == CostModel().block && cm.near_multi_entry == CostModel().near_multi_entry;
+    int jg = 0;
+    while (std::llround(std::pow(2.0, (jg + 1) / 4.0)) <= N) ++jg;
+    const int64_t Ng = std::llround(std::pow(2.0, jg / 4.0));
+    TunedParams tp;
+    if (default_cm && Ng != N && Ng >= 1024 && tuned_params(task, Ng, eps, precision, nrhs, nu, shift, cm, tp)) {
+        if (tp.M > 0) candidate(tp.M, tp.beta, tp.P);
+    } else {
+        const double betas[] = {0.06, 0.1, 0.15, 0.22, 0.3, 0.4, 0.55};
+        int bp = 0;
+        double bbeta = 0;
+        for (int Mc = 2; Mc <= 14; ++Mc) {
+            if (2 * Mc + 0.5 < nu) continue; // the remainder bound needs M >= nu/2 - 1/4
+            for (double beta : betas)
+                for (int P = 0; P <= 10; ++P) {
+                    const int before = best_M;
+                    const double bcost = best.cost;
+                    if (!candidate(Mc, beta, P)) break; // no new strip
+                    if (best_M != before || best.cost != bcost) {
+                        bp = P;
+                        bbeta = beta;
+                    }
+                }
+        }
+        last_search_ = TunedParams{best_M, bbeta, bp};
     }
     // keep the paper's reported M, K, T alongside the tuned partition
     best.M = p.M;

@@ -85,17 +85,18 @@ def batch_specs(count: int = 1024, seed: int = SEED_BATCH, nlo: int = 2 ** 8, nh
 def serve_trace(rate: float = 2000.0, seconds: float = 60.0, seed: int = SEED_SERVE,
                 lg_lo: int = 10, lg_hi: int = 22):
     """Open-loop Poisson arrivals at `rate` per second for `seconds`: the same
-    task and eps mix, one right-hand side, N log-uniform over the sizes
-    2^lg_lo .. 2^lg_hi (a grid, so that plans can be kept on the device)."""
+    task and eps mix, one right-hand side, N log-uniform over the integers
+    [2^lg_lo, 2^lg_hi] (so that most large sizes are seen once)."""
     rng = np.random.default_rng(seed)
     names = [t for t, _ in TASK_MIX]
     probs = [p for _, p in TASK_MIX]
     t, out = 0.0, []
+    lo, hi = np.log(2.0 ** lg_lo), np.log(2.0 ** lg_hi + 1.0)
     while True:
         t += float(rng.exponential(1.0 / rate))
         if t >= seconds:
             break
         out.append({"arrival": t, "task": names[int(rng.choice(3, p=probs))],
-                    "N": int(2 ** int(rng.integers(lg_lo, lg_hi + 1))),
+                    "N": int(min(2 ** lg_hi, np.exp(rng.uniform(lo, hi)))),
                     "eps": float(EPS_SET[int(rng.integers(0, 3))])})
     return out

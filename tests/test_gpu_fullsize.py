@@ -32,14 +32,19 @@ def boundary_rows(task, N, eps, **kw):
 
 
 def check(task, N, eps, c, rows, label, **kw):
+    """The sampled rows against the oracle: within C eps sum|c| (the paper's
+    statement) and, for the dense random c of these workloads, also within
+    C eps ||c||_2, which is tighter by about sqrt(N)."""
     f = host(hank.transform(task, dev(c), eps, **kw))
     ref = oracle.eval_rows(task, c, rows=rows)
     err = float(np.max(np.abs(f[rows - 1] - ref)))
     Cm = err / (eps * float(np.sum(np.abs(c))))
+    C2 = err / (eps * float(np.sqrt(np.sum(c * c))))
     info = hank.plan_info(task, N, eps, **kw)
-    print("%s N=%d eps=%g %s blocks=%d fp32=%d rows=%d max err %.3e measured C=%.3g" %
-          (task, N, eps, label, info["nblocks"], info["bulk_fp32"], len(rows), err, Cm))
+    print("%s N=%d eps=%g %s blocks=%d fp32=%d rows=%d max err %.3e measured C=%.3g (l2: %.3g)" %
+          (task, N, eps, label, info["nblocks"], info["bulk_fp32"], len(rows), err, Cm, C2))
     assert Cm <= C_TOL
+    assert C2 <= C_TOL
     return f
 
 
@@ -74,6 +79,14 @@ def test_dht0_2pow20(eps):
     c = inputs.workload("dht0", N)
     rows = inputs.sampled_rows(N, 48, boundary_rows("dht0", N, eps))
     check("dht0", N, eps, c, rows, "tuned")
+
+
+def test_dht0_2pow20_fp64_headline():
+    """The configuration bench.py times: eps = 1e-8, every far transform in FP64."""
+    N, eps = 1 << 20, 1e-8
+    c = inputs.workload("dht0", N)
+    rows = inputs.sampled_rows(N, 48, boundary_rows("dht0", N, eps, precision=1))
+    check("dht0", N, eps, c, rows, "tuned, FP64 transforms", precision=1)
 
 
 def test_dht0_2pow20_paper_plan():
@@ -152,6 +165,39 @@ def test_dht0_2pow20_one_hot_columns():
         ref = oracle.eval_rows("dht0", c)
         worst = max(worst, float(np.max(np.abs(f - ref))))
     print("dht0 N=2^20 one-hot %d columns: worst entry error %.3e (%.3g eps)" % (len(cols), worst, worst / eps))
+    assert worst <= C_TOL * eps
+
+
+def interior_columns(task, N, eps, **kw):
+    """Per far block: its middle column, the columns on both sides of the
+    first row-FFT boundary of its work buffer (n - col0 = L1 - 1, L1: the
+    four-step split puts them in different FFT rows and columns), and its
+    second-to-last column."""
+    cols = set()
+    for b in hank.plan_blocks(task, N, eps, **kw):
+        c0, c1, l1 = b["col0"], b["col1"], b["fft_l1"]
+        cols |= {(c0 + c1) // 2, c1 - 1}
+        cols |= {n for n in (c0 + l1 - 1, c0 + l1) if n <= c1}
+    return sorted(n for n in cols if 1 <= n <= N)
+
+
+@pytest.mark.parametrize("task,N,eps,precision", [("dht0", 1 << 20, 1e-8, 1), ("dht0", 1 << 20, 1e-4, 0),
+                                                  ("fourier_bessel", 1 << 16, 1e-14, 0)])
+def test_one_hot_block_interior_columns(task, N, eps, precision):
+    """c = e_n at columns inside every far block (see interior_columns): each
+    one drives the block's full FFTs, and every row is checked against
+    J_0(r_k w_n) per entry within C eps."""
+    cols = interior_columns(task, N, eps, precision=precision)
+    assert len(cols) >= 6
+    worst = 0.0
+    for n in cols:
+        c = np.zeros(N)
+        c[n - 1] = 1.0
+        f = host(hank.transform(task, dev(c), eps, precision=precision))
+        ref = oracle.eval_rows(task, c)
+        e = float(np.max(np.abs(f - ref)))
+        print("%s N=%d eps=%g one-hot column %d: worst entry error %.3e (%.3g eps)" % (task, N, eps, n, e, e / eps))
+        worst = max(worst, e)
     assert worst <= C_TOL * eps
 
 
