@@ -39,6 +39,7 @@ PMC_PASSES = [
     "SQ_ACTIVE_INST_VMEM SQ_INSTS_VALU_FLOPS_FP64 GRBM_GUI_ACTIVE",
     "FETCH_SIZE", "WRITE_SIZE"]
 PMC_HEADLINE = "python3 bench.py --only headline --steps 2 --warmup 1 --no-cpu --no-direct"
+PMC_BATCHED = "python3 bench.py --only batched-kernels --steps 1"
 PMC_COPY = "python3 bench.py --only copy"
 
 
@@ -51,10 +52,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def kernel_counters(kernel):
-    """Counters per launch of `kernel` (the name up to its template
-    arguments) from the committed summary, or None if there is none or the
-    kernel sources changed since it was taken."""
+def kernel_counters(kernel, workload="headline"):
+    """Counters per launch of `kernel` on the headline (or the batched
+    workload's one-call batch) from the committed summary, or None if there is
+    none or the kernel sources changed since it was taken."""
     try:
         with open(COUNTER_FILE) as fh:
             t = json.load(fh)
@@ -62,7 +63,7 @@ def kernel_counters(kernel):
         return None
     if t.get("source_hash") != kernel_source_hash():
         return None
-    return t.get("kernels", {}).get(kernel)
+    return t.get("kernels" if workload == "headline" else "kernels_batched", {}).get(kernel)
 
 
 def measured_traffic(kernel):
@@ -99,6 +100,8 @@ def write_counters(pmc_dir):
         return acc
 
     runs = {i: per_kernel(os.path.join(pmc_dir, "p%d" % i, "p_counter_collection.csv")) for i in range(1, 9)}
+    p9 = os.path.join(pmc_dir, "p9", "p_counter_collection.csv")  # FP64 counters of the batched workload
+    batched = per_kernel(p9) if os.path.exists(p9) else {}
 
     def copy_kib(i, counter):
         return max(sum(v[counter]) / len(v[counter]) for v in runs[i].values() if counter in v)
@@ -113,7 +116,9 @@ def write_counters(pmc_dir):
             k = kernels.setdefault(name, {})
             for cn, v in cs.items():
                 k[cn] = sum(v) / len(v)
-    for k in kernels.values():
+    kernels_b = {name: {cn: sum(v) / len(v) for cn, v in cs.items()} for name, cs in batched.items()
+                 if name.startswith("k_")}
+    for k in list(kernels.values()) + list(kernels_b.values()):
         if "FETCH_SIZE" in k and "WRITE_SIZE" in k:
             k["hbm_bytes"] = 1024.0 * (k["FETCH_SIZE"] * fscale + k["WRITE_SIZE"] * wscale)
         if "SQ_INSTS_VALU_FMA_F64" in k:
@@ -127,9 +132,13 @@ def write_counters(pmc_dir):
             for i, c in enumerate(PMC_PASSES)]
     cmds += ["cd /tmp && rocprofv3 --pmc %s --output-format csv -d <dir>/p%d -o p -- %s" % (c, i + 7, PMC_COPY)
              for i, c in enumerate(["FETCH_SIZE", "WRITE_SIZE"])]
+    if batched:
+        cmds.append("cd /tmp && rocprofv3 --pmc %s --output-format csv -d <dir>/p9 -o p -- %s" %
+                    (PMC_PASSES[2], PMC_BATCHED))
     out = {"source_hash": kernel_source_hash(), "fetch_scale": fscale, "write_scale": wscale,
-           "workload": "the headline: dht0 N=2^20 eps=1e-8, every far transform in FP64",
-           "commands": cmds, "kernels": kernels}
+           "workload": "the headline: dht0 N=2^20 eps=1e-8, every far transform in FP64; kernels_batched: "
+                       "the batched workload's one-call batch (1024 requests)",
+           "commands": cmds, "kernels": kernels, "kernels_batched": kernels_b}
     with open(COUNTER_FILE, "w") as fh:
         json.dump(out, fh, indent=1, sort_keys=True)
     return out
@@ -155,7 +164,8 @@ def parse():
     ap.add_argument("--serve-low-seconds", type=float, default=20.0,
                     help="arrival window of the second serving trace, at 0.8 x the plain form's capacity (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--only", choices=["all", "headline", "batched", "serve", "copy", "ablation", "configs"],
+    ap.add_argument("--only", choices=["all", "headline", "batched", "batched-kernels", "serve", "copy", "ablation",
+                                       "configs"],
                     default="all")
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the other workloads (configs block)")
@@ -178,8 +188,13 @@ def run_batched(hank, inputs, torch, count, stages=8):
     tuned = hank.autotune()
     specs = inputs.batch_specs(count)
     with concurrent.futures.ThreadPoolExecutor(16) as ex:  # host planning only
-        model_s = list(ex.map(lambda sp: hank.plan_info(sp["task"], sp["N"], sp["eps"], nrhs=sp["nrhs"])["model_s"],
-                              specs))
+        infos = list(ex.map(lambda sp: hank.plan_info(sp["task"], sp["N"], sp["eps"], nrhs=sp["nrhs"]), specs))
+    model_s = [pi["model_s"] for pi in infos]
+    # nominal FP64 work of the multi-right-hand-side near kernel: one J_0 per
+    # entry, shared by the right-hand sides, and one multiply-add (2 flops)
+    # per entry and right-hand side (requests of up to 3 run as single ones)
+    multi_nominal = sum(pi["near_entries"] * (NEAR_FLOPS_PER_ENTRY + 2.0 * sp["nrhs"])
+                        for sp, pi in zip(specs, infos) if sp["nrhs"] > SINGLE_RHS_MAX)
     reqs = []
     for sp, m in zip(specs, model_s):
         g = torch.Generator(device="cuda").manual_seed(sp["seed"])
@@ -228,6 +243,26 @@ def run_batched(hank, inputs, torch, count, stages=8):
         lat_st = sorted(done[k] for k in range(stages) for _ in range(bounds[k + 1] - bounds[k]))
         ts_st.append(done[-1] / 1e3)
     tst = sorted(ts_st)[len(ts_st) // 2]
+    # kernel times of one whole-batch call (HIP events around every launch)
+    hank.profile(True)
+    hank.batch(reqs)
+    torch.cuda.synchronize()
+    kst = hank.profile_report()
+    hank.profile(False)
+    kernels = {k["name"]: {"launches": k["launches"], "ms": k["total_ms"]} for k in kst}
+    nm = [k for k in kst if k["name"] == "near_multi"]
+    multi_roofline = None
+    if nm and nm[0]["total_ms"] > 0:
+        kc = kernel_counters("k_near_multi", "batched")
+        counted = bool(kc and "fp64_flops" in kc)
+        # FP64 operations of the launch: counted on this workload when the
+        # counter summary matches the sources, else the nominal count
+        flops = kc["fp64_flops"] if counted else multi_nominal
+        ach = flops / (nm[0]["total_ms"] * 1e-3) / 1e12
+        multi_roofline = {"kernel": "near_multi", "bound": "alu", "achieved": ach, "peak": FP64_VECTOR_TFLOPS,
+                          "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_TFLOPS,
+                          "flops_basis": "rocprofv3 FP64 VALU and MFMA counts" if counted else
+                          "nominal: 60 per entry (J_0) + 2 per entry and right-hand side"}
     # one request at a time in the same order, completion stamped per call
     for i in order:
         hank.transform(reqs[i]["task"], reqs[i]["c"], reqs[i]["eps"], out=reqs[i]["out"])
@@ -254,7 +289,8 @@ def run_batched(hank, inputs, torch, count, stages=8):
             "batched_latency_p50_ms": quantile(lat_st, 0.5), "batched_latency_p99_ms": quantile(lat_st, 0.99),
             "sequential_transforms_per_s": count / ts, "sequential_ms": ts * 1e3,
             "sequential_latency_p50_ms": quantile(lat, 0.5), "sequential_latency_p99_ms": quantile(lat, 0.99),
-            "speedup": ts / tst, "first_call_incl_planning_s": warm_s}
+            "speedup": ts / tst, "first_call_incl_planning_s": warm_s,
+            "one_call_kernels": kernels, "near_multi_roofline": multi_roofline}
 
 
 def _median_ms(hank, torch, task, c, eps, out, reps, **kw):
@@ -593,6 +629,19 @@ def main():
     if args.only == "copy":
         print(json.dumps(run_copy(torch)))
         return
+    if args.only == "batched-kernels":  # the batched workload's one-call batch, for profilers
+        specs = inputs.batch_specs(args.batch_count)
+        reqs = []
+        for sp in specs:
+            g = torch.Generator(device="cuda").manual_seed(sp["seed"])
+            shape = (sp["nrhs"], sp["N"]) if sp["nrhs"] > 1 else (sp["N"],)
+            c = torch.rand(shape, generator=g, dtype=torch.float64, device="cuda") * 2.0 - 1.0
+            reqs.append({"task": sp["task"], "c": c, "out": torch.empty_like(c), "eps": sp["eps"]})
+        for _ in range(1 + args.steps):
+            hank.batch(reqs)
+        torch.cuda.synchronize()
+        print(json.dumps({"batches": 1 + args.steps, "requests": len(reqs)}))
+        return
     if args.only == "configs":
         print(json.dumps({"configs": run_configs()}))
         return
@@ -800,8 +849,11 @@ def main():
     print(json.dumps(line))
 
 
-# operation count charged per near-field entry
+# operation count charged per near-field entry: one J_0 evaluation of the
+# asymptotic or series form (about 60 FP64 operations) and the multiply-add
 NEAR_FLOPS_PER_ENTRY = 60.0
+# requests with up to this many right-hand sides run as single transforms
+SINGLE_RHS_MAX = 3
 
 if __name__ == "__main__":
     main()

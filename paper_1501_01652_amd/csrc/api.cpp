@@ -296,6 +296,7 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
     const Grid& g = p.g;
     const int64_t N = g.N;
     dp.G = grid_args(g);
+    dp.G.lean = (!p.direct && p.eps >= 1e-9) ? 1 : 0; // near budget eps/8 >= 1.25e-10
     hank_status st;
     if (g.col_pert || g.row_pert) {
         if ((st = dev_alloc(dp.b, size_t(N + 1), dp.bytes))) return st;
@@ -439,6 +440,14 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
 
 // Right-hand sides a plan is balanced for: nrhs rounded up to a power of two
 // (at most 64); plans are cached per bucket.
+// Right-hand sides a plan is made for: 1 for order nu > 0 (its near field
+// sums one right-hand side at a time) and for up to three right-hand sides,
+// which run as that many single transforms (measured: 2 right-hand sides
+// 22-27% faster that way than on the several-right-hand-side MFMA kernel, 3
+// about equal, 4 or more slower).
+constexpr int64_t SINGLE_RHS_MAX = 3;
+int64_t plan_nrhs(int64_t nrhs, int nu) { return (nu > 0 || nrhs <= SINGLE_RHS_MAX) ? 1 : nrhs; }
+
 int64_t rhs_bucket(int64_t nrhs) {
     int64_t b = 1;
     while (b < nrhs && b < 64) b *= 2;
@@ -451,7 +460,7 @@ Key plan_key(int task, int64_t N, double eps, const hank_options* o, int dev, in
     uint64_t eb;
     std::memcpy(&eb, &eps, 8);
     int M = o ? o->M : 0, nu = o ? o->nu : 0, shift = o ? o->shift : 0;
-    if (nu > 0) nrhs = 1; // order nu > 0 sums one right-hand side at a time
+    nrhs = plan_nrhs(nrhs, nu);
     return Key{task, N, eb, mode + 4 * M + 128 * (nu + 16 * shift), prec,
                (direct * 2 + far) * 128 + int(rhs_bucket(nrhs)), dev};
 }
@@ -476,7 +485,7 @@ hank_status get_plan(int task, int64_t N, double eps, const hank_options* o, hip
     try {
         dp->plan = prebuilt ? *prebuilt
                             : make_plan(task, N, eps, mode, prec, direct != 0, cost_model_for(o),
-                                        rhs_bucket(o && o->nu > 0 ? 1 : nrhs), o ? o->M : 0, o ? o->nu : 0,
+                                        rhs_bucket(plan_nrhs(nrhs, o ? o->nu : 0)), o ? o->M : 0, o ? o->nu : 0,
                                         o ? o->shift : 0);
     } catch (const std::exception& ex) {
         return fail(HANK_EINVAL, std::string("planning failed: ") + ex.what());
@@ -658,7 +667,7 @@ void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR, size_t budget =
     // (order nu > 0: one right-hand side per job)
     std::vector<Job> jobs;
     for (const Job& J : jobs_in) {
-        const int64_t w = J.dp->plan.g.nu > 0 ? 1 : 64;
+        const int64_t w = plan_nrhs(J.nrhs, J.dp->plan.g.nu) == 1 ? 1 : 64;
         for (int64_t j0 = 0; j0 < J.nrhs; j0 += w) {
             Job P = J;
             P.c = J.c + j0 * J.ldc;
@@ -1128,7 +1137,7 @@ struct hank_server {
             std::string msg;
             try {
                 np->plan = make_plan(req.task, req.N, req.eps, 0, req.precision, false, cost_model_for(&o),
-                                     rhs_bucket(req.nu > 0 ? 1 : req.nrhs), 0, req.nu, req.shift);
+                                     rhs_bucket(plan_nrhs(req.nrhs, req.nu)), 0, req.nu, req.shift);
             } catch (const std::exception& ex) {
                 st = HANK_EINVAL;
                 msg = std::string("planning failed: ") + ex.what();
@@ -1549,7 +1558,7 @@ static hank_status batch_jobs(const hank_request* reqs, int64_t count, hipStream
                 o.shift = r.shift;
                 try {
                     todo[t]->second.second = make_plan(r.task, r.N, r.eps, 0, r.precision, false, cost_model_for(&o),
-                                                       rhs_bucket(r.nu > 0 ? 1 : r.nrhs), 0, r.nu, r.shift);
+                                                       rhs_bucket(plan_nrhs(r.nrhs, r.nu)), 0, r.nu, r.shift);
                 } catch (...) {
                     bad = true;
                 }
@@ -1916,7 +1925,7 @@ static hank_status host_plan(int32_t task, int64_t N, double eps, const hank_opt
     if (!valid_task(task)) return fail(HANK_EINVAL, "unknown task");
     try {
         p = make_plan(task, N, eps, o ? o->plan_mode : 0, o ? o->precision : 0, o && o->direct,
-                      cost_model_for(o), rhs_bucket(o && o->nrhs > 1 && o->nu == 0 ? o->nrhs : 1), o ? o->M : 0,
+                      cost_model_for(o), rhs_bucket(plan_nrhs(o && o->nrhs > 1 ? o->nrhs : 1, o ? o->nu : 0)), o ? o->M : 0,
                       o ? o->nu : 0, o ? o->shift : 0);
     } catch (const std::exception& ex) {
         return fail(HANK_EINVAL, ex.what());

@@ -22,6 +22,7 @@ struct GridArgs {
     int64_t ar, br, ac, bc, D, Dr, Qc;
     double pi_Qc, piD_hi, piD_lo, invD, invQc;
     int32_t row_pert, col_pert;
+    int32_t lean, pad; // lean: the near field's per-entry budget is at least 1.25e-10 (eps >= 1e-9)
 };
 
 // columns of one near-field tile (its coefficients are staged in LDS)

@@ -158,9 +158,10 @@ __global__ void k_j0(const double* z, int64_t n, double* out) {
 struct Hankel0 {
     double p[12], q[12];
 };
-constexpr Hankel0 make_hankel0() {
+// coefficients of P_0 and Q_0 (Sec. 3.1), times `scale`
+constexpr Hankel0 make_hankel0(double scale = 1.0) {
     Hankel0 h{};
-    double a = 1.0;
+    double a = scale;
     for (int m = 0; m < 24; ++m) {
         if (m > 0) a *= -double(2 * m - 1) * double(2 * m - 1) / (8.0 * m);
         const double sg = ((m / 2) & 1) ? -1.0 : 1.0;
@@ -172,19 +173,27 @@ constexpr Hankel0 make_hankel0() {
     return h;
 }
 
-// z^{-1/2} to full precision: hardware estimate and two Newton steps
-__device__ __forceinline__ double rsqrt_full(double z) {
+// z^{-1/2}: hardware estimate and Newton steps, two to full precision; one
+// when lean (the estimate's relative error is about 2^-23, one step leaves
+// about 1e-14)
+__device__ __forceinline__ double rsqrt_nr(double z, bool lean) {
     double y = __builtin_amdgcn_rsq(z);
-    double h = 0.5 * z;
+    const double h = 0.5 * z;
     y = y * fma(-h * y, y, 1.5);
-    y = y * fma(-h * y, y, 1.5);
+    if (!lean) y = y * fma(-h * y, y, 1.5);
     return y;
 }
+__device__ __forceinline__ double rsqrt_full(double z) { return rsqrt_nr(z, false); }
 
 // sin and cos of a residual phase |x| < 0.06 (Taylor; the first omitted terms
-// are below 1e-17)
-__device__ __forceinline__ void sincos_tiny(double x, double* s, double* c) {
+// are below 1e-17; lean, the series to x^5 and x^4: below 6.5e-11)
+__device__ __forceinline__ void sincos_tiny(double x, double* s, double* c, bool lean = false) {
     const double x2 = x * x;
+    if (lean) {
+        *s = x * fma(x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), 1.0);
+        *c = fma(x2, fma(x2, 1.0 / 24.0, -0.5), 1.0);
+        return;
+    }
     *s = x * fma(x2, fma(x2, fma(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
     *c = fma(x2, fma(x2, fma(x2, fma(x2, 1.0 / 40320.0, -1.0 / 720.0), 1.0 / 24.0), -0.5), 1.0);
 }
@@ -264,12 +273,14 @@ __device__ __forceinline__ void near_skip16(NearLane& r) {
 // Hankel expansion (Sec. 3.1, M pairs of terms) at the lane's current column;
 // bn = b_n (0 without column perturbations).  z only sets the amplitude and
 // the P, Q series, so it is formed to working precision.
-template <int M, bool PERT>
+// LEAN (the plan's G.lean: per-entry budget of at least 1.25e-10): one Newton
+// step for z^{-1/2} and the shorter residual sine and cosine.
+template <int M, bool PERT, bool LEAN = false>
 __device__ __forceinline__ double near_asy(const GridArgs& G, const NearLane& r, double bn) {
-    constexpr Hankel0 H = make_hankel0();
+    constexpr Hankel0 H = make_hankel0(0.79788456080286535588); // sqrt(2/pi) folded in
     const double delta = PERT ? fma(r.ek, fma(r.Nd, G.pi_Qc, bn), r.rk * bn) : 0.0;
     const double z = fma(r.Kd * r.Nd, G.piD_hi, delta);
-    const double y = rsqrt_full(z), zi = y * y, zi2 = zi * zi;
+    const double y = rsqrt_nr(z, LEAN), zi = y * y, zi2 = zi * zi;
     double P = H.p[M - 1], Q = H.q[M - 1];
 #pragma unroll
     for (int m = M - 2; m >= 0; --m) {
@@ -279,11 +290,11 @@ __device__ __forceinline__ double near_asy(const GridArgs& G, const NearLane& r,
     double cs = r.u.x, sn = r.u.y;
     if (PERT) {
         double s, c;
-        sincos_tiny(r.sk * bn, &s, &c);
+        sincos_tiny(r.sk * bn, &s, &c, LEAN);
         cs = fma(r.u.x, c, -r.u.y * s);
         sn = fma(r.u.y, c, r.u.x * s);
     }
-    return (0.79788456080286535588 * y) * fma(cs, P, -sn * (Q * zi)); // sqrt(2/pi)
+    return y * fma(cs, P, -sn * (Q * zi));
 }
 
 // z at the lane's current column with pi K N / D carried in two parts (the
@@ -298,7 +309,7 @@ __device__ __forceinline__ double near_z_exact(const GridArgs& G, const NearLane
 // J_0 at the lane's current column, then one step on
 // (both branches: each lane takes its own, so a wave pays for both only where
 // its rows straddle z = 20)
-template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG>
+template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG, bool LEAN = false>
 __device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, double bn) {
     double J;
     if (SMALL && ASY) {
@@ -306,11 +317,11 @@ __device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, doub
         if (z < J0_ASY_Z)
             J = j0_small<NT>(z);
         else
-            J = near_asy<M, PERT>(G, r, bn);
+            J = near_asy<M, PERT, LEAN>(G, r, bn);
     } else if (SMALL) {
         J = j0_small<NT>(near_z_exact(G, r, bn));
     } else {
-        J = near_asy<M, PERT>(G, r, bn);
+        J = near_asy<M, PERT, LEAN>(G, r, bn);
     }
     if (ASY) r.u = cmul(r.u, r.w);
     r.Nd += r.dNd;
@@ -344,13 +355,13 @@ __device__ __forceinline__ int tile_block_variant(const uint32_t* bv, int64_t n0
 }
 
 // One 64-column block of a sweep: the lane's columns p[0], p[4], ... (cnt of them)
-template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG>
+template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG, bool LEAN = false>
 __device__ __forceinline__ void near_block(const GridArgs& G, const ColCB* p, int cnt, NearLane& r, double& acc) {
     if (ASY) near_anchor(G, r);
     HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
     for (int i = 0; i < cnt; ++i) {
         const ColCB v = p[4 * i];
-        acc = fma(v.c, near_step<M, SMALL, ASY, PERT, NT>(G, r, PERT ? v.b : 0.0), acc);
+        acc = fma(v.c, near_step<M, SMALL, ASY, PERT, NT, LEAN>(G, r, PERT ? v.b : 0.0), acc);
     }
 }
 
@@ -358,7 +369,7 @@ __device__ __forceinline__ void near_block(const GridArgs& G, const ColCB* p, in
 // column is n: columns n, n+4, ... < T.n1, 16 per block of 64, coefficients
 // and root offsets read from LDS (cb[i] is column T.n0 + i).  The variant is
 // chosen per block (wave-uniform).
-template <bool PERT>
+template <bool PERT, bool LEAN>
 __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb, const uint32_t* bv,
                                              const NearTile& T, int64_t n, NearLane& r) {
     double acc = 0.0;
@@ -366,8 +377,8 @@ __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb,
         const int64_t nw = n + (nb - T.n0);
         const int cnt = (int)min<int64_t>(16, (T.n1 - nw + 3) / 4);
         const ColCB* p = cb + (nw - T.n0);
-#define BLOCK(M_, S_, A_) near_block<M_, S_, A_, PERT>(G, p, cnt, r, acc); break
-#define BLOCK8(M_, A_) near_block<M_, true, A_, PERT, 8>(G, p, cnt, r, acc); break
+#define BLOCK(M_, S_, A_) near_block<M_, S_, A_, PERT, J0_TAYLOR_DEG, LEAN>(G, p, cnt, r, acc); break
+#define BLOCK8(M_, A_) near_block<M_, true, A_, PERT, 8, LEAN>(G, p, cnt, r, acc); break
         switch (tile_block_variant(bv, T.n0, nb)) {
         case NV_SMALL: BLOCK(3, true, false);
         case NV_MIX12: BLOCK(12, true, true);
@@ -423,7 +434,10 @@ void k_near(const NearProb* __restrict__ probs, int nprob, double* __restrict__ 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t n = T.n0 + wave;
     NearLane R = near_lane(G, evec, T, lane, n);
-    const double acc = G.col_pert ? near_sweep<true>(G, cb, sbv, T, n, R) : near_sweep<false>(G, cb, sbv, T, n, R);
+    const double acc = G.col_pert ? (G.lean ? near_sweep<true, true>(G, cb, sbv, T, n, R)
+                                            : near_sweep<true, false>(G, cb, sbv, T, n, R))
+                                  : (G.lean ? near_sweep<false, true>(G, cb, sbv, T, n, R)
+                                            : near_sweep<false, false>(G, cb, sbv, T, n, R));
     red[wave][lane] = R.active ? acc : 0.0;
     __syncthreads();
     if (wave == 0) {
