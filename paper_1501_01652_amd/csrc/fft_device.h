@@ -5,7 +5,9 @@
 // holds the R points x[tt + r*NT], r < R, before and after the call (natural
 // order both ways).  SIGN = -1 is the forward DFT X_m = sum_j x_j e^{-2 pi i jm/LEN},
 // SIGN = +1 the unnormalised inverse.  Every stage is one radix butterfly per
-// register group, one LDS write and one LDS read; `sh` must hold
+// register group, one LDS write and one LDS read, except the last, which
+// leaves its outputs in the registers that hold them (its exchange would be
+// the identity); `sh` must hold
 // LEN + LEN/8 elements for this transform and every thread of the workgroup
 // must call the function (it synchronises the workgroup).
 #pragma once
@@ -120,7 +122,12 @@ __device__ __forceinline__ void wave_sync() {
 // WAVE: the LEN/R threads of the transform are one wave (LEN = 64 R), whose
 // exchanges need no workgroup barrier; its LDS slots are lds_swz(i) (LEN
 // elements), otherwise lds_pad(i) (LEN + LEN/8).
-template <typename F, int LEN, int R, int RS, int SIGN, bool WAVE = false>
+// LAST: the final stage (Ns * RS = LEN).  Its butterfly q of thread tt
+// produces the outputs tt + (q + s NB) NT -- exactly the positions that thread
+// holds in registers v[q + s NB] afterwards -- so its LDS exchange is the
+// identity and is skipped (the previous stage's synchronisation already
+// orders every earlier LDS access before the caller's next one).
+template <typename F, int LEN, int R, int RS, int SIGN, bool WAVE = false, bool LAST = false>
 __device__ __forceinline__ void fft_stage(cx<F> (&v)[R], cx<F>* sh, int tt, int Ns, const double (*tw)[2]) {
     constexpr int NT = LEN / R;
     constexpr int NB = R / RS;
@@ -151,10 +158,16 @@ __device__ __forceinline__ void fft_stage(cx<F> (&v)[R], cx<F>* sh, int tt, int 
 #endif
         }
         dft_small<F, RS, SIGN>(a);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int s = 0; s < RS; ++s) v[q + s * NB] = a[s];
+            continue;
+        }
         const int base = (j - kk) * RS + kk;
 #pragma unroll
         for (int s = 0; s < RS; ++s) sh[slot(base + s * Ns)] = a[s];
     }
+    if constexpr (LAST) return;
     if constexpr (WAVE) wave_sync(); else __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = sh[slot(tt + r * NT)];
@@ -175,13 +188,22 @@ __device__ __forceinline__ void fft_reg(cx<F> (&v)[R], cx<F>* sh, int tt) {
     constexpr int LG = ilog2<LEN>::v, LR = ilog2<R>::v;
     static_assert((1 << LG) == LEN && (1 << LR) == R && LEN >= R, "power-of-two sizes");
     static_assert(!WAVE || LEN == 64 * R, "a wave-local transform has one point set per lane");
+    constexpr int NST = LG / LR; // full-radix stages
     int Ns = 1;
 #pragma unroll
-    for (int st = 0; st < LG / LR; ++st) {
+    for (int st = 0; st < NST - 1; ++st) {
         fft_stage<F, LEN, R, R, SIGN, WAVE>(v, sh, tt, Ns, opaque_tw());
         Ns *= R;
     }
-    if constexpr (LG % LR != 0) fft_stage<F, LEN, R, (1 << (LG % LR)), SIGN, WAVE>(v, sh, tt, Ns, opaque_tw());
+    if constexpr (LG % LR != 0) {
+        if constexpr (NST > 0) {
+            fft_stage<F, LEN, R, R, SIGN, WAVE>(v, sh, tt, Ns, opaque_tw());
+            Ns *= R;
+        }
+        fft_stage<F, LEN, R, (1 << (LG % LR)), SIGN, WAVE, true>(v, sh, tt, Ns, opaque_tw());
+    } else {
+        fft_stage<F, LEN, R, R, SIGN, WAVE, true>(v, sh, tt, Ns, opaque_tw());
+    }
 }
 
 // e^{-2 pi i e / L} for 0 <= e < L, L = 2^lg <= 2^23, from the two-level table
