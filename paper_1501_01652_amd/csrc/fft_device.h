@@ -61,9 +61,18 @@ __device__ __forceinline__ cx<F> mul_si(cx<F> a) { // a * (SIGN i)
     return SIGN < 0 ? mk(a.y, -a.x) : mk(-a.y, a.x);
 }
 
-template <typename F, int RS, int SIGN>
+// HALF: a[RS/2 ..] are known to be zero (RS = 4, 8)
+template <typename F, int RS, int SIGN, bool HALF = false>
 __device__ __forceinline__ void dft_small(cx<F> (&a)[RS]) {
-    if constexpr (RS == 2) {
+    static_assert(!HALF || RS >= 4, "half-zero inputs for radix 4 and 8");
+    if constexpr (RS == 4 && HALF) {
+        const cx<F> t = mul_si<F, SIGN>(a[1]);
+        const cx<F> a0 = a[0], a1 = a[1];
+        a[0] = a0 + a1;
+        a[1] = a0 + t;
+        a[2] = a0 - a1;
+        a[3] = a0 - t;
+    } else if constexpr (RS == 2) {
         cx<F> t = a[0];
         a[0] = t + a[1];
         a[1] = t - a[1];
@@ -76,8 +85,8 @@ __device__ __forceinline__ void dft_small(cx<F> (&a)[RS]) {
     } else { // RS == 8: two DFT4 and the W8 twiddles
         const F c = F(0.70710678118654752440);
         cx<F> e[4] = {a[0], a[2], a[4], a[6]}, o[4] = {a[1], a[3], a[5], a[7]};
-        dft_small<F, 4, SIGN>(e);
-        dft_small<F, 4, SIGN>(o);
+        dft_small<F, 4, SIGN, HALF>(e);
+        dft_small<F, 4, SIGN, HALF>(o);
         cx<F> o1 = mk(c * (o[1].x - F(SIGN) * o[1].y), c * (F(SIGN) * o[1].x + o[1].y));
         cx<F> o2 = mul_si<F, SIGN>(o[2]);
         cx<F> o3 = mk(c * (-o[3].x - F(SIGN) * o[3].y), c * (F(SIGN) * o[3].x - o[3].y));
@@ -127,8 +136,10 @@ __device__ __forceinline__ void wave_sync() {
 // holds in registers v[q + s NB] afterwards -- so its LDS exchange is the
 // identity and is skipped (the previous stage's synchronisation already
 // orders every earlier LDS access before the caller's next one).
-template <typename F, int LEN, int R, int RS, int SIGN, bool WAVE = false, bool LAST = false>
+// HALFIN (first stage only, RS = R): the inputs v[R/2 ..] are zero.
+template <typename F, int LEN, int R, int RS, int SIGN, bool WAVE = false, bool LAST = false, bool HALFIN = false>
 __device__ __forceinline__ void fft_stage(cx<F> (&v)[R], cx<F>* sh, int tt, int Ns, const double (*tw)[2]) {
+    static_assert(!HALFIN || RS == R, "half-zero input in a full-radix first stage");
     constexpr int NT = LEN / R;
     constexpr int NB = R / RS;
     auto slot = [](int i) { return WAVE ? lds_swz(i) : lds_pad(i); };
@@ -157,7 +168,7 @@ __device__ __forceinline__ void fft_stage(cx<F> (&v)[R], cx<F>* sh, int tt, int 
             }
 #endif
         }
-        dft_small<F, RS, SIGN>(a);
+        dft_small<F, RS, SIGN, HALFIN>(a);
         if constexpr (LAST) {
 #pragma unroll
             for (int s = 0; s < RS; ++s) v[q + s * NB] = a[s];
@@ -183,16 +194,22 @@ struct ilog2<1> {
     static constexpr int v = 0;
 };
 
-template <typename F, int LEN, int R, int SIGN, bool WAVE = false>
+// HALFIN: the inputs x[LEN/2 ..] (registers v[R/2 ..]) are zero; needs
+// LEN >= R * R, so that the first stage is a full-radix one
+template <typename F, int LEN, int R, int SIGN, bool WAVE = false, bool HALFIN = false>
 __device__ __forceinline__ void fft_reg(cx<F> (&v)[R], cx<F>* sh, int tt) {
     constexpr int LG = ilog2<LEN>::v, LR = ilog2<R>::v;
     static_assert((1 << LG) == LEN && (1 << LR) == R && LEN >= R, "power-of-two sizes");
     static_assert(!WAVE || LEN == 64 * R, "a wave-local transform has one point set per lane");
     constexpr int NST = LG / LR; // full-radix stages
+    static_assert(!HALFIN || NST >= 2, "half-zero input: at least two full-radix stages");
     int Ns = 1;
 #pragma unroll
     for (int st = 0; st < NST - 1; ++st) {
-        fft_stage<F, LEN, R, R, SIGN, WAVE>(v, sh, tt, Ns, opaque_tw());
+        if (HALFIN && st == 0)
+            fft_stage<F, LEN, R, R, SIGN, WAVE, false, HALFIN>(v, sh, tt, Ns, opaque_tw());
+        else
+            fft_stage<F, LEN, R, R, SIGN, WAVE>(v, sh, tt, Ns, opaque_tw());
         Ns *= R;
     }
     if constexpr (LG % LR != 0) {

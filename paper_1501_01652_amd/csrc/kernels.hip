@@ -1232,30 +1232,101 @@ constexpr int wave_col_bufs() {
     return L2 <= 256 ? 2 : 1;
 }
 
+// Pass A for a block of at most L1 columns: only row 0 (n' = j1) of each
+// column input can be nonzero, so the column DFT is that value at every m2
+// and the output is it times the four-step twiddle e^{-2 pi i j1 m2 / L}: no
+// FFT and no LDS.  Thread t writes column jb + t % 8, rows t/8 + 64 r, as the
+// transposed stores of the general path do.
+template <typename F, int L2>
+__device__ __forceinline__ void pass_aw_row0(const FarDesc& D, const FarItem& mp, int64_t jb) {
+    constexpr int W = 8, R = L2 / 64;
+    const FarArgs& A = D.A;
+    const int t = threadIdx.x, cw = t % W, q = t / W;
+    const int64_t j1 = jb + cw;
+    const int ng = A.g1 - A.g0;
+    cx<F>* buf = (cx<F>*)D.buf;
+    const int j = mp.j;
+    double vw = 1.0, xb = 0.0, la = 0.0;
+    cx<double> qb = mk(0.0, 0.0);
+    if (j1 < A.ncols) {
+        const int64_t n = A.na + j1;
+        const int64_t Nn = A.ac * n + A.bc;
+        const double wn = (double)Nn * A.pi_Qc;
+        const double bn = A.col_pert ? D.b[n - 1] : 0.0;
+        vw = wn / A.w0;
+        const double iw = 1.0 / vw;
+        xb = (bn / A.bref) * iw;
+        la = (wn + bn) / A.lref;
+        qb = cscale(expi_ratio(2 * A.Kka * A.ac * j1 + A.ar * A.ac * j1 * j1, 2 * A.D),
+                    sqrt(iw) * D.c[(int64_t)j * D.ldc + n - 1]);
+    }
+    cx<F> tw[R];
+    {
+        cx<double> w = tw_big<double>(j1 * q, A.twshift);
+        const cx<double> ws = tw_big<double>(j1 * 64, A.twshift);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            tw[r] = mk(F(w.x), F(w.y));
+            if (r + 1 < R) w = cmul(w, ws);
+        }
+    }
+    const int gs = A.g0 + mp.chunk * D.gchunk, ge = min(A.g1, gs + D.gchunk);
+    int ecur = 0, acur = 0;
+    double pw = 1.0;
+    for (int g = gs; g < ge; ++g) {
+        const GroupDev Gd = scalar_entry(A.groups, g);
+        if (Gd.a != acur || g == gs) {
+            pw = ipow_d<double>(vw, Gd.e) * (Gd.a ? ipow_d<double>(la, Gd.a) : 1.0);
+        } else {
+            for (; ecur < Gd.e; ++ecur) pw *= vw;
+            for (; ecur > Gd.e; --ecur) pw /= vw;
+        }
+        ecur = Gd.e;
+        acur = Gd.a;
+        double xp = 1.0, Xr = 0.0, Xi = 0.0;
+        int bcur = 0;
+        for (int ti = Gd.t0; ti < Gd.t1; ++ti) {
+            const TermDev Td = scalar_entry(A.terms, ti);
+            while (bcur < Td.b) {
+                xp *= xb;
+                ++bcur;
+            }
+            Xr = fma(Td.kre, xp, Xr);
+            Xi = fma(Td.kim, xp, Xi);
+        }
+        const cx<double> y = cmul(mk(Xr * pw, Xi * pw), qb);
+        const cx<F> yf = mk(F(y.x), F(y.y));
+        cx<F>* out = buf + ((int64_t)j * ng + (g - A.g0)) * A.L + jb + cw;
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[(int64_t)(q + 64 * r) * A.L1] = cmul(yf, tw[r]);
+    }
+}
+
 // Pass A: the inputs of the lane's positions n' = j1 + L1 (lane + 64 r) of the
 // wave's column j1 for every group (as k_pass_a), the column FFT, the
 // four-step twiddle, and through LDS to buf[m2][j1].
-template <typename F, int L2>
-__global__ __launch_bounds__(512) HANK_WAVE_COLS_WPE void k_pass_aw(const FarDesc* __restrict__ descs, int ndesc) {
+// HALF: every position n' >= jb + L/2 is past the block's columns, so the
+// lane's registers r >= R/2 hold zeros (not formed; the FFT's first stage
+// knows them).
+template <typename F, int L2, bool HALF>
+__device__ __forceinline__ void pass_aw_main(const FarDesc& D, const FarItem& mp, int64_t jb,
+                                             cx<F> (*sh)[8 * wave_col_stride<L2>()]) {
     constexpr int W = 8, R = L2 / 64, S = wave_col_stride<L2>(), NB = wave_col_bufs<L2>();
-    __shared__ cx<F> sh[NB][W * S];
-    const FarItem mp = far_item(descs, ndesc, 0, descs[0].A.L1 / W);
-    const FarDesc& D = descs[mp.desc];
+    constexpr int RH = HALF ? R / 2 : R; // registers that can be nonzero
     const FarArgs& A = D.A;
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int cw = t % W, q = t / W;
-    const int64_t jb = (int64_t)mp.wg * W, j1 = jb + wv;
-    if (jb >= A.ncols) return; // columns past the block: zero input, not stored
+    const int64_t j1 = jb + wv;
     const int ng = A.g1 - A.g0;
     cx<F>* buf = (cx<F>*)D.buf;
 
-    double vw[R], xb[R], la[R], pw[R];
-    cx<double> qb[R]; // q(n') c_n (w^_n/w0)^(-1/2); zero past the block's columns
+    double vw[RH], xb[RH], la[RH], pw[RH];
+    cx<double> qb[RH]; // q(n') c_n (w^_n/w0)^(-1/2); zero past the block's columns
     const int j = mp.j;
     const double* cj = D.c + (int64_t)j * D.ldc;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
+    for (int r = 0; r < RH; ++r) {
         const int64_t np = j1 + (int64_t)A.L1 * (lane + 64 * r);
         vw[r] = 1.0;
         xb[r] = la[r] = 0.0;
@@ -1281,23 +1352,25 @@ __global__ __launch_bounds__(512) HANK_WAVE_COLS_WPE void k_pass_aw(const FarDes
         const GroupDev Gd = scalar_entry(A.groups, g);
         if (Gd.a != acur || g == gs) {
 #pragma unroll
-            for (int r = 0; r < R; ++r)
+            for (int r = 0; r < RH; ++r)
                 pw[r] = ipow_d<double>(vw[r], Gd.e) * (Gd.a ? ipow_d<double>(la[r], Gd.a) : 1.0);
         } else {
             for (; ecur < Gd.e; ++ecur) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) pw[r] *= vw[r];
+                for (int r = 0; r < RH; ++r) pw[r] *= vw[r];
             }
             for (; ecur > Gd.e; --ecur) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) pw[r] /= vw[r];
+                for (int r = 0; r < RH; ++r) pw[r] /= vw[r];
             }
         }
         ecur = Gd.e;
         acur = Gd.a;
         cx<F> v[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int r = RH; r < R; ++r) v[r] = mk(F(0), F(0));
+#pragma unroll
+        for (int r = 0; r < RH; ++r) {
             double xp = 1.0, Xr = 0.0, Xi = 0.0;
             int bcur = 0;
             for (int ti = Gd.t0; ti < Gd.t1; ++ti) {
@@ -1313,7 +1386,7 @@ __global__ __launch_bounds__(512) HANK_WAVE_COLS_WPE void k_pass_aw(const FarDes
             v[r] = mk(F(y.x), F(y.y));
         }
         cx<F>* my = &sh[b][wv * S];
-        fft_reg<F, L2, R, -1, true>(v, my, lane);
+        fft_reg<F, L2, R, -1, true, HALF>(v, my, lane);
         cx<double> tw = tw0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -1334,29 +1407,120 @@ __global__ __launch_bounds__(512) HANK_WAVE_COLS_WPE void k_pass_aw(const FarDes
     }
 }
 
+template <typename F, int L2>
+__global__ __launch_bounds__(512) HANK_WAVE_COLS_WPE void k_pass_aw(const FarDesc* __restrict__ descs, int ndesc) {
+    constexpr int W = 8, S = wave_col_stride<L2>(), NB = wave_col_bufs<L2>();
+    __shared__ cx<F> sh[NB][W * S];
+    const FarItem mp = far_item(descs, ndesc, 0, descs[0].A.L1 / W);
+    const FarDesc& D = descs[mp.desc];
+    const FarArgs& A = D.A;
+    const int64_t jb = (int64_t)mp.wg * W;
+    if (jb >= A.ncols) return; // columns past the block: zero input, not stored
+    // (uniform per workgroup)
+    if (A.ncols <= A.L1)
+        pass_aw_row0<F, L2>(D, mp, jb); // one input row
+    else if (A.ncols <= jb + A.L / 2)
+        pass_aw_main<F, L2, true>(D, mp, jb, sh);
+    else
+        pass_aw_main<F, L2, false>(D, mp, jb, sh);
+}
+
+// Pass C for a block of at most L1 rows: only row 0 (k' = j1) of each column
+// is an output, and row 0 of the inverse column DFT is the plain sum of the
+// column.  Thread t (column jb + t % 8, rows t/8 + 64 r) adds its values of
+// every group with the group's weight at k' = j1; the 64 threads of a column
+// are then summed in a fixed order, the 8 of each wave by lane shuffles and
+// the 8 waves through LDS (red: 64 complex values).
+template <typename F, int L2>
+__device__ __forceinline__ void pass_cw_row0(const FarDesc& D, const FarItem& mp, int64_t jb, cx<double>* red) {
+    constexpr int W = 8, R = L2 / 64;
+    const FarArgs& A = D.A;
+    const int t = threadIdx.x, cw = t % W, q = t / W;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int64_t kp = jb + cw;
+    const bool valid = kp < A.nrows;
+    const int ng = A.g1 - A.g0;
+    const cx<F>* buf = (const cx<F>*)D.buf;
+    const int j = mp.j;
+    double rho = 1.0, ek = 0.0;
+    if (valid) {
+        const int64_t k = A.ka + kp;
+        rho = ((double)(A.ar * k + A.br) / (double)A.Dr) / A.r0;
+        ek = A.row_pert ? D.e[k - 1] / A.eref : 0.0;
+    }
+    const int gs = A.g0 + mp.chunk * D.gchunk, ge = min(A.g1, gs + D.gchunk);
+    int ecur = 0, acur = 0;
+    double pw = 1.0;
+    cx<double> acc = mk(0.0, 0.0);
+    for (int g = gs; g < ge; ++g) {
+        const GroupDev Gd = scalar_entry(A.groups, g);
+        if (Gd.a != acur || g == gs) {
+            pw = ipow_d<double>(rho, Gd.e) * (Gd.a ? ipow_d<double>(ek, Gd.a) : 1.0);
+        } else {
+            for (; ecur < Gd.e; ++ecur) pw *= rho;
+            for (; ecur > Gd.e; --ecur) pw /= rho;
+        }
+        ecur = Gd.e;
+        acur = Gd.a;
+        if (valid) {
+            const cx<F>* p = buf + ((int64_t)j * ng + (g - A.g0)) * A.L + jb + cw;
+            double sx = 0.0, sy = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const cx<F> v = p[(int64_t)(q + 64 * r) * A.L1];
+                sx += (double)v.x;
+                sy += (double)v.y;
+            }
+            const double wgt = Gd.scale * pw;
+            acc.x = fma(wgt, sx, acc.x);
+            acc.y = fma(wgt, sy, acc.y);
+        }
+    }
+    // lanes cw + 8 i of a wave hold column cw: add over i (lane bits 3-5)
+#pragma unroll
+    for (int m = 8; m < 64; m <<= 1) {
+        acc.x += __shfl_xor(acc.x, m);
+        acc.y += __shfl_xor(acc.y, m);
+    }
+    if ((t & 63) < W) red[wv * W + cw] = acc;
+    __syncthreads();
+    if (t < W && valid) {
+        cx<double> tot = red[cw];
+#pragma unroll
+        for (int w = 1; w < 8; ++w) tot = tot + red[w * W + cw];
+        const cx<double> pk = cscale(
+            expi_ratio(2 * A.Kka * A.Nna + 2 * A.ar * A.Nna * kp + A.ar * A.ac * kp * kp, 2 * A.D), 1.0 / sqrt(rho));
+        const double val = pk.x * tot.x - pk.y * tot.y;
+        if (D.nchunk == 1)
+            D.f[(int64_t)j * D.ldo + A.ka - 1 + kp] += val;
+        else
+            D.part[((int64_t)j * D.nchunk + mp.chunk) * A.nrows + kp] = val;
+    }
+}
+
 // Pass C: buf[m2][j1] through LDS to the wave of column j1, the inverse column
 // FFT, and per output position k' = j1 + L1 (lane + 64 r) the complex sum
 // acc = sum_g A_g(k) conv_g(k') over the groups (A_g real, so that the post-
 // chirp p(k') is applied once at the end: f_k += Re(p(k') acc)).  The next
 // group's data are loaded while the current one is transformed.
-template <typename F, int L2>
-__global__ __launch_bounds__(512) HANK_WAVE_COLS_WPE void k_pass_cw(const FarDesc* __restrict__ descs, int ndesc) {
+// HALF: every output position k' >= jb + L/2 is past the block's rows, so
+// the lane's registers r >= R/2 are not used (nor, after the FFT, formed).
+template <typename F, int L2, bool HALF>
+__device__ __forceinline__ void pass_cw_main(const FarDesc& D, const FarItem& mp, int64_t jb,
+                                             cx<F> (*sh)[8 * wave_col_stride<L2>()]) {
     constexpr int W = 8, R = L2 / 64, S = wave_col_stride<L2>(), NB = wave_col_bufs<L2>();
-    __shared__ cx<F> sh[NB][W * S];
-    const FarItem mp = far_item(descs, ndesc, 0, descs[0].A.L1 / W);
-    const FarDesc& D = descs[mp.desc];
+    constexpr int RH = HALF ? R / 2 : R; // registers holding output rows
     const FarArgs& A = D.A;
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int cw = t % W, q = t / W;
-    const int64_t jb = (int64_t)mp.wg * W, j1 = jb + wv;
-    if (jb >= A.nrows) return; // columns holding no output row
+    const int64_t j1 = jb + wv;
     const int ng = A.g1 - A.g0;
     const cx<F>* buf = (const cx<F>*)D.buf;
-    double rho[R], ek[R], pw[R];
-    cx<double> acc[R];
+    double rho[RH], ek[RH], pw[RH];
+    cx<double> acc[RH];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
+    for (int r = 0; r < RH; ++r) {
         const int64_t kp = j1 + (int64_t)A.L1 * (lane + 64 * r);
         rho[r] = 1.0;
         ek[r] = 0.0;
@@ -1394,22 +1558,22 @@ __global__ __launch_bounds__(512) HANK_WAVE_COLS_WPE void k_pass_cw(const FarDes
         const GroupDev Gd = scalar_entry(A.groups, g);
         if (Gd.a != acur || g == gs) {
 #pragma unroll
-            for (int r = 0; r < R; ++r)
+            for (int r = 0; r < RH; ++r)
                 pw[r] = ipow_d<double>(rho[r], Gd.e) * (Gd.a ? ipow_d<double>(ek[r], Gd.a) : 1.0);
         } else {
             for (; ecur < Gd.e; ++ecur) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) pw[r] *= rho[r];
+                for (int r = 0; r < RH; ++r) pw[r] *= rho[r];
             }
             for (; ecur > Gd.e; --ecur) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) pw[r] /= rho[r];
+                for (int r = 0; r < RH; ++r) pw[r] /= rho[r];
             }
         }
         ecur = Gd.e;
         acur = Gd.a;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < RH; ++r) {
             const double wgt = Gd.scale * pw[r];
             acc[r].x = fma(wgt, (double)v[r].x, acc[r].x);
             acc[r].y = fma(wgt, (double)v[r].y, acc[r].y);
@@ -1422,7 +1586,7 @@ __global__ __launch_bounds__(512) HANK_WAVE_COLS_WPE void k_pass_cw(const FarDes
     double* fj = D.nchunk == 1 ? D.f + (int64_t)j * D.ldo + A.ka - 1
                                : D.part + ((int64_t)j * D.nchunk + mp.chunk) * A.nrows;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
+    for (int r = 0; r < RH; ++r) {
         const int64_t kp = j1 + (int64_t)A.L1 * (lane + 64 * r);
         if (kp < A.nrows) { // rows past the block are discarded
             const cx<double> pk = cscale(
@@ -1435,6 +1599,24 @@ __global__ __launch_bounds__(512) HANK_WAVE_COLS_WPE void k_pass_cw(const FarDes
                 fj[kp] = val;
         }
     }
+}
+
+template <typename F, int L2>
+__global__ __launch_bounds__(512) HANK_WAVE_COLS_WPE void k_pass_cw(const FarDesc* __restrict__ descs, int ndesc) {
+    constexpr int W = 8, S = wave_col_stride<L2>(), NB = wave_col_bufs<L2>();
+    __shared__ cx<F> sh[NB][W * S];
+    const FarItem mp = far_item(descs, ndesc, 0, descs[0].A.L1 / W);
+    const FarDesc& D = descs[mp.desc];
+    const FarArgs& A = D.A;
+    const int64_t jb = (int64_t)mp.wg * W;
+    if (jb >= A.nrows) return; // columns holding no output row
+    // (uniform per workgroup)
+    if (A.nrows <= A.L1)
+        pass_cw_row0<F, L2>(D, mp, jb, reinterpret_cast<cx<double>*>(&sh[0][0])); // one output row
+    else if (A.nrows <= jb + A.L / 2)
+        pass_cw_main<F, L2, true>(D, mp, jb, sh);
+    else
+        pass_cw_main<F, L2, false>(D, mp, jb, sh);
 }
 
 // ---------------------------------------------------------------------------
