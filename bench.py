@@ -43,6 +43,11 @@ PMC_BATCHED = "python3 bench.py --only batched-kernels --steps 1"
 PMC_COPY = "python3 bench.py --only copy"
 
 
+def note(msg):
+    """A progress line on stderr as each phase of the run ends."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -319,6 +324,7 @@ def run_ablation(hank, inputs, torch, task, N, eps, c_host, precision=1):
         part[name] = {"ms": ms, "points_per_s": N / (ms * 1e-3), "M": info["M"], "P": info["P"],
                       "blocks": info["nblocks"], "near_entries": info["near_entries"],
                       "far_transforms": info["far_transforms"], "fft_bytes": info["fft_bytes"]}
+        note("ablation: %s plan %.3f ms" % (name, ms))
     del c, out
     hank.cache_clear()
     Ns = 5000
@@ -334,6 +340,7 @@ def run_ablation(hank, inputs, torch, task, N, eps, c_host, precision=1):
         sweep["%g" % e] = {"ms_by_M": ms, "best_M": best, "table4_M": table4,
                            "table4_over_best": ms[table4] / ms[best],
                            "tuned_ms": _median_ms(hank, torch, "schlomilch", cs, e, outs, 5)}
+        note("ablation: M sweep at eps %g, best M %d" % (e, best))
     direct_ms = _median_ms(hank, torch, "schlomilch", cs, 1e-15, outs, 5, direct=1)
     hank.cache_clear()
     return {"partition": part,
@@ -457,10 +464,13 @@ def run_serving(hank, inputs, torch, seconds, rate, low_seconds):
                        "1 rhs, eps {1e-4,1e-8,1e-14}, seed %d" % (rate, seconds, inputs.SEED_SERVE),
            "requests": len(trace), "distinct_sizes": len({(t["task"], t["N"], t["eps"]) for t in trace})}
     res["startup"] = warm_partition_tables(hank, trace)
+    note("serving: %d requests, partition tables warmed" % len(trace))
     res["continuous_batching"] = run_serve(hank, inputs, torch, trace, c_all, outs)
     hank.cache_clear()
+    note("serving: continuous batching done")
     res["plain_sequential"] = run_plain(hank, torch, trace, c_all, outs)
     hank.cache_clear()
+    note("serving: plain sequential done")
     cap = res["plain_sequential"]["throughput"]
     if low_seconds > 0 and cap > 0:
         low_rate = 0.8 * cap
@@ -469,8 +479,10 @@ def run_serving(hank, inputs, torch, seconds, rate, low_seconds):
                                   "startup": warm_partition_tables(hank, low),
                                   "continuous_batching": run_serve(hank, inputs, torch, low, c_all, outs)}
         hank.cache_clear()
+        note("serving at 0.8 x capacity: continuous batching done")
         res["at_0.8_capacity"]["plain_sequential"] = run_plain(hank, torch, low, c_all, outs)
         hank.cache_clear()
+        note("serving at 0.8 x capacity: plain sequential done")
     del c_all, outs
     return res
 
@@ -567,6 +579,7 @@ def run_config(hank, inputs, torch, np, cpu, task, N, eps, precision, c_host, ro
         rec["error"]["rows_checked"] = int(len(rows))
         rec["cpu_oracle_rows_per_s"] = len(rows) / tcpu
     del c, out
+    note("config %s N=%d eps=%g %s: %.4f ms" % (task, N, eps, rec["precision"], rec["ms"]))
     return rec
 
 
@@ -593,6 +606,7 @@ def main():
     def run_extra():
         if args.only in ("all", "batched") and args.batch_count > 0:
             extra["batched"] = run_batched(hank, inputs, torch, args.batch_count)
+            note("batched workload done")
         if args.only in ("all", "serve") and args.serve_seconds > 0:
             extra["serving"] = run_serving(hank, inputs, torch, args.serve_seconds, args.serve_rate,
                                            args.serve_low_seconds)
@@ -656,6 +670,7 @@ def main():
     # timed region: K steps with events between steps only
     step_ms, elapsed, plan_s = step_times(hank, torch, task, c, eps, out, args.steps, args.warmup, **kw)
     f_head = out.cpu().numpy()
+    note("headline timed: %.4f ms per step" % (1e3 * elapsed / args.steps))
     # per-kernel durations: a second pass of K steps with HIP events around
     # every launch on the launch stream (kept out of the timed region above,
     # whose rate they would lower by about 4%)
@@ -756,6 +771,7 @@ def main():
         torch.cuda.synchronize()
         td = time.perf_counter() - t0
         direct = {"points_per_s": N / td, "ms": td * 1e3, "speedup_fast_vs_direct": value / (N / td)}
+        note("direct sum on the GPU: %.1f ms" % (td * 1e3))
 
     # the library's automatic precision choice on the same workload: FP64
     # bulk with the transforms whose contribution is small enough in FP32
@@ -768,6 +784,7 @@ def main():
                  "fp32_transforms": mi["fp32_transforms"], "far_transforms": mi["far_transforms"],
                  "near_entries": mi["near_entries"], "blocks": mi["nblocks"]}
         f_mixed = out.cpu().numpy()
+        note("automatic precision: %.4f ms" % mixed["ms"])
 
     inverse = None
     if task == "dht0" and args.only == "all":
@@ -789,6 +806,7 @@ def main():
                    "roundtrip_max_abs_err": float(torch.max(torch.abs(out - c)).item()),
                    "c_max_abs": float(torch.max(torch.abs(c)).item())}
         del back
+        note("inverse DHT: %.4f ms" % inv_ms)
 
     cpu_line = None
     head_err = None
@@ -817,6 +835,7 @@ def main():
         # the same rows measure the error of the timed results
         head_err = error_stats(np, f_head[rows - 1], ref, c_host, eps)
         head_err["rows_checked"] = int(nrows)
+        note("oracle baseline: %d rows in %.1f s" % (nrows, tc))
         if mixed is not None:
             mixed["error"] = error_stats(np, f_mixed[rows - 1], ref, c_host, eps)
             mixed["error"]["rows_checked"] = int(nrows)
@@ -844,6 +863,7 @@ def main():
         line["configs"] = run_configs()
     if args.only == "all" and not args.no_ablation:
         line["ablation"] = run_ablation(hank, inputs, torch, task, N, eps, c_host, precision=args.precision)
+        note("ablation done")
     run_extra()
     line.update(extra)
     print(json.dumps(line))
