@@ -262,6 +262,7 @@ struct NearRule {
     double zM[6]; // s_{0,M} for M = 2, 3, 4, 6, 8, 12
     bool mix6;    // 6 pairs suffice at z = 20
     bool small8;  // 8 terms of the small-argument pieces suffice (budget >= 1.25e-9)
+    double rho1;  // residual phases up to this take the first-order factor (NV_*R)
 };
 
 NearRule near_rule(const Plan& p) {
@@ -271,7 +272,23 @@ NearRule near_rule(const Plan& p) {
     for (int i = 0; i < 6; ++i) r.zM[i] = param_s(0, Ms[i], e);
     r.mix6 = r.zM[3] <= J0_ASY_Z;
     r.small8 = e >= 1.25e-9;
+    // |e^{i rho} - (1 + i rho)| <= rho^2/2 times an amplitude <= 0.2 (z >= 20):
+    // at most eps/64 per entry for rho <= sqrt(eps/6.4).  Only k_near has these
+    // variants: plans for several right-hand sides (k_near_multi) keep the
+    // full factor.
+    r.rho1 = (p.direct || p.nrhs > 1) ? 0.0 : std::sqrt(p.eps / 6.4);
     return r;
+}
+
+// Bound on the residual phase rho = (e_k + r^_k) b_n over rows <= k1 and
+// columns >= n0: r^_k grows with k; e_k <= b_k / (pi (N + 3/4)) < 0.02/N
+// (Lemma 3.2's perturbation of the DHT rows, b_k < 0.05); b_n < 1/(8 pi (n - 1/4))
+// (the leading term of McMahon's expansion, which the next, negative, term
+// only lowers), with a margin of 0.1%.
+double rho_bound(const Grid& g, int64_t k1, int64_t n0) {
+    if (!g.col_pert) return 0.0;
+    const double s = g.rhat(k1) + (g.row_pert ? 0.02 / double(g.N) : 0.0);
+    return s * 1.001 / (8.0 * M_PI * (double(n0) - 0.25));
 }
 
 // Variant of the block of columns [n0, n1] of rows [k0, k1], from bounds on z
@@ -279,17 +296,21 @@ NearRule near_rule(const Plan& p) {
 // z <= z~ + 0.25.
 int near_block_variant(const Grid& g, const NearRule& r, int64_t k0, int64_t k1, int64_t n0, int64_t n1) {
     const double zlo = g.ztilde(k0, n0), zhi = g.ztilde(k1, n1) + 0.25;
+    const bool rot1 = g.col_pert && rho_bound(g, k1, n0) <= r.rho1;
     if (!(zhi >= J0_ASY_Z)) return r.small8 ? NV_SMALL8 : NV_SMALL;
-    if (zlo < J0_ASY_Z) return r.mix6 ? (r.small8 ? NV_MIX6_8 : NV_MIX6) : (r.small8 ? NV_MIX12_8 : NV_MIX12);
+    if (zlo < J0_ASY_Z)
+        return r.mix6 ? (r.small8 ? (rot1 ? NV_MIX6_8R : NV_MIX6_8) : NV_MIX6) : (r.small8 ? NV_MIX12_8 : NV_MIX12);
     const int codes[6] = {NV_M2, NV_M3, NV_M4, NV_M6, NV_M8, NV_M12};
+    const int rcodes[3] = {NV_M2R, NV_M3R, NV_M4R};
     for (int i = 0; i < 6; ++i)
-        if (r.zM[i] <= zlo) return codes[i];
+        if (r.zM[i] <= zlo) return (rot1 && i < 3) ? rcodes[i] : codes[i];
     return NV_M12;
 }
 
 // relative cost per entry of each variant (VALU operations, measured from the
 // compiled loops)
-constexpr double NV_COST[NV_COUNT] = {0.9, 1.9, 1.7, 0.85, 0.9, 1.0, 1.1, 1.2, 1.35, 0.7, 1.7, 1.5};
+constexpr double NV_COST[NV_COUNT] = {0.9, 1.9, 1.7, 0.85, 0.9, 1.0, 1.1, 1.2, 1.35, 0.7, 1.7, 1.5,
+                                      0.68, 0.73, 0.83, 1.4};
 
 hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
     const Plan& p = dp.plan;

@@ -275,7 +275,9 @@ __device__ __forceinline__ void near_skip16(NearLane& r) {
 // the P, Q series, so it is formed to working precision.
 // LEAN (the plan's G.lean: per-entry budget of at least 1.25e-10): one Newton
 // step for z^{-1/2} and the shorter residual sine and cosine.
-template <int M, bool PERT, bool LEAN = false>
+// ROT1: the residual factor e^{i rho} to first order, 1 + i rho (blocks whose
+// rho is small enough, chosen on the host).
+template <int M, bool PERT, bool LEAN = false, bool ROT1 = false>
 __device__ __forceinline__ double near_asy(const GridArgs& G, const NearLane& r, double bn) {
     constexpr Hankel0 H = make_hankel0(0.79788456080286535588); // sqrt(2/pi) folded in
     const double delta = PERT ? fma(r.ek, fma(r.Nd, G.pi_Qc, bn), r.rk * bn) : 0.0;
@@ -288,7 +290,11 @@ __device__ __forceinline__ double near_asy(const GridArgs& G, const NearLane& r,
         Q = fma(Q, zi2, H.q[m]);
     }
     double cs = r.u.x, sn = r.u.y;
-    if (PERT) {
+    if (PERT && ROT1) {
+        const double x = r.sk * bn;
+        cs = fma(-r.u.y, x, r.u.x);
+        sn = fma(r.u.x, x, r.u.y);
+    } else if (PERT) {
         double s, c;
         sincos_tiny(r.sk * bn, &s, &c, LEAN);
         cs = fma(r.u.x, c, -r.u.y * s);
@@ -309,7 +315,7 @@ __device__ __forceinline__ double near_z_exact(const GridArgs& G, const NearLane
 // J_0 at the lane's current column, then one step on
 // (both branches: each lane takes its own, so a wave pays for both only where
 // its rows straddle z = 20)
-template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG, bool LEAN = false>
+template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG, bool LEAN = false, bool ROT1 = false>
 __device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, double bn) {
     double J;
     if (SMALL && ASY) {
@@ -317,11 +323,11 @@ __device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, doub
         if (z < J0_ASY_Z)
             J = j0_small<NT>(z);
         else
-            J = near_asy<M, PERT, LEAN>(G, r, bn);
+            J = near_asy<M, PERT, LEAN, ROT1>(G, r, bn);
     } else if (SMALL) {
         J = j0_small<NT>(near_z_exact(G, r, bn));
     } else {
-        J = near_asy<M, PERT, LEAN>(G, r, bn);
+        J = near_asy<M, PERT, LEAN, ROT1>(G, r, bn);
     }
     if (ASY) r.u = cmul(r.u, r.w);
     r.Nd += r.dNd;
@@ -355,13 +361,13 @@ __device__ __forceinline__ int tile_block_variant(const uint32_t* bv, int64_t n0
 }
 
 // One 64-column block of a sweep: the lane's columns p[0], p[4], ... (cnt of them)
-template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG, bool LEAN = false>
+template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG, bool LEAN = false, bool ROT1 = false>
 __device__ __forceinline__ void near_block(const GridArgs& G, const ColCB* p, int cnt, NearLane& r, double& acc) {
     if (ASY) near_anchor(G, r);
     HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
     for (int i = 0; i < cnt; ++i) {
         const ColCB v = p[4 * i];
-        acc = fma(v.c, near_step<M, SMALL, ASY, PERT, NT, LEAN>(G, r, PERT ? v.b : 0.0), acc);
+        acc = fma(v.c, near_step<M, SMALL, ASY, PERT, NT, LEAN, ROT1>(G, r, PERT ? v.b : 0.0), acc);
     }
 }
 
@@ -379,7 +385,12 @@ __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb,
         const ColCB* p = cb + (nw - T.n0);
 #define BLOCK(M_, S_, A_) near_block<M_, S_, A_, PERT, J0_TAYLOR_DEG, LEAN>(G, p, cnt, r, acc); break
 #define BLOCK8(M_, A_) near_block<M_, true, A_, PERT, 8, LEAN>(G, p, cnt, r, acc); break
+#define BLOCKR(M_, S_, A_, NT_) near_block<M_, S_, A_, PERT, NT_, LEAN, PERT>(G, p, cnt, r, acc); break
         switch (tile_block_variant(bv, T.n0, nb)) {
+        case NV_M2R: BLOCKR(2, false, true, J0_TAYLOR_DEG);
+        case NV_M3R: BLOCKR(3, false, true, J0_TAYLOR_DEG);
+        case NV_M4R: BLOCKR(4, false, true, J0_TAYLOR_DEG);
+        case NV_MIX6_8R: BLOCKR(6, true, true, 8);
         case NV_SMALL: BLOCK(3, true, false);
         case NV_MIX12: BLOCK(12, true, true);
         case NV_MIX6: BLOCK(6, true, true);
@@ -393,6 +404,7 @@ __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb,
         case NV_M8: BLOCK(8, false, true);
         default: BLOCK(12, false, true);
         }
+#undef BLOCKR
 #undef BLOCK8
 #undef BLOCK
         near_skip16(r);
@@ -1227,9 +1239,15 @@ template <int L2>
 constexpr int wave_col_stride() {
     return HANK_LDS_SWZ ? L2 + 2 : (L2 + L2 / 8) | 1;
 }
+// LDS buffers (groups alternate between them: one workgroup barrier per
+// group with two, two with one).  At 512 points a workgroup already holds a
+// compute unit by its registers, so its two buffers (148 KB) cost nothing.
+#ifndef HANK_WAVE_COLS_BUFS512
+#define HANK_WAVE_COLS_BUFS512 2
+#endif
 template <int L2>
 constexpr int wave_col_bufs() {
-    return L2 <= 256 ? 2 : 1;
+    return L2 <= 256 ? 2 : HANK_WAVE_COLS_BUFS512;
 }
 
 // Pass A for a block of at most L1 columns: only row 0 (n' = j1) of each

@@ -221,3 +221,24 @@ def test_m_override_rejected():
     with pytest.raises(hank.HankError):
         hank.plan_info("dht0", 1 << 16, 1e-14, plan_mode=1, M=4)
     assert hank.plan_info("dht0", 1 << 16, 1e-14, plan_mode=1, M=5)["M"] == 5
+
+
+def test_first_order_residual_bounds():
+    """The planner gives a near-field block the first-order residual factor
+    1 + i rho when its bound on rho = (e_k + r^_k) b_n is small enough; that
+    bound takes b_n < 1.001 / (8 pi (n - 1/4)) (McMahon's leading term) and,
+    for the DHT rows, 0 <= e_k < 0.02/N.  Both checked against the oracle's
+    roots of J_0 (Lemma 3.2)."""
+    import oracle
+
+    nmax = 200000
+    b = oracle.root_offsets(nmax)
+    n = np.arange(1, nmax + 1, dtype=np.float64)
+    assert np.all(b > 0.0)
+    assert np.all(b < 1.001 / (8.0 * np.pi * (n - 0.25)))
+    for N in (1000, 1 << 16):
+        j = oracle.roots(N + 1)
+        k = np.arange(1, N + 1, dtype=np.float64)
+        e = j[:N] / j[N] - (k - 0.25) / (N + 0.75)
+        assert np.all(e >= -1e-15)
+        assert np.all(e < 0.02 / N)
