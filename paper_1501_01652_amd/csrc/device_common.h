@@ -32,6 +32,37 @@ __device__ __forceinline__ cx<F> cmul(cx<F> a, cx<F> b) {
 template <typename F>
 __device__ __forceinline__ cx<F> cscale(cx<F> a, F s) { return mk(a.x * s, a.y * s); }
 
+// Global-memory views.  A pointer read from a descriptor in memory is one the
+// compiler cannot prove global, so it would be accessed with FLAT
+// instructions, which also count against the LDS wait counter (every wait for
+// an LDS exchange would then wait for the outstanding HBM loads and stores as
+// well).  Through these views the accesses are global_* instructions.
+template <typename T>
+using glob = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ glob<T>* gview(T* p) {
+    return (glob<T>*)p;
+}
+template <typename T>
+__device__ __forceinline__ const glob<T>* gview(const T* p) {
+    return (const glob<T>*)p;
+}
+// complex loads and stores through a global view (as one 2-vector)
+template <typename F>
+__device__ __forceinline__ cx<F> gload(const glob<cx<F>>* p) {
+    typedef F v2 __attribute__((ext_vector_type(2)));
+    const v2 t = *(const glob<v2>*)p;
+    return mk(t.x, t.y);
+}
+template <typename F>
+__device__ __forceinline__ void gstore(glob<cx<F>>* p, cx<F> v) {
+    typedef F v2 __attribute__((ext_vector_type(2)));
+    v2 t;
+    t.x = v.x;
+    t.y = v.y;
+    *(glob<v2>*)p = t;
+}
+
 // Device copy of the host tables (see tables.cpp).
 extern __device__ DeviceTables g_tab;
 

@@ -431,8 +431,8 @@ void k_near(const NearProb* __restrict__ probs, int nprob, double* __restrict__ 
     if (threadIdx.x < 4) sbv[threadIdx.x] = P.tiles[blockIdx.x - P.tile_start].bvar[threadIdx.x];
     double* out = partial + P.pbase + T.slot * 64;
     const GridArgs G = P.G; // by value: scalar registers, loaded once
-    const double* c = P.c;
-    const double* bvec = P.b;
+    const auto c = gview(P.c);
+    const auto bvec = gview(P.b);
     const double* evec = P.e;
     const int ncol = (int)(T.n1 - T.n0);
     for (int i = threadIdx.x; i < ncol; i += 256) {
@@ -457,7 +457,7 @@ void k_near(const NearProb* __restrict__ probs, int nprob, double* __restrict__ 
         if (!T.sole)
             out[lane] = v;
         else if (lane < T.nk)
-            P.f[T.k0 + lane - 1] = v; // what the reduce would write: 0 + v
+            gview(P.f)[T.k0 + lane - 1] = v; // what the reduce would write: 0 + v
     }
 }
 
@@ -563,9 +563,9 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int j = (t >> 6) + 4 * i;
-                Cs[lane][j] = (j < nr && n < T.n1) ? P.c[(int64_t)j * P.ldc + n - 1] : 0.0;
+                Cs[lane][j] = (j < nr && n < T.n1) ? gview(P.c)[(int64_t)j * P.ldc + n - 1] : 0.0;
             }
-            if (PERT && t < 64) Bs[t] = n < T.n1 ? P.b[n - 1] : 0.0;
+            if (PERT && t < 64) Bs[t] = n < T.n1 ? gview(P.b)[n - 1] : 0.0;
         }
         __syncthreads();
 #define BLOCK(M_, S_, A_) near_multi_block<M_, S_, A_, PERT>(G, R, Cs, Bs, Js + 1024 * wave, nb, T.n1, kq, lane, nblk, acc); break
@@ -663,8 +663,8 @@ __global__ __launch_bounds__(256) void k_near_nu(const NearProb* __restrict__ pr
     const bool pert = G.col_pert != 0;
     const int ncol = (int)(T.n1 - T.n0);
     for (int i = threadIdx.x; i < ncol; i += 256) {
-        cs[i] = P.c[T.n0 - 1 + i];
-        bs[i] = pert ? P.b[T.n0 - 1 + i] : 0.0;
+        cs[i] = gview(P.c)[T.n0 - 1 + i];
+        bs[i] = pert ? gview(P.b)[T.n0 - 1 + i] : 0.0;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -780,9 +780,9 @@ __global__ __launch_bounds__(256) void k_near_reduce1(const NearProb* __restrict
         red[wave][lane] = s;
         __syncthreads();
         if (wave == 0 && lane < R.nk)
-            P.f[R.k0 + lane - 1] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+            gview(P.f)[R.k0 + lane - 1] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
     } else if (valid && lane < R.nk) {
-        P.f[R.k0 + lane - 1] = s;
+        gview(P.f)[R.k0 + lane - 1] = s;
     }
 }
 
@@ -811,7 +811,7 @@ __device__ __forceinline__ void near_reduce_multi(const NearProb& P, const RowTi
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int e = (int)threadIdx.x + 256 * i, l = e & 63;
-        if (e < E && l < R.nk) P.f[(int64_t)(e >> 6) * P.ldo + R.k0 + l - 1] = s[i];
+        if (e < E && l < R.nk) gview(P.f)[(int64_t)(e >> 6) * P.ldo + R.k0 + l - 1] = s[i];
     }
 }
 
@@ -930,7 +930,7 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict
     if ((int64_t)mp.wg * W >= A.ncols) return; // columns past the block: zero input, not stored
     cx<F>* my = sh + w * col_stride<L2>();
     const int ng = A.g1 - A.g0;
-    cx<F>* buf = (cx<F>*)D.buf;
+    const auto buf = gview((cx<F>*)D.buf);
 
     double vw[R], xb[R], la[R], pw[R];
     cx<double> qb[R];
@@ -946,7 +946,7 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict
             const int64_t n = A.na + np;
             const int64_t Nn = A.ac * n + A.bc;
             const double wn = (double)Nn * A.pi_Qc;
-            const double bn = A.col_pert ? D.b[n - 1] : 0.0;
+            const double bn = A.col_pert ? gview(D.b)[n - 1] : 0.0;
             vw[r] = wn / A.w0;
             const double iw = 1.0 / vw[r];
             xb[r] = (bn / A.bref) * iw;
@@ -958,7 +958,7 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict
     {
         const int j = mp.j;
         const int gs = A.g0 + mp.chunk * D.gchunk, ge = min(A.g1, gs + D.gchunk);
-        const double* cj = D.c + (int64_t)j * D.ldc;
+        const auto cj = gview(D.c) + (int64_t)j * D.ldc;
         double cv[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) cv[r] = nidx[r] >= 0 ? cj[nidx[r]] : 0.0;
@@ -1005,12 +1005,12 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_a(const FarDesc* __restrict
                 v[r] = mk(F(y.x), F(y.y));
             }
             fft_reg<F, L2, R, -1>(v, my, tt);
-            cx<F>* out = buf + ((int64_t)j * ng + (g - A.g0)) * A.L;
+            const auto out = buf + ((int64_t)j * ng + (g - A.g0)) * A.L;
             cx<double> tw = tw0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t m2 = tt + r * NTC;
-                out[m2 * A.L1 + j1] = cmul(v[r], mk(F(tw.x), F(tw.y)));
+                gstore(out + m2 * A.L1 + j1, cmul(v[r], mk(F(tw.x), F(tw.y))));
                 if (r + 1 < R) tw = cmul(tw, tws);
             }
         }
@@ -1093,11 +1093,11 @@ __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(const FarDesc* __restr
     const bool okrow = row < A.L2;
     const int64_t rowc = okrow ? row : 0;
     cx<F>* my = sh + rl * (L1 + L1 / 8);
-    const cx<F>* hrow = (const cx<F>*)D.H + rowc * L1;
-    cx<F>* buf = (cx<F>*)D.buf;
+    const auto hrow = gview((const cx<F>*)D.H) + rowc * L1;
+    const auto buf = gview((cx<F>*)D.buf);
     cx<F> hv[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) hv[r] = hrow[tt + r * NTR];
+    for (int r = 0; r < R; ++r) hv[r] = gload(hrow + tt + r * NTR);
     // inverse four-step twiddles e^{+2 pi i j1 m2 / L}, j1 = tt + r NTR, formed
     // per group as t0 ts^r from two table entries (holding all eight across the
     // groups would cost 32 more registers)
@@ -1109,12 +1109,12 @@ __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(const FarDesc* __restr
     const int gs = mp.chunk * D.gchunk, ge = min(ng, gs + D.gchunk);
     for (int gq = gs; gq < ge; ++gq) {
         const int64_t q = (int64_t)mp.j * ng + gq;
-        cx<F>* p = buf + q * A.L + rowc * L1;
+        const auto p = buf + q * A.L + rowc * L1;
         cx<F> v[R];
         // columns j1 >= ncols hold zeros (pass A does not store them), and
         // columns j1 >= nrows feed no output row (pass C skips them)
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = tt + r * NTR < A.ncols ? p[tt + r * NTR] : mk(F(0), F(0));
+        for (int r = 0; r < R; ++r) v[r] = tt + r * NTR < A.ncols ? gload(p + tt + r * NTR) : mk(F(0), F(0));
         fft_reg<F, L1, R, -1>(v, my, tt);
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = cmul(v[r], hv[r]);
@@ -1124,7 +1124,7 @@ __global__ __launch_bounds__(ROWS * L1 / 8) void k_pass_b(const FarDesc* __restr
             asm volatile("" : "+v"(t.x), "+v"(t.y)); // formed here, not hoisted out of the group loop
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (tt + r * NTR < A.nrows) p[tt + r * NTR] = cmul(v[r], mk(F(t.x), F(t.y)));
+                if (tt + r * NTR < A.nrows) gstore(p + tt + r * NTR, cmul(v[r], mk(F(t.x), F(t.y))));
                 if (r + 1 < R) t = cmul(t, ts);
             }
         }
@@ -1146,7 +1146,7 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict
     if ((int64_t)mp.wg * W >= A.nrows) return; // columns holding no output row
     cx<F>* my = sh + w * col_stride<L2>();
     const int ng = A.g1 - A.g0;
-    const cx<F>* buf = (const cx<F>*)D.buf;
+    const auto buf = gview((const cx<F>*)D.buf);
     double rho[R], ek[R], acc[R], pw[R];
     cx<double> pk[R];
 #pragma unroll
@@ -1158,7 +1158,7 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict
         if (kp < A.nrows) {
             const int64_t k = A.ka + kp;
             rho[r] = ((double)(A.ar * k + A.br) / (double)A.Dr) / A.r0;
-            ek[r] = A.row_pert ? D.e[k - 1] / A.eref : 0.0;
+            ek[r] = A.row_pert ? gview(D.e)[k - 1] / A.eref : 0.0;
             pk[r] = cscale(expi_ratio(2 * A.Kka * A.Nna + 2 * A.ar * A.Nna * kp + A.ar * A.ac * kp * kp, 2 * A.D),
                            1.0 / sqrt(rho[r]));
         }
@@ -1187,10 +1187,10 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict
             }
             ecur = Gd.e;
             acur = Gd.a;
-            const cx<F>* p = buf + ((int64_t)j * ng + (g - A.g0)) * A.L;
+            const auto p = buf + ((int64_t)j * ng + (g - A.g0)) * A.L;
             cx<F> v[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[r] = p[(int64_t)(tt + r * NTC) * A.L1 + j1];
+            for (int r = 0; r < R; ++r) v[r] = gload(p + (int64_t)(tt + r * NTC) * A.L1 + j1);
             fft_reg<F, L2, R, 1>(v, my, tt);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -1201,14 +1201,14 @@ __global__ __launch_bounds__(W * L2 / 8) void k_pass_c(const FarDesc* __restrict
             }
         }
         if (D.nchunk == 1) {
-            double* fj = D.f + (int64_t)j * D.ldo;
+            const auto fj = gview(D.f) + (int64_t)j * D.ldo;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t kp = j1 + (int64_t)A.L1 * (tt + r * NTC);
                 if (kp < A.nrows) fj[A.ka + kp - 1] += acc[r];
             }
         } else {
-            double* pj = D.part + ((int64_t)j * D.nchunk + mp.chunk) * A.nrows;
+            const auto pj = gview(D.part) + ((int64_t)j * D.nchunk + mp.chunk) * A.nrows;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t kp = j1 + (int64_t)A.L1 * (tt + r * NTC);
@@ -1262,7 +1262,7 @@ __device__ __forceinline__ void pass_aw_row0(const FarDesc& D, const FarItem& mp
     const int t = threadIdx.x, cw = t % W, q = t / W;
     const int64_t j1 = jb + cw;
     const int ng = A.g1 - A.g0;
-    cx<F>* buf = (cx<F>*)D.buf;
+    const auto buf = gview((cx<F>*)D.buf);
     const int j = mp.j;
     double vw = 1.0, xb = 0.0, la = 0.0;
     cx<double> qb = mk(0.0, 0.0);
@@ -1270,13 +1270,13 @@ __device__ __forceinline__ void pass_aw_row0(const FarDesc& D, const FarItem& mp
         const int64_t n = A.na + j1;
         const int64_t Nn = A.ac * n + A.bc;
         const double wn = (double)Nn * A.pi_Qc;
-        const double bn = A.col_pert ? D.b[n - 1] : 0.0;
+        const double bn = A.col_pert ? gview(D.b)[n - 1] : 0.0;
         vw = wn / A.w0;
         const double iw = 1.0 / vw;
         xb = (bn / A.bref) * iw;
         la = (wn + bn) / A.lref;
         qb = cscale(expi_ratio(2 * A.Kka * A.ac * j1 + A.ar * A.ac * j1 * j1, 2 * A.D),
-                    sqrt(iw) * D.c[(int64_t)j * D.ldc + n - 1]);
+                    sqrt(iw) * gview(D.c)[(int64_t)j * D.ldc + n - 1]);
     }
     cx<F> tw[R];
     {
@@ -1314,9 +1314,9 @@ __device__ __forceinline__ void pass_aw_row0(const FarDesc& D, const FarItem& mp
         }
         const cx<double> y = cmul(mk(Xr * pw, Xi * pw), qb);
         const cx<F> yf = mk(F(y.x), F(y.y));
-        cx<F>* out = buf + ((int64_t)j * ng + (g - A.g0)) * A.L + jb + cw;
+        const auto out = buf + ((int64_t)j * ng + (g - A.g0)) * A.L + jb + cw;
 #pragma unroll
-        for (int r = 0; r < R; ++r) out[(int64_t)(q + 64 * r) * A.L1] = cmul(yf, tw[r]);
+        for (int r = 0; r < R; ++r) gstore(out + (int64_t)(q + 64 * r) * A.L1, cmul(yf, tw[r]));
     }
 }
 
@@ -1337,12 +1337,12 @@ __device__ __forceinline__ void pass_aw_main(const FarDesc& D, const FarItem& mp
     const int cw = t % W, q = t / W;
     const int64_t j1 = jb + wv;
     const int ng = A.g1 - A.g0;
-    cx<F>* buf = (cx<F>*)D.buf;
+    const auto buf = gview((cx<F>*)D.buf);
 
     double vw[RH], xb[RH], la[RH], pw[RH];
     cx<double> qb[RH]; // q(n') c_n (w^_n/w0)^(-1/2); zero past the block's columns
     const int j = mp.j;
-    const double* cj = D.c + (int64_t)j * D.ldc;
+    const auto cj = gview(D.c) + (int64_t)j * D.ldc;
 #pragma unroll
     for (int r = 0; r < RH; ++r) {
         const int64_t np = j1 + (int64_t)A.L1 * (lane + 64 * r);
@@ -1353,7 +1353,7 @@ __device__ __forceinline__ void pass_aw_main(const FarDesc& D, const FarItem& mp
             const int64_t n = A.na + np;
             const int64_t Nn = A.ac * n + A.bc;
             const double wn = (double)Nn * A.pi_Qc;
-            const double bn = A.col_pert ? D.b[n - 1] : 0.0;
+            const double bn = A.col_pert ? gview(D.b)[n - 1] : 0.0;
             vw[r] = wn / A.w0;
             const double iw = 1.0 / vw[r];
             xb[r] = (bn / A.bref) * iw;
@@ -1412,11 +1412,11 @@ __device__ __forceinline__ void pass_aw_main(const FarDesc& D, const FarItem& mp
             if (r + 1 < R) tw = cmul(tw, tws);
         }
         __syncthreads();
-        cx<F>* out = buf + ((int64_t)j * ng + (g - A.g0)) * A.L;
+        const auto out = buf + ((int64_t)j * ng + (g - A.g0)) * A.L;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int m2 = q + 64 * r;
-            out[(int64_t)m2 * A.L1 + jb + cw] = sh[b][cw * S + lds_swz(m2)];
+            gstore(out + (int64_t)m2 * A.L1 + jb + cw, sh[b][cw * S + lds_swz(m2)]);
         }
         if constexpr (NB == 1)
             __syncthreads();
@@ -1458,13 +1458,13 @@ __device__ __forceinline__ void pass_cw_row0(const FarDesc& D, const FarItem& mp
     const int64_t kp = jb + cw;
     const bool valid = kp < A.nrows;
     const int ng = A.g1 - A.g0;
-    const cx<F>* buf = (const cx<F>*)D.buf;
+    const auto buf = gview((const cx<F>*)D.buf);
     const int j = mp.j;
     double rho = 1.0, ek = 0.0;
     if (valid) {
         const int64_t k = A.ka + kp;
         rho = ((double)(A.ar * k + A.br) / (double)A.Dr) / A.r0;
-        ek = A.row_pert ? D.e[k - 1] / A.eref : 0.0;
+        ek = A.row_pert ? gview(D.e)[k - 1] / A.eref : 0.0;
     }
     const int gs = A.g0 + mp.chunk * D.gchunk, ge = min(A.g1, gs + D.gchunk);
     int ecur = 0, acur = 0;
@@ -1481,11 +1481,11 @@ __device__ __forceinline__ void pass_cw_row0(const FarDesc& D, const FarItem& mp
         ecur = Gd.e;
         acur = Gd.a;
         if (valid) {
-            const cx<F>* p = buf + ((int64_t)j * ng + (g - A.g0)) * A.L + jb + cw;
+            const auto p = buf + ((int64_t)j * ng + (g - A.g0)) * A.L + jb + cw;
             double sx = 0.0, sy = 0.0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const cx<F> v = p[(int64_t)(q + 64 * r) * A.L1];
+                const cx<F> v = gload(p + (int64_t)(q + 64 * r) * A.L1);
                 sx += (double)v.x;
                 sy += (double)v.y;
             }
@@ -1510,9 +1510,9 @@ __device__ __forceinline__ void pass_cw_row0(const FarDesc& D, const FarItem& mp
             expi_ratio(2 * A.Kka * A.Nna + 2 * A.ar * A.Nna * kp + A.ar * A.ac * kp * kp, 2 * A.D), 1.0 / sqrt(rho));
         const double val = pk.x * tot.x - pk.y * tot.y;
         if (D.nchunk == 1)
-            D.f[(int64_t)j * D.ldo + A.ka - 1 + kp] += val;
+            gview(D.f)[(int64_t)j * D.ldo + A.ka - 1 + kp] += val;
         else
-            D.part[((int64_t)j * D.nchunk + mp.chunk) * A.nrows + kp] = val;
+            gview(D.part)[((int64_t)j * D.nchunk + mp.chunk) * A.nrows + kp] = val;
     }
 }
 
@@ -1534,7 +1534,7 @@ __device__ __forceinline__ void pass_cw_main(const FarDesc& D, const FarItem& mp
     const int cw = t % W, q = t / W;
     const int64_t j1 = jb + wv;
     const int ng = A.g1 - A.g0;
-    const cx<F>* buf = (const cx<F>*)D.buf;
+    const auto buf = gview((const cx<F>*)D.buf);
     double rho[RH], ek[RH], pw[RH];
     cx<double> acc[RH];
 #pragma unroll
@@ -1546,15 +1546,15 @@ __device__ __forceinline__ void pass_cw_main(const FarDesc& D, const FarItem& mp
         if (kp < A.nrows) {
             const int64_t k = A.ka + kp;
             rho[r] = ((double)(A.ar * k + A.br) / (double)A.Dr) / A.r0;
-            ek[r] = A.row_pert ? D.e[k - 1] / A.eref : 0.0;
+            ek[r] = A.row_pert ? gview(D.e)[k - 1] / A.eref : 0.0;
         }
     }
     const int j = mp.j;
     const int gs = A.g0 + mp.chunk * D.gchunk, ge = min(A.g1, gs + D.gchunk);
     auto load = [&](int g, cx<F>(&v)[R]) {
-        const cx<F>* p = buf + ((int64_t)j * ng + (g - A.g0)) * A.L + jb + cw;
+        const auto p = buf + ((int64_t)j * ng + (g - A.g0)) * A.L + jb + cw;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = p[(int64_t)(q + 64 * r) * A.L1];
+        for (int r = 0; r < R; ++r) v[r] = gload(p + (int64_t)(q + 64 * r) * A.L1);
     };
     cx<F> vn[R];
     load(gs, vn);
@@ -1601,8 +1601,8 @@ __device__ __forceinline__ void pass_cw_main(const FarDesc& D, const FarItem& mp
         else
             b ^= 1;
     }
-    double* fj = D.nchunk == 1 ? D.f + (int64_t)j * D.ldo + A.ka - 1
-                               : D.part + ((int64_t)j * D.nchunk + mp.chunk) * A.nrows;
+    const auto fj = gview(D.nchunk == 1 ? D.f + (int64_t)j * D.ldo + A.ka - 1
+                                        : D.part + ((int64_t)j * D.nchunk + mp.chunk) * A.nrows);
 #pragma unroll
     for (int r = 0; r < RH; ++r) {
         const int64_t kp = j1 + (int64_t)A.L1 * (lane + 64 * r);
@@ -1693,11 +1693,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int64_t row = mp.wg; // one row per workgroup: mp.wg < L2
     cx<F>* my = sh + wv * SR;
     // this wave's chirp spectrum (permuted layout)
-    const cx<F>* hrow = (const cx<F>*)D.H + row * L1 + wv * 512;
+    const auto hrow = gview((const cx<F>*)D.H) + row * L1 + wv * 512;
     cx<F> hv[8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) hv[s] = hrow[lane + 64 * s];
-    cx<F>* buf = (cx<F>*)D.buf;
+    for (int s = 0; s < 8; ++s) hv[s] = gload(hrow + lane + 64 * s);
+    const auto buf = gview((cx<F>*)D.buf);
     const int ng = A.g1 - A.g0;
     const int gs = mp.chunk * D.gchunk, ge = min(ng, gs + D.gchunk);
     // columns j1 = t + 512 a >= ncols hold zeros (pass A does not store them),
@@ -1710,10 +1710,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         smask |= uint32_t(t + 512 * a < A.nrows) << a;
     }
     for (int gq = gs; gq < ge; ++gq) {
-        cx<F>* p = buf + ((int64_t)mp.j * ng + gq) * A.L + row * L1;
+        const auto p = buf + ((int64_t)mp.j * ng + gq) * A.L + row * L1;
         cx<F> v[8];
 #pragma unroll
-        for (int a = 0; a < 8; ++a) v[a] = (lmask >> a) & 1 ? p[t + 512 * a] : mk(F(0), F(0));
+        for (int a = 0; a < 8; ++a) v[a] = (lmask >> a) & 1 ? gload(p + t + 512 * a) : mk(F(0), F(0));
         row8x512_forward<F, SR>(v, sh, t, lane, wv);
 #pragma unroll
         for (int s = 0; s < 8; ++s) v[s] = cmul(v[s], hv[s]);
@@ -1741,7 +1741,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         cx<double> w = mk(f0.x, -f0.y);
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
-            if ((smask >> a) & 1) p[t + 512 * a] = cmul(v[a], mk(F(w.x), F(w.y)));
+            if ((smask >> a) & 1) gstore(p + t + 512 * a, cmul(v[a], mk(F(w.x), F(w.y))));
             if (a + 1 < 8) w = cmul(w, fs);
         }
     }
@@ -1772,10 +1772,10 @@ __global__ __launch_bounds__(256) void k_far_reduce(const FarDesc* __restrict__ 
     const FarDesc& D = descs[mp.desc];
     const int64_t kp = (int64_t)mp.wg * 256 + threadIdx.x;
     if (kp >= D.A.nrows) return;
-    const double* pj = D.part + (int64_t)mp.j * D.nchunk * D.A.nrows + kp;
+    const const auto pj = gview(D.part) + (int64_t)mp.j * D.nchunk * D.A.nrows + kp;
     double s = 0.0;
     for (int q = 0; q < D.nchunk; ++q) s += pj[(int64_t)q * D.A.nrows];
-    D.f[(int64_t)mp.j * D.ldo + D.A.ka + kp - 1] += s;
+    gview(D.f)[(int64_t)mp.j * D.ldo + D.A.ka + kp - 1] += s;
 }
 
 // ---------------------------------------------------------------------------
