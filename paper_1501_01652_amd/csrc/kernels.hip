@@ -1772,7 +1772,7 @@ __global__ __launch_bounds__(256) void k_far_reduce(const FarDesc* __restrict__ 
     const FarDesc& D = descs[mp.desc];
     const int64_t kp = (int64_t)mp.wg * 256 + threadIdx.x;
     if (kp >= D.A.nrows) return;
-    const const auto pj = gview(D.part) + (int64_t)mp.j * D.nchunk * D.A.nrows + kp;
+    const auto pj = gview(D.part) + (int64_t)mp.j * D.nchunk * D.A.nrows + kp;
     double s = 0.0;
     for (int q = 0; q < D.nchunk; ++q) s += pj[(int64_t)q * D.A.nrows];
     gview(D.f)[(int64_t)mp.j * D.ldo + D.A.ka + kp - 1] += s;
