@@ -839,12 +839,23 @@ void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR, size_t budget =
                     const double GL = double(ng) * double(J.nrhs) * double(d.args.L);
                     off += size_t(GL * esz);
                     const double cols = double(d.args.ncols), rws = double(d.args.nrows), nr = double(J.nrhs);
+                    // a strip of at most L1 columns on the FP64 wave kernels hands pass B
+                    // only its one nonzero input per column
+                    const bool x0fused = !it.f32 && d.args.L1 == 4096 && (d.args.L2 == 256 || d.args.L2 == 512) &&
+                                         d.args.ncols <= d.args.L1;
+                    D.x0off = -1;
+                    if (x0fused) {
+                        D.x0off = int64_t(off);
+                        off += size_t(double(ng) * nr * cols * esz);
+                        off = (off + 255) & ~size_t(255);
+                    }
                     // the work buffer columns j1 < ncols carry data (pass A -> pass B) and
                     // j1 < nrows results (pass B -> pass C); the others are not moved
                     const double L1 = double(d.args.L1);
                     const double fa = std::min(cols, L1) / L1, fc = std::min(rws, L1) / L1;
-                    Ln.bytesA += GL * esz * fa + cols * (8.0 * nr + (d.args.col_pert ? 8.0 : 0.0));
-                    Ln.bytesB += GL * esz * (fa + fc) + double(d.args.L) * esz;
+                    const double ain = x0fused ? double(ng) * nr * cols * esz : GL * esz * fa; // A -> B
+                    Ln.bytesA += ain + cols * (8.0 * nr + (d.args.col_pert ? 8.0 : 0.0));
+                    Ln.bytesB += ain + GL * esz * fc + double(d.args.L) * esz;
                     Ln.bytesC += GL * esz * fc + rws * (d.args.row_pert ? 8.0 : 0.0);
                     if (D.nchunk > 1) {
                         D.part = reinterpret_cast<double*>(part_need);
@@ -954,6 +965,7 @@ hank_status run_jobs(std::vector<Job>& jobs_in, hipStream_t s) {
     if ((st = ensure(g_ex.work, PR.work_need, s))) return st;
     if ((st = ensure(g_ex.fpart, std::max<size_t>(PR.part_need, 8), s))) return st;
     for (auto& D : PR.descs) {
+        D.x0 = D.x0off >= 0 ? static_cast<char*>(g_ex.work.p) + D.x0off : nullptr;
         D.buf = static_cast<char*>(g_ex.work.p) + reinterpret_cast<size_t>(D.buf);
         if (D.nchunk > 1)
             D.part = reinterpret_cast<double*>(static_cast<char*>(g_ex.fpart.p) + reinterpret_cast<size_t>(D.part));
@@ -1666,6 +1678,7 @@ hank_status hank_batch_graph_create(const hank_request* reqs, int64_t count, han
     if ((st = alloc(g->probs, PR.probs.size() * sizeof(NearProb)))) return st;
     if ((st = alloc(g->descs, PR.descs.size() * sizeof(FarDesc)))) return st;
     for (auto& D : PR.descs) {
+        D.x0 = D.x0off >= 0 ? static_cast<char*>(g->work) + D.x0off : nullptr;
         D.buf = static_cast<char*>(g->work) + reinterpret_cast<size_t>(D.buf);
         if (D.nchunk > 1)
             D.part = reinterpret_cast<double*>(static_cast<char*>(g->fpart) + reinterpret_cast<size_t>(D.part));
@@ -1826,6 +1839,8 @@ hank_status hank_autotune(hank_stream_t stream, int32_t* chosen) {
                 D.c = static_cast<const double*>(c);
                 D.f = static_cast<double*>(f);
                 D.buf = buf;
+                D.x0off = -1;
+                D.x0 = nullptr;
                 D.H = H;
                 D.part = static_cast<double*>(part);
                 D.ldc = D.ldo = L / 2;
@@ -2060,6 +2075,7 @@ hank_status hank_transform_noalloc(int32_t task, const double* c, int64_t N, int
     p += al(PR.part_need);
     char* work = p;
     for (auto& D : PR.descs) {
+        D.x0 = D.x0off >= 0 ? work + D.x0off : nullptr;
         D.buf = work + reinterpret_cast<size_t>(D.buf);
         if (D.nchunk > 1) D.part = reinterpret_cast<double*>(fpart + reinterpret_cast<size_t>(D.part));
     }

@@ -130,6 +130,12 @@ struct FarDesc {
     int64_t ldc, ldo;
     int64_t wg_ac, wg_b, wg_r;
     int32_t nrhs, nchunk, gchunk, pad;
+    // Blocks of at most L1 = 4096 columns on the FP64 wave-column/row kernels:
+    // pass A stores only each column's one nonzero input, x0[j][g][j1] (j1 <
+    // ncols), and pass B forms its rows from it; x0off is its offset in the
+    // work area (-1: not used), x0 the address.
+    int64_t x0off;
+    void* x0;
 };
 
 hipError_t upload_tables(const DeviceTables& t);

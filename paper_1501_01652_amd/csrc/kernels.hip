@@ -1263,6 +1263,7 @@ __device__ __forceinline__ void pass_aw_row0(const FarDesc& D, const FarItem& mp
     const int64_t j1 = jb + cw;
     const int ng = A.g1 - A.g0;
     const auto buf = gview((cx<F>*)D.buf);
+    const auto x0 = gview((cx<F>*)D.x0); // (null: the full columns)
     const int j = mp.j;
     double vw = 1.0, xb = 0.0, la = 0.0;
     cx<double> qb = mk(0.0, 0.0);
@@ -1279,7 +1280,7 @@ __device__ __forceinline__ void pass_aw_row0(const FarDesc& D, const FarItem& mp
                     sqrt(iw) * gview(D.c)[(int64_t)j * D.ldc + n - 1]);
     }
     cx<F> tw[R];
-    {
+    if (!x0) {
         cx<double> w = tw_big<double>(j1 * q, A.twshift);
         const cx<double> ws = tw_big<double>(j1 * 64, A.twshift);
 #pragma unroll
@@ -1314,6 +1315,10 @@ __device__ __forceinline__ void pass_aw_row0(const FarDesc& D, const FarItem& mp
         }
         const cx<double> y = cmul(mk(Xr * pw, Xi * pw), qb);
         const cx<F> yf = mk(F(y.x), F(y.y));
+        if (x0) { // pass B forms the rows from this value
+            if (q == 0 && j1 < A.ncols) gstore(x0 + ((int64_t)j * ng + (g - A.g0)) * A.ncols + j1, yf);
+            continue;
+        }
         const auto out = buf + ((int64_t)j * ng + (g - A.g0)) * A.L + jb + cw;
 #pragma unroll
         for (int r = 0; r < R; ++r) gstore(out + (int64_t)(q + 64 * r) * A.L1, cmul(yf, tw[r]));
@@ -1709,11 +1714,25 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         lmask |= uint32_t(t + 512 * a < A.ncols) << a;
         smask |= uint32_t(t + 512 * a < A.nrows) << a;
     }
+    const auto x0 = gview((const cx<F>*)D.x0);
     for (int gq = gs; gq < ge; ++gq) {
         const auto p = buf + ((int64_t)mp.j * ng + gq) * A.L + row * L1;
         cx<F> v[8];
+        if (x0) {
+            // a block of at most L1 columns: the row is x0(j1) e^{-2 pi i j1 row / L},
+            // j1 = t + 512 a < ncols (what pass A would have stored)
+            const auto xr = x0 + ((int64_t)mp.j * ng + gq) * A.ncols;
+            cx<double> w = tw_big<double>((int64_t)t * row, A.twshift);
+            const cx<double> ws = tw_big<double>((int64_t)512 * row, A.twshift);
 #pragma unroll
-        for (int a = 0; a < 8; ++a) v[a] = (lmask >> a) & 1 ? gload(p + t + 512 * a) : mk(F(0), F(0));
+            for (int a = 0; a < 8; ++a) {
+                v[a] = (lmask >> a) & 1 ? cmul(gload(xr + t + 512 * a), mk(F(w.x), F(w.y))) : mk(F(0), F(0));
+                if (a + 1 < 8) w = cmul(w, ws);
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < 8; ++a) v[a] = (lmask >> a) & 1 ? gload(p + t + 512 * a) : mk(F(0), F(0));
+        }
         row8x512_forward<F, SR>(v, sh, t, lane, wv);
 #pragma unroll
         for (int s = 0; s < 8; ++s) v[s] = cmul(v[s], hv[s]);
