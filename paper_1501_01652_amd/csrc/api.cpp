@@ -273,10 +273,8 @@ NearRule near_rule(const Plan& p) {
     r.mix6 = r.zM[3] <= J0_ASY_Z;
     r.small8 = e >= 1.25e-9;
     // |e^{i rho} - (1 + i rho)| <= rho^2/2 times an amplitude <= 0.2 (z >= 20):
-    // at most eps/64 per entry for rho <= sqrt(eps/6.4).  Only k_near has these
-    // variants: plans for several right-hand sides (k_near_multi) keep the
-    // full factor.
-    r.rho1 = (p.direct || p.nrhs > 1) ? 0.0 : std::sqrt(p.eps / 6.4);
+    // at most eps/64 per entry for rho <= sqrt(eps/6.4)
+    r.rho1 = p.direct ? 0.0 : std::sqrt(p.eps / 6.4);
     return r;
 }
 

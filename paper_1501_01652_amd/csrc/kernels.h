@@ -39,8 +39,7 @@ constexpr int NEAR_TILE_COLS = 2048;
 // NV_*R: the same with the residual phase factor e^{i rho}, rho = (e_k + r^_k) b_n,
 // taken to first order, 1 + i rho, for blocks where rho <= sqrt(eps/6.4): the
 // dropped terms are below rho^2/2 times the amplitude (<= 0.2 at z >= 20), so
-// below eps/64 per entry (the multiple-right-hand-side kernel runs the full
-// factor).
+// below eps/64 per entry.
 enum NearVariant {
     NV_SMALL = 0, NV_MIX12, NV_MIX6, NV_M2, NV_M3, NV_M4, NV_M6, NV_M8, NV_M12,
     NV_SMALL8, NV_MIX12_8, NV_MIX6_8, NV_M2R, NV_M3R, NV_M4R, NV_MIX6_8R, NV_COUNT

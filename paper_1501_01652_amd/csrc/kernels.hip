@@ -508,7 +508,7 @@ constexpr int CS_LD = 80; // row stride of the coefficient tile (16 mod 32 banks
 #ifndef HANK_MULTI_STAGE
 #define HANK_MULTI_STAGE 1
 #endif
-template <int M, bool SMALL, bool ASY, bool PERT>
+template <int M, bool SMALL, bool ASY, bool PERT, bool ROT1 = false>
 __device__ __forceinline__ void near_multi_block(const GridArgs& G, NearLane& R, const double (*Cs)[CS_LD],
                                                  const double* Bs, double* Js, int64_t nb, int64_t n1, int kq,
                                                  int lane, int nblk, v4d (&acc)[4]) {
@@ -517,7 +517,7 @@ __device__ __forceinline__ void near_multi_block(const GridArgs& G, NearLane& R,
     HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
     for (int i = 0; i < 16; ++i) {
         const int col = 4 * i + kq;
-        const double J = near_step<M, SMALL, ASY, PERT>(G, R, PERT ? Bs[col] : 0.0);
+        const double J = near_step<M, SMALL, ASY, PERT, J0_TAYLOR_DEG, false, ROT1>(G, R, PERT ? Bs[col] : 0.0);
         Js[64 * i + lane] = (R.active && nb + col < n1) ? J : 0.0;
     }
 #pragma unroll 1
@@ -569,10 +569,16 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
         }
         __syncthreads();
 #define BLOCK(M_, S_, A_) near_multi_block<M_, S_, A_, PERT>(G, R, Cs, Bs, Js + 1024 * wave, nb, T.n1, kq, lane, nblk, acc); break
-        // the 8-term small-argument codes run in full here
+        // the 8-term small-argument codes run in full here (with the first-order
+        // residual factor where the code says so)
         int var = tile_block_variant(bv, T.n0, nb);
         var = var == NV_SMALL8 ? NV_SMALL : var == NV_MIX12_8 ? NV_MIX12 : var == NV_MIX6_8 ? NV_MIX6 : var;
+#define BLOCKR(M_, S_, A_) near_multi_block<M_, S_, A_, PERT, PERT>(G, R, Cs, Bs, Js + 1024 * wave, nb, T.n1, kq, lane, nblk, acc); break
         switch (var) {
+        case NV_M2R: BLOCKR(2, false, true);
+        case NV_M3R: BLOCKR(3, false, true);
+        case NV_M4R: BLOCKR(4, false, true);
+        case NV_MIX6_8R: BLOCKR(6, true, true);
         case NV_SMALL: BLOCK(3, true, false);
         case NV_MIX12: BLOCK(12, true, true);
         case NV_MIX6: BLOCK(6, true, true);
@@ -583,6 +589,7 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
         case NV_M8: BLOCK(8, false, true);
         default: BLOCK(12, false, true);
         }
+#undef BLOCKR
 #undef BLOCK
         near_skip16(R);
         __syncthreads();

@@ -89,6 +89,22 @@ def test_dht0_2pow20_fp64_headline():
     check("dht0", N, eps, c, rows, "tuned, FP64 transforms", precision=1)
 
 
+def test_dht0_2pow20_several_rhs():
+    """Four right-hand sides at N = 2^20 (a plan for several right-hand sides:
+    k_near_multi, and far passes over every column's groups, the strip block's
+    compact inputs indexed per right-hand side): each column against the oracle."""
+    N, eps, nrhs = 1 << 20, 1e-8, 4
+    C = np.stack([inputs.coefficients("gauss", N, inputs.SEED_DHT0 + j) for j in range(nrhs)])
+    rows = inputs.sampled_rows(N, 24, boundary_rows("dht0", N, eps, precision=1, nrhs=nrhs))
+    F = host(hank.transform("dht0", dev(C), eps, precision=1))
+    for j in range(nrhs):
+        ref = oracle.eval_rows("dht0", C[j], rows=rows)
+        err = float(np.max(np.abs(F[j][rows - 1] - ref)))
+        Cm = err / (eps * float(np.sum(np.abs(C[j]))))
+        print("dht0 N=%d eps=%g rhs %d of %d: rows=%d max err %.3e measured C=%.3g" % (N, eps, j, nrhs, len(rows), err, Cm))
+        assert Cm <= C_TOL
+
+
 def test_dht0_2pow20_paper_plan():
     N, eps = 1 << 20, 1e-8
     c = inputs.workload("dht0", N)
