@@ -160,7 +160,7 @@ def parse():
     ap.add_argument("--plan-mode", type=int, default=0)
     ap.add_argument("--precision", type=int, default=1,
                     help="1: every far transform in FP64 (the headline); 0: the library's automatic choice")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
