@@ -270,6 +270,31 @@ __device__ __forceinline__ void near_skip16(NearLane& r) {
     if (r.ir >= r.D2) r.ir -= r.D2;
 }
 
+// The first M coefficients of P and Q with sqrt(2/pi) folded in, held in
+// scalar registers from the start of a block: as the addends of the Horner
+// steps they are operands of three-address v_fma_f64 (constants the compiler
+// keeps in vector registers are copied into the accumulator of v_fmac_f64 at
+// every use instead).  The empty asm statements only pin the values to scalar
+// registers once, outside the step loops.
+template <int M>
+struct HankelSet {
+    double p[M], q[M];
+};
+template <int M>
+__device__ __forceinline__ HankelSet<M> hankel_set() {
+    constexpr Hankel0 H = make_hankel0(0.79788456080286535588);
+    HankelSet<M> h;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        double a = H.p[m], b = H.q[m];
+        asm("" : "+s"(a));
+        asm("" : "+s"(b));
+        h.p[m] = a;
+        h.q[m] = b;
+    }
+    return h;
+}
+
 // Hankel expansion (Sec. 3.1, M pairs of terms) at the lane's current column;
 // bn = b_n (0 without column perturbations).  z only sets the amplitude and
 // the P, Q series, so it is formed to working precision.
@@ -278,8 +303,8 @@ __device__ __forceinline__ void near_skip16(NearLane& r) {
 // ROT1: the residual factor e^{i rho} to first order, 1 + i rho (blocks whose
 // rho is small enough, chosen on the host).
 template <int M, bool PERT, bool LEAN = false, bool ROT1 = false>
-__device__ __forceinline__ double near_asy(const GridArgs& G, const NearLane& r, double bn) {
-    constexpr Hankel0 H = make_hankel0(0.79788456080286535588); // sqrt(2/pi) folded in
+__device__ __forceinline__ double near_asy(const GridArgs& G, const NearLane& r, double bn,
+                                           const HankelSet<M>& H) {
     const double delta = PERT ? fma(r.ek, fma(r.Nd, G.pi_Qc, bn), r.rk * bn) : 0.0;
     const double z = fma(r.Kd * r.Nd, G.piD_hi, delta);
     const double y = rsqrt_nr(z, LEAN), zi = y * y, zi2 = zi * zi;
@@ -316,18 +341,18 @@ __device__ __forceinline__ double near_z_exact(const GridArgs& G, const NearLane
 // (both branches: each lane takes its own, so a wave pays for both only where
 // its rows straddle z = 20)
 template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG, bool LEAN = false, bool ROT1 = false>
-__device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, double bn) {
+__device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, double bn, const HankelSet<M>& H) {
     double J;
     if (SMALL && ASY) {
         const double z = near_z_exact(G, r, bn);
         if (z < J0_ASY_Z)
             J = j0_small<NT>(z);
         else
-            J = near_asy<M, PERT, LEAN, ROT1>(G, r, bn);
+            J = near_asy<M, PERT, LEAN, ROT1>(G, r, bn, H);
     } else if (SMALL) {
         J = j0_small<NT>(near_z_exact(G, r, bn));
     } else {
-        J = near_asy<M, PERT, LEAN, ROT1>(G, r, bn);
+        J = near_asy<M, PERT, LEAN, ROT1>(G, r, bn, H);
     }
     if (ASY) r.u = cmul(r.u, r.w);
     r.Nd += r.dNd;
@@ -364,10 +389,11 @@ __device__ __forceinline__ int tile_block_variant(const uint32_t* bv, int64_t n0
 template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG, bool LEAN = false, bool ROT1 = false>
 __device__ __forceinline__ void near_block(const GridArgs& G, const ColCB* p, int cnt, NearLane& r, double& acc) {
     if (ASY) near_anchor(G, r);
+    const HankelSet<M> H = hankel_set<M>();
     HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
     for (int i = 0; i < cnt; ++i) {
         const ColCB v = p[4 * i];
-        acc = fma(v.c, near_step<M, SMALL, ASY, PERT, NT, LEAN, ROT1>(G, r, PERT ? v.b : 0.0), acc);
+        acc = fma(v.c, near_step<M, SMALL, ASY, PERT, NT, LEAN, ROT1>(G, r, PERT ? v.b : 0.0, H), acc);
     }
 }
 
@@ -513,11 +539,12 @@ __device__ __forceinline__ void near_multi_block(const GridArgs& G, NearLane& R,
                                                  const double* Bs, double* Js, int64_t nb, int64_t n1, int kq,
                                                  int lane, int nblk, v4d (&acc)[4]) {
     if (ASY) near_anchor(G, R);
+    const HankelSet<M> H = hankel_set<M>();
 #if HANK_MULTI_STAGE
     HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
     for (int i = 0; i < 16; ++i) {
         const int col = 4 * i + kq;
-        const double J = near_step<M, SMALL, ASY, PERT, J0_TAYLOR_DEG, false, ROT1>(G, R, PERT ? Bs[col] : 0.0);
+        const double J = near_step<M, SMALL, ASY, PERT, J0_TAYLOR_DEG, false, ROT1>(G, R, PERT ? Bs[col] : 0.0, H);
         Js[64 * i + lane] = (R.active && nb + col < n1) ? J : 0.0;
     }
 #pragma unroll 1
@@ -533,7 +560,7 @@ __device__ __forceinline__ void near_multi_block(const GridArgs& G, NearLane& R,
     HANK_PRAGMA(unroll HANK_MULTI_UNROLL)
     for (int i = 0; i < 16; ++i) {
         const int col = 4 * i + kq;
-        double J = near_step<M, SMALL, ASY, PERT>(G, R, PERT ? Bs[col] : 0.0);
+        double J = near_step<M, SMALL, ASY, PERT>(G, R, PERT ? Bs[col] : 0.0, H);
         J = (R.active && nb + col < n1) ? J : 0.0;
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb)
