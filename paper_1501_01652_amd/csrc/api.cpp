@@ -50,7 +50,7 @@ hank_status fail(hank_status s, const std::string& msg) {
 // Columns per near-field work item.  A tile's columns are a serial loop, so
 // the widest tile bounds the launch: the width is the largest of 2048, 1024,
 // ..., 64 whose 64-row tile holds no more than the average work of one of the
-// 768 workgroups the chip keeps resident (256 compute units x 3; occupancy of
+// 1024 workgroups the chip keeps resident (256 compute units x 4; occupancy of
 // the near kernel).  Small problems then fill the chip with short tiles and
 // large ones keep the per-row reduction short.  HANK_NEAR_COLS fixes it.
 int64_t near_chunk(const std::vector<NearSeg>& segs) {
@@ -61,7 +61,7 @@ int64_t near_chunk(const std::vector<NearSeg>& segs) {
     if (fixed) return fixed;
     double entries = 0;
     for (auto& seg : segs) entries += double(seg.k1 - seg.k0) * double(seg.ncut - 1);
-    const double resident = 768.0;
+    const double resident = 1024.0;
     int64_t chunk = NEAR_TILE_COLS;
     while (chunk > 64 && 64.0 * double(chunk) * resident > entries) chunk /= 2;
     return chunk;

@@ -360,14 +360,15 @@ __device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, doub
 }
 
 // Build knobs (measured variants): unroll of the near-field column loop, and
-// a lower bound on waves per SIMD for k_near (0: the compiler's choice; 3
-// keeps it below 168 registers at the price of a small spill, which measured
-// faster than 2 waves without).
+// a lower bound on waves per SIMD for k_near (0: the compiler's choice).  With
+// the Hankel coefficients in scalar registers the kernel fits 4 waves (at most
+// 128 registers) without spilling, which measured 4% faster at N = 2^20 than
+// 3 (slower by up to 10% on the small all-near Schlomilch N = 4096).
 #ifndef HANK_NEAR_UNROLL
 #define HANK_NEAR_UNROLL 4
 #endif
 #ifndef HANK_NEAR_WPE
-#define HANK_NEAR_WPE 3
+#define HANK_NEAR_WPE 4
 #endif
 #define HANK_STR2(x) #x
 #define HANK_PRAGMA(x) _Pragma(HANK_STR2(x))
