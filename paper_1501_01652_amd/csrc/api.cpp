@@ -360,8 +360,12 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
                 t.nk = r.nk;
                 t.n0 = n;
                 t.n1 = std::min(seg.ncut, n + chunk);
+                // k_near also evaluates the columns from n1 up to the next
+                // multiple of 4 past n0 (with c = 0): the last block's variant
+                // covers them too
+                const int64_t n1p = t.n0 + ((t.n1 - t.n0 + 3) & ~int64_t(3));
                 for (int64_t nb = t.n0, b = 0; nb < t.n1; nb += 64, ++b) {
-                    const int v = near_block_variant(g, rule, t.k0, t.k0 + t.nk - 1, nb, std::min(nb + 63, t.n1 - 1));
+                    const int v = near_block_variant(g, rule, t.k0, t.k0 + t.nk - 1, nb, std::min(nb + 63, n1p - 1));
                     t.bvar[b >> 3] |= uint32_t(v) << (4 * (b & 7));
                 }
                 t.slot = int64_t(tiles.size());

@@ -145,6 +145,29 @@ __device__ __forceinline__ double j0_small(double z) {
     return p;
 }
 
+// j0_small with the Taylor pieces read from a copy of their first NT
+// coefficients in LDS, LD doubles per piece (the series part below z = 2 has
+// one set of coefficients for every lane and stays in the global table)
+template <int NT, int LD>
+__device__ __forceinline__ double j0_small_tab(double z, const double* tl) {
+    static_assert(NT <= LD && NT <= J0_SERIES_TERMS, "table size");
+    if (z < J0_TAYLOR_Z0) {
+        double w = 0.25 * z * z;
+        double p = g_tab.ser[NT - 1];
+#pragma unroll
+        for (int k = NT - 2; k >= 0; --k) p = fma(p, w, g_tab.ser[k]);
+        return p;
+    }
+    int i = (int)((z - J0_TAYLOR_Z0) * (1.0 / J0_TAYLOR_H));
+    i = i < 0 ? 0 : (i >= J0_TAYLOR_INTERVALS ? J0_TAYLOR_INTERVALS - 1 : i);
+    double dz = z - (J0_TAYLOR_Z0 + (i + 0.5) * J0_TAYLOR_H);
+    const double* t = tl + i * LD;
+    double p = t[NT - 1];
+#pragma unroll
+    for (int u = NT - 2; u >= 0; --u) p = fma(p, dz, t[u]);
+    return p;
+}
+
 // Hankel P_nu, Q_nu (Sec. 3.1) with M = mterms pairs, at zi = 1/z.
 __device__ __forceinline__ void hankel_pq(int nu, double zi, int mterms, double* P, double* Q) {
     double zi2 = zi * zi;

@@ -198,6 +198,27 @@ __device__ __forceinline__ void sincos_tiny(double x, double* s, double* c, bool
     *c = fma(x2, fma(x2, fma(x2, fma(x2, 1.0 / 40320.0, -1.0 / 720.0), 1.0 / 24.0), -0.5), 1.0);
 }
 
+// Workgroup-uniform read-only records (a block's group and term tables, a
+// near-field tile) read through the constant address space from a
+// readfirstlane'd base: their fields then come through scalar loads into
+// scalar registers, and the loops they drive are uniform branches instead of
+// masked vector loops.
+template <typename T>
+__device__ __forceinline__ T scalar_entry(const T* p, int i) {
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    typedef const __attribute__((address_space(4))) uint32_t cword;
+    const uint64_t a = reinterpret_cast<uint64_t>(p + i);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    cword* q = reinterpret_cast<cword*>(((uint64_t)hi << 32) | lo);
+    uint32_t w[sizeof(T) / 4];
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) w[k] = q[k];
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
+
 // Index of the last of n descriptors whose grid offset (member M) is <= bid:
 // the descriptor of workgroup bid (offsets are non-decreasing; a descriptor
 // with no workgroups is never the last one at or below a valid bid).
@@ -221,9 +242,11 @@ __device__ __forceinline__ int find_desc(const T* __restrict__ d, int n, int64_t
 // where ir_n = K_k N_n mod 2D is exact.  L_n grows by the same amount at every
 // step, so u = e^{i pi L_n} is advanced by one complex rotation w and set
 // afresh every 16 steps; e^{i rho_n} comes from sincos_tiny (b_n <= b_1 < 0.05).
-// Integers (ir, N_n) are carried exactly in doubles.
+// Integers (ir, N_n) are carried exactly in doubles.  For the amplitude and
+// the P, Q series z is formed as al N_n + s_k b_n, al = pi K_k / D + pi e_k / Qc,
+// s_k = e_k + r^_k (working precision, one FMA per column).
 struct NearLane {
-    double Kd, rk, ek, sk;
+    double Kd, al, ek, sk;
     double ir, ir16, D2;
     double Nd, dNd;
     cx<double> u, w;
@@ -240,9 +263,10 @@ __device__ __forceinline__ NearLane near_lane(const GridArgs& G, const double* _
     const int64_t Nn = G.ac * n + G.bc;
     const int64_t step = (K * 4 * G.ac) % D2;
     r.Kd = (double)K;
-    r.rk = r.Kd / (double)G.Dr;
+    const double rk = r.Kd / (double)G.Dr;
     r.ek = G.row_pert ? evec[k - 1] : 0.0;
-    r.sk = r.ek + r.rk;
+    r.sk = r.ek + rk;
+    r.al = fma(r.ek, G.pi_Qc, r.Kd * G.piD_hi);
     r.ir = (double)((K * Nn) % D2);
     r.ir16 = (double)((16 * step) % D2);
     r.D2 = (double)D2;
@@ -305,8 +329,9 @@ __device__ __forceinline__ HankelSet<M> hankel_set() {
 template <int M, bool PERT, bool LEAN = false, bool ROT1 = false>
 __device__ __forceinline__ double near_asy(const GridArgs& G, const NearLane& r, double bn,
                                            const HankelSet<M>& H) {
-    const double delta = PERT ? fma(r.ek, fma(r.Nd, G.pi_Qc, bn), r.rk * bn) : 0.0;
-    const double z = fma(r.Kd * r.Nd, G.piD_hi, delta);
+    // z = z~ + e_k (w^_n + b_n) + r^_k b_n = al N_n + rho, rho = s_k b_n
+    const double x = PERT ? r.sk * bn : 0.0;
+    const double z = PERT ? fma(r.al, r.Nd, x) : r.al * r.Nd;
     const double y = rsqrt_nr(z, LEAN), zi = y * y, zi2 = zi * zi;
     double P = H.p[M - 1], Q = H.q[M - 1];
 #pragma unroll
@@ -316,12 +341,11 @@ __device__ __forceinline__ double near_asy(const GridArgs& G, const NearLane& r,
     }
     double cs = r.u.x, sn = r.u.y;
     if (PERT && ROT1) {
-        const double x = r.sk * bn;
         cs = fma(-r.u.y, x, r.u.x);
         sn = fma(r.u.x, x, r.u.y);
     } else if (PERT) {
         double s, c;
-        sincos_tiny(r.sk * bn, &s, &c, LEAN);
+        sincos_tiny(x, &s, &c, LEAN);
         cs = fma(r.u.x, c, -r.u.y * s);
         sn = fma(r.u.y, c, r.u.x * s);
     }
@@ -330,27 +354,50 @@ __device__ __forceinline__ double near_asy(const GridArgs& G, const NearLane& r,
 
 // z at the lane's current column with pi K N / D carried in two parts (the
 // small-argument branch needs it to absolute accuracy)
-__device__ __forceinline__ double near_z_exact(const GridArgs& G, const NearLane& r, double bn) {
-    const double delta = fma(r.ek, fma(r.Nd, G.pi_Qc, bn), r.rk * bn);
-    const double I = r.Kd * r.Nd; // exact: K_k N_n < 2^53
+__device__ __forceinline__ double near_z_at(const GridArgs& G, const NearLane& r, double Nd, double bn) {
+    const double delta = fma(r.ek * Nd, G.pi_Qc, r.sk * bn);
+    const double I = r.Kd * Nd; // exact: K_k N_n < 2^53
     const double pz = I * G.piD_hi;
     return (pz + (fma(I, G.piD_hi, -pz) + I * G.piD_lo)) + delta;
+}
+__device__ __forceinline__ double near_z_exact(const GridArgs& G, const NearLane& r, double bn) {
+    return near_z_at(G, r, r.Nd, bn);
+}
+
+// Taylor pieces of J_0 copied to LDS by k_near: the first TAY_LDS_NT
+// coefficients of each piece in rows of TAY_LDS_LD doubles (80 bytes: 16-byte
+// aligned for 128-bit reads, and the rows of neighbouring pieces start in
+// different banks).  Build knob HANK_TAYLOR_LDS: 0 reads the global table.
+#ifndef HANK_TAYLOR_LDS
+#define HANK_TAYLOR_LDS 0
+#endif
+constexpr int TAY_LDS_NT = 8, TAY_LDS_LD = 10;
+
+template <int NT, bool TL>
+__device__ __forceinline__ double near_j0_small(double z, const double* tl) {
+    if constexpr (TL)
+        return j0_small_tab<NT, TAY_LDS_LD>(z, tl);
+    else
+        return j0_small<NT>(z);
 }
 
 // J_0 at the lane's current column, then one step on
 // (both branches: each lane takes its own, so a wave pays for both only where
-// its rows straddle z = 20)
-template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG, bool LEAN = false, bool ROT1 = false>
-__device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, double bn, const HankelSet<M>& H) {
+// its rows straddle z = 20).  TL: the small-argument pieces come from the LDS
+// copy tl.
+template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG, bool LEAN = false, bool ROT1 = false,
+          bool TL = false>
+__device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, double bn, const HankelSet<M>& H,
+                                            const double* tl = nullptr) {
     double J;
     if (SMALL && ASY) {
         const double z = near_z_exact(G, r, bn);
         if (z < J0_ASY_Z)
-            J = j0_small<NT>(z);
+            J = near_j0_small<NT, TL>(z, tl);
         else
             J = near_asy<M, PERT, LEAN, ROT1>(G, r, bn, H);
     } else if (SMALL) {
-        J = j0_small<NT>(near_z_exact(G, r, bn));
+        J = near_j0_small<NT, TL>(near_z_exact(G, r, bn), tl);
     } else {
         J = near_asy<M, PERT, LEAN, ROT1>(G, r, bn, H);
     }
@@ -388,32 +435,59 @@ __device__ __forceinline__ int tile_block_variant(const uint32_t* bv, int64_t n0
 
 // One 64-column block of a sweep: the lane's columns p[0], p[4], ... (cnt of them)
 template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG, bool LEAN = false, bool ROT1 = false>
-__device__ __forceinline__ void near_block(const GridArgs& G, const ColCB* p, int cnt, NearLane& r, double& acc) {
+__device__ __forceinline__ void near_block(const GridArgs& G, const ColCB* p, int cnt, NearLane& r, double& acc,
+                                           const double* tl) {
+    constexpr bool TL = HANK_TAYLOR_LDS && SMALL && NT <= TAY_LDS_NT;
     if (ASY) near_anchor(G, r);
     const HankelSet<M> H = hankel_set<M>();
     HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
     for (int i = 0; i < cnt; ++i) {
         const ColCB v = p[4 * i];
-        acc = fma(v.c, near_step<M, SMALL, ASY, PERT, NT, LEAN, ROT1>(G, r, PERT ? v.b : 0.0, H), acc);
+        acc = fma(v.c, near_step<M, SMALL, ASY, PERT, NT, LEAN, ROT1, TL>(G, r, PERT ? v.b : 0.0, H, tl), acc);
     }
 }
 
-// Near-field sweep of one tile (one right-hand side) for the wave whose first
-// column is n: columns n, n+4, ... < T.n1, 16 per block of 64, coefficients
-// and root offsets read from LDS (cb[i] is column T.n0 + i).  The variant is
-// chosen per block (wave-uniform).
+// Internal code of the Hankel-only block with 6 pairs and the first-order
+// residual factor (the Hankel side of NV_MIX6_8R; never stored in a tile).
+constexpr int NV_M6R_WAVE = NV_COUNT;
+
+// A block the host marked as taking both branches (NV_MIX*) may lie on one
+// side of z = 20 for the 16 rows of this wave: z grows along a row, so the
+// lanes' first and last columns decide.  Returns the variant that evaluates
+// exactly the same branch for every entry of the wave: the small-argument or
+// the Hankel code alone, or the mixed one.
+__device__ __forceinline__ int near_refine_mix(int v, const GridArgs& G, const NearLane& r, const ColCB* p,
+                                               int cnt) {
+    const bool small = near_z_at(G, r, r.Nd, p[0].b) < J0_ASY_Z;
+    const bool asy = !(near_z_at(G, r, fma(double(cnt - 1), r.dNd, r.Nd), p[4 * (cnt - 1)].b) < J0_ASY_Z);
+    const bool any_small = __ballot(small) != 0;
+    const bool any_asy = __ballot(asy) != 0;
+    if (any_small && any_asy) return v;
+    const bool t8 = v == NV_MIX12_8 || v == NV_MIX6_8 || v == NV_MIX6_8R;
+    if (!any_asy) return t8 ? NV_SMALL8 : NV_SMALL;
+    return v == NV_MIX6_8R ? NV_M6R_WAVE : (v == NV_MIX12 || v == NV_MIX12_8) ? NV_M12 : NV_M6;
+}
+
+// Near-field sweep of one tile (one right-hand side) for the lane of column
+// phase ph: columns T.n0 + ph, +4, ..., 16 per block of 64, coefficients and
+// root offsets read from LDS (cb[i] is column T.n0 + i; the columns from T.n1
+// to the next multiple of 4 carry c = 0, so that every lane of a block takes
+// the same number of steps).  The variant is chosen per block (wave-uniform).
 template <bool PERT, bool LEAN>
 __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb, const uint32_t* bv,
-                                             const NearTile& T, int64_t n, NearLane& r) {
+                                             const double* tl, const NearTile& T, int ph, NearLane& r) {
     double acc = 0.0;
     for (int64_t nb = T.n0; nb < T.n1; nb += 64) {
-        const int64_t nw = n + (nb - T.n0);
-        const int cnt = (int)min<int64_t>(16, (T.n1 - nw + 3) / 4);
-        const ColCB* p = cb + (nw - T.n0);
-#define BLOCK(M_, S_, A_) near_block<M_, S_, A_, PERT, J0_TAYLOR_DEG, LEAN>(G, p, cnt, r, acc); break
-#define BLOCK8(M_, A_) near_block<M_, true, A_, PERT, 8, LEAN>(G, p, cnt, r, acc); break
-#define BLOCKR(M_, S_, A_, NT_) near_block<M_, S_, A_, PERT, NT_, LEAN, PERT>(G, p, cnt, r, acc); break
-        switch (tile_block_variant(bv, T.n0, nb)) {
+        const int cnt = ((int)min<int64_t>(64, T.n1 - nb) + 3) >> 2;
+        const ColCB* p = cb + (nb - T.n0) + ph;
+        int v = tile_block_variant(bv, T.n0, nb);
+        if (v == NV_MIX12 || v == NV_MIX6 || v == NV_MIX12_8 || v == NV_MIX6_8 || v == NV_MIX6_8R)
+            v = near_refine_mix(v, G, r, p, cnt);
+#define BLOCK(M_, S_, A_) near_block<M_, S_, A_, PERT, J0_TAYLOR_DEG, LEAN>(G, p, cnt, r, acc, tl); break
+#define BLOCK8(M_, A_) near_block<M_, true, A_, PERT, 8, LEAN>(G, p, cnt, r, acc, tl); break
+#define BLOCKR(M_, S_, A_, NT_) near_block<M_, S_, A_, PERT, NT_, LEAN, PERT>(G, p, cnt, r, acc, tl); break
+        switch (v) {
+        case NV_M6R_WAVE: BLOCKR(6, false, true, J0_TAYLOR_DEG);
         case NV_M2R: BLOCKR(2, false, true, J0_TAYLOR_DEG);
         case NV_M3R: BLOCKR(3, false, true, J0_TAYLOR_DEG);
         case NV_M4R: BLOCKR(4, false, true, J0_TAYLOR_DEG);
@@ -439,12 +513,13 @@ __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb,
     return acc;
 }
 
-// One workgroup = 64 rows (one per lane) x a column range of at most
-// NEAR_TILE_COLS; its 4 waves take every 4th column (the column data are
-// wave-uniform LDS reads) and their sums are added in a fixed order, into the
-// tile's partial slot or, for the only tile of its rows, into f.  One kernel
-// serves every variant, so that tiles of all kinds share a launch and fill
-// the chip together.
+// One workgroup = 64 rows x a column range of at most NEAR_TILE_COLS.  Wave w
+// takes rows 16w .. 16w+15 of the tile (lane l: row 16w + l%16) and lane l
+// every 4th column from phase l/16, so a wave's rows straddle z = 20 over
+// fewer columns than 64 rows would; the four phase sums of a row are added in
+// a fixed order, into the tile's partial slot or, for the only tile of its
+// rows, into f.  One kernel serves every variant, so that tiles of all kinds
+// share a launch and fill the chip together.
 __global__ __launch_bounds__(256)
 #if HANK_NEAR_WPE
 __attribute__((amdgpu_waves_per_eu(HANK_NEAR_WPE)))
@@ -453,8 +528,9 @@ void k_near(const NearProb* __restrict__ probs, int nprob, double* __restrict__ 
     __shared__ ColCB cb[NEAR_TILE_COLS];
     __shared__ double red[4][64];
     __shared__ uint32_t sbv[4];
+    __shared__ __align__(16) double tl[HANK_TAYLOR_LDS ? J0_TAYLOR_INTERVALS * TAY_LDS_LD : 2];
     const NearProb& P = probs[find_desc<NearProb, &NearProb::tile_start>(probs, nprob, blockIdx.x)];
-    const NearTile T = P.tiles[blockIdx.x - P.tile_start];
+    const NearTile T = scalar_entry(P.tiles, (int)(blockIdx.x - P.tile_start));
     if (threadIdx.x < 4) sbv[threadIdx.x] = P.tiles[blockIdx.x - P.tile_start].bvar[threadIdx.x];
     double* out = partial + P.pbase + T.slot * 64;
     const GridArgs G = P.G; // by value: scalar registers, loaded once
@@ -462,22 +538,27 @@ void k_near(const NearProb* __restrict__ probs, int nprob, double* __restrict__ 
     const auto bvec = gview(P.b);
     const double* evec = P.e;
     const int ncol = (int)(T.n1 - T.n0);
-    for (int i = threadIdx.x; i < ncol; i += 256) {
-        ColCB v;
-        v.c = c[T.n0 - 1 + i];
-        v.b = G.col_pert ? bvec[T.n0 - 1 + i] : 0.0;
+    for (int i = threadIdx.x; i < ((ncol + 3) & ~3); i += 256) {
+        ColCB v{0.0, 0.0};
+        if (i < ncol) {
+            v.c = c[T.n0 - 1 + i];
+            v.b = G.col_pert ? bvec[T.n0 - 1 + i] : 0.0;
+        }
         cb[i] = v;
     }
+    if (HANK_TAYLOR_LDS)
+        for (int i = threadIdx.x; i < J0_TAYLOR_INTERVALS * TAY_LDS_NT; i += 256)
+            tl[(i / TAY_LDS_NT) * TAY_LDS_LD + i % TAY_LDS_NT] = g_tab.tay[i / TAY_LDS_NT][i % TAY_LDS_NT];
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t n = T.n0 + wave;
-    NearLane R = near_lane(G, evec, T, lane, n);
-    const double acc = G.col_pert ? (G.lean ? near_sweep<true, true>(G, cb, sbv, T, n, R)
-                                            : near_sweep<true, false>(G, cb, sbv, T, n, R))
-                                  : (G.lean ? near_sweep<false, true>(G, cb, sbv, T, n, R)
-                                            : near_sweep<false, false>(G, cb, sbv, T, n, R));
-    red[wave][lane] = R.active ? acc : 0.0;
+    const int row = 16 * wave + (lane & 15), ph = lane >> 4;
+    NearLane R = near_lane(G, evec, T, row, T.n0 + ph);
+    const double acc = G.col_pert ? (G.lean ? near_sweep<true, true>(G, cb, sbv, tl, T, ph, R)
+                                            : near_sweep<true, false>(G, cb, sbv, tl, T, ph, R))
+                                  : (G.lean ? near_sweep<false, true>(G, cb, sbv, tl, T, ph, R)
+                                            : near_sweep<false, false>(G, cb, sbv, tl, T, ph, R));
+    red[ph][row] = R.active ? acc : 0.0;
     __syncthreads();
     if (wave == 0) {
         const double v = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
@@ -887,26 +968,6 @@ __device__ __forceinline__ double ipow_d(double x, int e) {
         u >>= 1;
     }
     return inv ? 1.0 / r : r;
-}
-
-// A block's group and term tables as read-only, workgroup-uniform memory
-// (constant address space from a readfirstlane'd base): their entries then
-// come through scalar loads into scalar registers, and the loops they drive
-// are uniform branches instead of masked vector loops.
-template <typename T>
-__device__ __forceinline__ T scalar_entry(const T* p, int i) {
-    static_assert(sizeof(T) % 4 == 0, "whole words");
-    typedef const __attribute__((address_space(4))) uint32_t cword;
-    const uint64_t a = reinterpret_cast<uint64_t>(p + i);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
-    cword* q = reinterpret_cast<cword*>(((uint64_t)hi << 32) | lo);
-    uint32_t w[sizeof(T) / 4];
-#pragma unroll
-    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) w[k] = q[k];
-    T out;
-    __builtin_memcpy(&out, w, sizeof(T));
-    return out;
 }
 
 // LDS elements per column FFT buffer of the column passes: L2 + L2/8 made
