@@ -145,22 +145,17 @@ __device__ __forceinline__ double j0_small(double z) {
     return p;
 }
 
-// j0_small with the Taylor pieces read from a copy of their first NT
-// coefficients in LDS, LD doubles per piece (the series part below z = 2 has
-// one set of coefficients for every lane and stays in the global table)
+// J_0(z), 0 <= z < 20 (and up to a rounding above), from the first NT
+// coefficients of the Taylor pieces about 0.25, 0.75, ..., 19.75 held in
+// `tl` (LD doubles per piece, pieces 0-3 on [0, 2)): no series branch, and
+// the truncation error is that of the pieces above 2 (NT = 8: below
+// 0.25^8/8! < 3.8e-10, |J_0^(8)| <= 1)
 template <int NT, int LD>
 __device__ __forceinline__ double j0_small_tab(double z, const double* tl) {
-    static_assert(NT <= LD && NT <= J0_SERIES_TERMS, "table size");
-    if (z < J0_TAYLOR_Z0) {
-        double w = 0.25 * z * z;
-        double p = g_tab.ser[NT - 1];
-#pragma unroll
-        for (int k = NT - 2; k >= 0; --k) p = fma(p, w, g_tab.ser[k]);
-        return p;
-    }
-    int i = (int)((z - J0_TAYLOR_Z0) * (1.0 / J0_TAYLOR_H));
-    i = i < 0 ? 0 : (i >= J0_TAYLOR_INTERVALS ? J0_TAYLOR_INTERVALS - 1 : i);
-    double dz = z - (J0_TAYLOR_Z0 + (i + 0.5) * J0_TAYLOR_H);
+    static_assert(NT <= LD && NT <= J0_TAYLOR_DEG, "table size");
+    constexpr int NP = J0_TAYLOR0_PIECES + J0_TAYLOR_INTERVALS;
+    const int i = min((int)(z * (1.0 / J0_TAYLOR_H)), NP - 1);
+    const double dz = z - fma((double)i, J0_TAYLOR_H, 0.5 * J0_TAYLOR_H);
     const double* t = tl + i * LD;
     double p = t[NT - 1];
 #pragma unroll

@@ -364,14 +364,19 @@ __device__ __forceinline__ double near_z_exact(const GridArgs& G, const NearLane
     return near_z_at(G, r, r.Nd, bn);
 }
 
-// Taylor pieces of J_0 copied to LDS by k_near: the first TAY_LDS_NT
-// coefficients of each piece in rows of TAY_LDS_LD doubles (80 bytes: 16-byte
+// The 8-term small-argument step of k_near (budgets from 1.25e-9 up): Taylor
+// pieces on all of [0, 20) copied to LDS per workgroup, the first TAY_LDS_NT
+// coefficients of each in rows of TAY_LDS_LD doubles (80 bytes: 16-byte
 // aligned for 128-bit reads, and the rows of neighbouring pieces start in
-// different banks).  Build knob HANK_TAYLOR_LDS: 0 reads the global table.
+// different banks), and z in the working-precision form al N_n + rho of the
+// Hankel step (absolute error ~1e-14 below z = 20, far inside the budget),
+// which the branch between the two then shares.  Build knob HANK_TAYLOR_LDS:
+// 0 keeps the global table, the series below z = 2 and the compensated z.
 #ifndef HANK_TAYLOR_LDS
-#define HANK_TAYLOR_LDS 0
+#define HANK_TAYLOR_LDS 1
 #endif
 constexpr int TAY_LDS_NT = 8, TAY_LDS_LD = 10;
+constexpr int TAY_LDS_PIECES = J0_TAYLOR0_PIECES + J0_TAYLOR_INTERVALS;
 
 template <int NT, bool TL>
 __device__ __forceinline__ double near_j0_small(double z, const double* tl) {
@@ -381,23 +386,31 @@ __device__ __forceinline__ double near_j0_small(double z, const double* tl) {
         return j0_small<NT>(z);
 }
 
+// z for the branch at z = 20 and the small-argument step
+template <bool PERT, bool TL>
+__device__ __forceinline__ double near_z_small(const GridArgs& G, const NearLane& r, double Nd, double bn) {
+    if constexpr (TL)
+        return PERT ? fma(r.al, Nd, r.sk * bn) : r.al * Nd;
+    else
+        return near_z_at(G, r, Nd, bn);
+}
+
 // J_0 at the lane's current column, then one step on
 // (both branches: each lane takes its own, so a wave pays for both only where
-// its rows straddle z = 20).  TL: the small-argument pieces come from the LDS
-// copy tl.
+// its rows straddle z = 20).  TL: the small-argument step of the LDS pieces tl.
 template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG, bool LEAN = false, bool ROT1 = false,
           bool TL = false>
 __device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, double bn, const HankelSet<M>& H,
                                             const double* tl = nullptr) {
     double J;
     if (SMALL && ASY) {
-        const double z = near_z_exact(G, r, bn);
+        const double z = near_z_small<PERT, TL>(G, r, r.Nd, bn);
         if (z < J0_ASY_Z)
             J = near_j0_small<NT, TL>(z, tl);
         else
             J = near_asy<M, PERT, LEAN, ROT1>(G, r, bn, H);
     } else if (SMALL) {
-        J = near_j0_small<NT, TL>(near_z_exact(G, r, bn), tl);
+        J = near_j0_small<NT, TL>(near_z_small<PERT, TL>(G, r, r.Nd, bn), tl);
     } else {
         J = near_asy<M, PERT, LEAN, ROT1>(G, r, bn, H);
     }
@@ -456,10 +469,12 @@ constexpr int NV_M6R_WAVE = NV_COUNT;
 // lanes' first and last columns decide.  Returns the variant that evaluates
 // exactly the same branch for every entry of the wave: the small-argument or
 // the Hankel code alone, or the mixed one.
+template <bool PERT, bool TL>
 __device__ __forceinline__ int near_refine_mix(int v, const GridArgs& G, const NearLane& r, const ColCB* p,
                                                int cnt) {
-    const bool small = near_z_at(G, r, r.Nd, p[0].b) < J0_ASY_Z;
-    const bool asy = !(near_z_at(G, r, fma(double(cnt - 1), r.dNd, r.Nd), p[4 * (cnt - 1)].b) < J0_ASY_Z);
+    const bool small = near_z_small<PERT, TL>(G, r, r.Nd, p[0].b) < J0_ASY_Z;
+    const bool asy =
+        !(near_z_small<PERT, TL>(G, r, fma(double(cnt - 1), r.dNd, r.Nd), p[4 * (cnt - 1)].b) < J0_ASY_Z);
     const bool any_small = __ballot(small) != 0;
     const bool any_asy = __ballot(asy) != 0;
     if (any_small && any_asy) return v;
@@ -481,8 +496,10 @@ __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb,
         const int cnt = ((int)min<int64_t>(64, T.n1 - nb) + 3) >> 2;
         const ColCB* p = cb + (nb - T.n0) + ph;
         int v = tile_block_variant(bv, T.n0, nb);
-        if (v == NV_MIX12 || v == NV_MIX6 || v == NV_MIX12_8 || v == NV_MIX6_8 || v == NV_MIX6_8R)
-            v = near_refine_mix(v, G, r, p, cnt);
+        if (v == NV_MIX12 || v == NV_MIX6)
+            v = near_refine_mix<PERT, false>(v, G, r, p, cnt);
+        else if (v == NV_MIX12_8 || v == NV_MIX6_8 || v == NV_MIX6_8R)
+            v = near_refine_mix<PERT, HANK_TAYLOR_LDS != 0>(v, G, r, p, cnt);
 #define BLOCK(M_, S_, A_) near_block<M_, S_, A_, PERT, J0_TAYLOR_DEG, LEAN>(G, p, cnt, r, acc, tl); break
 #define BLOCK8(M_, A_) near_block<M_, true, A_, PERT, 8, LEAN>(G, p, cnt, r, acc, tl); break
 #define BLOCKR(M_, S_, A_, NT_) near_block<M_, S_, A_, PERT, NT_, LEAN, PERT>(G, p, cnt, r, acc, tl); break
@@ -528,7 +545,7 @@ void k_near(const NearProb* __restrict__ probs, int nprob, double* __restrict__ 
     __shared__ ColCB cb[NEAR_TILE_COLS];
     __shared__ double red[4][64];
     __shared__ uint32_t sbv[4];
-    __shared__ __align__(16) double tl[HANK_TAYLOR_LDS ? J0_TAYLOR_INTERVALS * TAY_LDS_LD : 2];
+    __shared__ __align__(16) double tl[HANK_TAYLOR_LDS ? TAY_LDS_PIECES * TAY_LDS_LD : 2];
     const NearProb& P = probs[find_desc<NearProb, &NearProb::tile_start>(probs, nprob, blockIdx.x)];
     const NearTile T = scalar_entry(P.tiles, (int)(blockIdx.x - P.tile_start));
     if (threadIdx.x < 4) sbv[threadIdx.x] = P.tiles[blockIdx.x - P.tile_start].bvar[threadIdx.x];
@@ -547,8 +564,11 @@ void k_near(const NearProb* __restrict__ probs, int nprob, double* __restrict__ 
         cb[i] = v;
     }
     if (HANK_TAYLOR_LDS)
-        for (int i = threadIdx.x; i < J0_TAYLOR_INTERVALS * TAY_LDS_NT; i += 256)
-            tl[(i / TAY_LDS_NT) * TAY_LDS_LD + i % TAY_LDS_NT] = g_tab.tay[i / TAY_LDS_NT][i % TAY_LDS_NT];
+        for (int i = threadIdx.x; i < TAY_LDS_PIECES * TAY_LDS_NT; i += 256) {
+            const int pc = i / TAY_LDS_NT, u = i % TAY_LDS_NT;
+            tl[pc * TAY_LDS_LD + u] =
+                pc < J0_TAYLOR0_PIECES ? g_tab.tay0[pc][u] : g_tab.tay[pc - J0_TAYLOR0_PIECES][u];
+        }
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

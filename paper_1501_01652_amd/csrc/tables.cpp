@@ -6,7 +6,9 @@
 //   with J_m(x) by Miller's backward recurrence (DLMF 3.6(vi)), the method the
 //   paper names for direct summation (Sec. 2.1), normalised by
 //   J_0 + 2 sum J_{2k} = 1.
-// * J_0 on [0, 2): the Taylor series (Sec. 3.2) coefficients (-1)^t/(t!)^2.
+// * J_0 on [0, 2): the Taylor series (Sec. 3.2) coefficients (-1)^t/(t!)^2,
+//   and Taylor polynomials about 0.25, 0.75, 1.25, 1.75 like those above (the
+//   near field's 8-term step uses pieces on all of [0, 20)).
 // * Hankel coefficients a_m(0), a_m(1) (Sec. 3.1) for the large-argument branch
 //   and the root iteration.
 // * FFT twiddles e^{-2 pi i t/2^13} and the two-level table of e^{-2 pi i t/2^23}.
@@ -105,6 +107,8 @@ void build_tables(DeviceTables& t) {
             t.tay[i][u] = double(d / fact);
         }
     }
+    // Taylor pieces on [0, 2)
+    for (int i = 0; i < J0_TAYLOR0_PIECES; ++i) taylor_coeffs(0, (i + 0.5L) * J0_TAYLOR_H, t.tay0[i]);
     // Hankel coefficients
     for (int nu = 0; nu < 2; ++nu) {
         long double a = 1.0L;

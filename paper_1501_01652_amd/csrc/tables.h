@@ -5,6 +5,7 @@ namespace hank {
 
 constexpr int J0_SERIES_TERMS = 14;     // sum_t (-1)^t (z^2/4)^t/(t!)^2 for z < 2
 constexpr int J0_TAYLOR_INTERVALS = 36; // [2, 20) in steps of 1/2
+constexpr int J0_TAYLOR0_PIECES = 4;    // [0, 2) in steps of 1/2 (the 8-term near-field step)
 constexpr int J0_TAYLOR_DEG = 14;       // coefficients per interval (degree 13)
 constexpr double J0_TAYLOR_Z0 = 2.0;
 constexpr double J0_TAYLOR_H = 0.5;
@@ -18,6 +19,7 @@ constexpr int TW_HI = TW_BIG / TW_LO;   // 2048
 struct DeviceTables {
     double ser[J0_SERIES_TERMS];
     double tay[J0_TAYLOR_INTERVALS][J0_TAYLOR_DEG];
+    double tay0[J0_TAYLOR0_PIECES][J0_TAYLOR_DEG];
     double hank[2][HANKEL_TERMS];
     double tw_small[TW_SMALL][2];
     double tw_hi[TW_HI][2];
