@@ -158,17 +158,21 @@ __global__ void k_j0(const double* z, int64_t n, double* out) {
 struct Hankel0 {
     double p[12], q[12];
 };
-// coefficients of P_0 and Q_0 (Sec. 3.1), times `scale`
-constexpr Hankel0 make_hankel0(double scale = 1.0) {
+// coefficients of P_0 and Q_0 (Sec. 3.1), times `scale`; for the scaled
+// amplitude Y = S z^{-1/2} (S a power of two, so the scaling is exact) the
+// j-th coefficient of P is divided by S^(4j+1) and that of Q by S^(4j+3):
+// with Z = Y^2, W = Z^2, Y (cos P'(W) - sin Z Q'(W)) is the unscaled form
+constexpr Hankel0 make_hankel0(double scale = 1.0, double S = 1.0) {
     Hankel0 h{};
-    double a = scale;
+    double a = scale, d = S; // d = S^(2m+1): 4j+1 for P (m = 2j), 4j+3 for Q (m = 2j+1)
     for (int m = 0; m < 24; ++m) {
         if (m > 0) a *= -double(2 * m - 1) * double(2 * m - 1) / (8.0 * m);
         const double sg = ((m / 2) & 1) ? -1.0 : 1.0;
         if (m & 1)
-            h.q[m / 2] = sg * a;
+            h.q[m / 2] = sg * a / d;
         else
-            h.p[m / 2] = sg * a;
+            h.p[m / 2] = sg * a / d;
+        d *= S * S;
     }
     return h;
 }
@@ -184,6 +188,17 @@ __device__ __forceinline__ double rsqrt_nr(double z, bool lean) {
     return y;
 }
 __device__ __forceinline__ double rsqrt_full(double z) { return rsqrt_nr(z, false); }
+
+// Y = S z^{-1/2} by the same Newton steps with the factor 1/2 left out
+// (S = 2 after one step, 16 after two; make_hankel0 folds S into the
+// coefficients): one multiplication per step fewer
+__device__ __forceinline__ double rsqrt_scaled(double z, bool lean) {
+    const double y = __builtin_amdgcn_rsq(z);
+    const double Y = y * fma(-z * y, y, 3.0);
+    if (lean) return Y;
+    return Y * fma(-z * Y, Y, 12.0);
+}
+constexpr double rsqrt_scale(bool lean) { return lean ? 2.0 : 16.0; }
 
 // sin and cos of a residual phase |x| < 0.06 (Taylor; the first omitted terms
 // are below 1e-17; lean, the series to x^5 and x^4: below 6.5e-11)
@@ -304,9 +319,9 @@ template <int M>
 struct HankelSet {
     double p[M], q[M];
 };
-template <int M>
+template <int M, bool LEAN = false>
 __device__ __forceinline__ HankelSet<M> hankel_set() {
-    constexpr Hankel0 H = make_hankel0(0.79788456080286535588);
+    constexpr Hankel0 H = make_hankel0(0.79788456080286535588, rsqrt_scale(LEAN));
     HankelSet<M> h;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -332,12 +347,13 @@ __device__ __forceinline__ double near_asy(const GridArgs& G, const NearLane& r,
     // z = z~ + e_k (w^_n + b_n) + r^_k b_n = al N_n + rho, rho = s_k b_n
     const double x = PERT ? r.sk * bn : 0.0;
     const double z = PERT ? fma(r.al, r.Nd, x) : r.al * r.Nd;
-    const double y = rsqrt_nr(z, LEAN), zi = y * y, zi2 = zi * zi;
+    // H holds the coefficients for Y = S z^{-1/2}, Z = Y^2, W = Z^2
+    const double Y = rsqrt_scaled(z, LEAN), Z = Y * Y, W = Z * Z;
     double P = H.p[M - 1], Q = H.q[M - 1];
 #pragma unroll
     for (int m = M - 2; m >= 0; --m) {
-        P = fma(P, zi2, H.p[m]);
-        Q = fma(Q, zi2, H.q[m]);
+        P = fma(P, W, H.p[m]);
+        Q = fma(Q, W, H.q[m]);
     }
     double cs = r.u.x, sn = r.u.y;
     if (PERT && ROT1) {
@@ -349,7 +365,7 @@ __device__ __forceinline__ double near_asy(const GridArgs& G, const NearLane& r,
         cs = fma(r.u.x, c, -r.u.y * s);
         sn = fma(r.u.y, c, r.u.x * s);
     }
-    return y * fma(cs, P, -sn * (Q * zi));
+    return Y * fma(cs, P, -sn * (Q * Z));
 }
 
 // z at the lane's current column with pi K N / D carried in two parts (the
@@ -449,10 +465,10 @@ __device__ __forceinline__ int tile_block_variant(const uint32_t* bv, int64_t n0
 // One 64-column block of a sweep: the lane's columns p[0], p[4], ... (cnt of them)
 template <int M, bool SMALL, bool ASY, bool PERT, int NT = J0_TAYLOR_DEG, bool LEAN = false, bool ROT1 = false>
 __device__ __forceinline__ void near_block(const GridArgs& G, const ColCB* p, int cnt, NearLane& r, double& acc,
-                                           const double* tl) {
+                                           const double* tl, bool anchor) {
     constexpr bool TL = HANK_TAYLOR_LDS && SMALL && NT <= TAY_LDS_NT;
-    if (ASY) near_anchor(G, r);
-    const HankelSet<M> H = hankel_set<M>();
+    if (ASY && anchor) near_anchor(G, r);
+    const HankelSet<M> H = hankel_set<M, LEAN>();
     HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
     for (int i = 0; i < cnt; ++i) {
         const ColCB v = p[4 * i];
@@ -483,15 +499,27 @@ __device__ __forceinline__ int near_refine_mix(int v, const GridArgs& G, const N
     return v == NV_MIX6_8R ? NV_M6R_WAVE : (v == NV_MIX12 || v == NV_MIX12_8) ? NV_M12 : NV_M6;
 }
 
+// Blocks of 64 columns (16 steps of a lane) between two settings of u from
+// sincospi, where u was carried through the previous block: 1 with the full
+// budget (the recurrence drifts by ~16 roundings per block), HANK_NEAR_ANCHOR
+// with the lean one (64 steps drift by ~1e-14, far inside 1.25e-10).
+#ifndef HANK_NEAR_ANCHOR
+#define HANK_NEAR_ANCHOR 4
+#endif
+
 // Near-field sweep of one tile (one right-hand side) for the lane of column
 // phase ph: columns T.n0 + ph, +4, ..., 16 per block of 64, coefficients and
 // root offsets read from LDS (cb[i] is column T.n0 + i; the columns from T.n1
 // to the next multiple of 4 carry c = 0, so that every lane of a block takes
 // the same number of steps).  The variant is chosen per block (wave-uniform).
+// A block of the small-argument step alone leaves u behind, so the next
+// block sets it afresh.
 template <bool PERT, bool LEAN>
 __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb, const uint32_t* bv,
                                              const double* tl, const NearTile& T, int ph, NearLane& r) {
     double acc = 0.0;
+    bool carried = false; // u is current at this block's first column
+    int since = 0;        // blocks since u was set
     for (int64_t nb = T.n0; nb < T.n1; nb += 64) {
         const int cnt = ((int)min<int64_t>(64, T.n1 - nb) + 3) >> 2;
         const ColCB* p = cb + (nb - T.n0) + ph;
@@ -500,9 +528,12 @@ __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb,
             v = near_refine_mix<PERT, false>(v, G, r, p, cnt);
         else if (v == NV_MIX12_8 || v == NV_MIX6_8 || v == NV_MIX6_8R)
             v = near_refine_mix<PERT, HANK_TAYLOR_LDS != 0>(v, G, r, p, cnt);
-#define BLOCK(M_, S_, A_) near_block<M_, S_, A_, PERT, J0_TAYLOR_DEG, LEAN>(G, p, cnt, r, acc, tl); break
-#define BLOCK8(M_, A_) near_block<M_, true, A_, PERT, 8, LEAN>(G, p, cnt, r, acc, tl); break
-#define BLOCKR(M_, S_, A_, NT_) near_block<M_, S_, A_, PERT, NT_, LEAN, PERT>(G, p, cnt, r, acc, tl); break
+        const bool anchor = !(LEAN && carried && since < HANK_NEAR_ANCHOR - 1);
+        since = anchor ? 0 : since + 1;
+        carried = !(v == NV_SMALL || v == NV_SMALL8);
+#define BLOCK(M_, S_, A_) near_block<M_, S_, A_, PERT, J0_TAYLOR_DEG, LEAN>(G, p, cnt, r, acc, tl, anchor); break
+#define BLOCK8(M_, A_) near_block<M_, true, A_, PERT, 8, LEAN>(G, p, cnt, r, acc, tl, anchor); break
+#define BLOCKR(M_, S_, A_, NT_) near_block<M_, S_, A_, PERT, NT_, LEAN, PERT>(G, p, cnt, r, acc, tl, anchor); break
         switch (v) {
         case NV_M6R_WAVE: BLOCKR(6, false, true, J0_TAYLOR_DEG);
         case NV_M2R: BLOCKR(2, false, true, J0_TAYLOR_DEG);
