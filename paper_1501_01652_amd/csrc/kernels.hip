@@ -443,6 +443,9 @@ __device__ __forceinline__ double near_step(const GridArgs& G, NearLane& r, doub
 #ifndef HANK_NEAR_UNROLL
 #define HANK_NEAR_UNROLL 4
 #endif
+#ifndef HANK_NEAR_PREFETCH
+#define HANK_NEAR_PREFETCH 1
+#endif
 #ifndef HANK_NEAR_WPE
 #define HANK_NEAR_WPE 4
 #endif
@@ -469,11 +472,23 @@ __device__ __forceinline__ void near_block(const GridArgs& G, const ColCB* p, in
     constexpr bool TL = HANK_TAYLOR_LDS && SMALL && NT <= TAY_LDS_NT;
     if (ASY && anchor) near_anchor(G, r);
     const HankelSet<M> H = hankel_set<M, LEAN>();
+#if HANK_NEAR_PREFETCH
+    // the next column's data read one step ahead (the read past the last
+    // column lands in the 4 spare entries of cb)
+    ColCB v = p[0];
+    HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
+    for (int i = 0; i < cnt; ++i) {
+        const ColCB vn = p[4 * (i + 1)];
+        acc = fma(v.c, near_step<M, SMALL, ASY, PERT, NT, LEAN, ROT1, TL>(G, r, PERT ? v.b : 0.0, H, tl), acc);
+        v = vn;
+    }
+#else
     HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
     for (int i = 0; i < cnt; ++i) {
         const ColCB v = p[4 * i];
         acc = fma(v.c, near_step<M, SMALL, ASY, PERT, NT, LEAN, ROT1, TL>(G, r, PERT ? v.b : 0.0, H, tl), acc);
     }
+#endif
 }
 
 // Internal code of the Hankel-only block with 6 pairs and the first-order
@@ -485,12 +500,12 @@ constexpr int NV_M6R_WAVE = NV_COUNT;
 // lanes' first and last columns decide.  Returns the variant that evaluates
 // exactly the same branch for every entry of the wave: the small-argument or
 // the Hankel code alone, or the mixed one.
+// b0, b1: the root offsets of the lane's first and last column of the block
 template <bool PERT, bool TL>
-__device__ __forceinline__ int near_refine_mix(int v, const GridArgs& G, const NearLane& r, const ColCB* p,
-                                               int cnt) {
-    const bool small = near_z_small<PERT, TL>(G, r, r.Nd, p[0].b) < J0_ASY_Z;
-    const bool asy =
-        !(near_z_small<PERT, TL>(G, r, fma(double(cnt - 1), r.dNd, r.Nd), p[4 * (cnt - 1)].b) < J0_ASY_Z);
+__device__ __forceinline__ int near_refine_mix(int v, const GridArgs& G, const NearLane& r, int cnt, double b0,
+                                               double b1) {
+    const bool small = near_z_small<PERT, TL>(G, r, r.Nd, b0) < J0_ASY_Z;
+    const bool asy = !(near_z_small<PERT, TL>(G, r, fma(double(cnt - 1), r.dNd, r.Nd), b1) < J0_ASY_Z);
     const bool any_small = __ballot(small) != 0;
     const bool any_asy = __ballot(asy) != 0;
     if (any_small && any_asy) return v;
@@ -525,9 +540,9 @@ __device__ __forceinline__ double near_sweep(const GridArgs& G, const ColCB* cb,
         const ColCB* p = cb + (nb - T.n0) + ph;
         int v = tile_block_variant(bv, T.n0, nb);
         if (v == NV_MIX12 || v == NV_MIX6)
-            v = near_refine_mix<PERT, false>(v, G, r, p, cnt);
+            v = near_refine_mix<PERT, false>(v, G, r, cnt, p[0].b, p[4 * (cnt - 1)].b);
         else if (v == NV_MIX12_8 || v == NV_MIX6_8 || v == NV_MIX6_8R)
-            v = near_refine_mix<PERT, HANK_TAYLOR_LDS != 0>(v, G, r, p, cnt);
+            v = near_refine_mix<PERT, HANK_TAYLOR_LDS != 0>(v, G, r, cnt, p[0].b, p[4 * (cnt - 1)].b);
         const bool anchor = !(LEAN && carried && since < HANK_NEAR_ANCHOR - 1);
         since = anchor ? 0 : since + 1;
         carried = !(v == NV_SMALL || v == NV_SMALL8);
@@ -573,7 +588,7 @@ __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(HANK_NEAR_WPE)))
 #endif
 void k_near(const NearProb* __restrict__ probs, int nprob, double* __restrict__ partial) {
-    __shared__ ColCB cb[NEAR_TILE_COLS];
+    __shared__ ColCB cb[NEAR_TILE_COLS + 4];
     __shared__ double red[4][64];
     __shared__ uint32_t sbv[4];
     __shared__ __align__(16) double tl[HANK_TAYLOR_LDS ? TAY_LDS_PIECES * TAY_LDS_LD : 2];
