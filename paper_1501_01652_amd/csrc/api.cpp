@@ -872,13 +872,32 @@ void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR, size_t budget =
                 }
                 Ln.d1 = descs.size();
                 const int32_t rows = far_rows_per_wg(Ln.L1);
+                // pass B on the FP64 row kernel (L1 = 4096) holds two 512-thread
+                // workgroups per compute unit; a launch with fewer (item, row)
+                // pairs than that splits each pair's groups over bsplit
+                // workgroups (pass B transforms the groups independently, so
+                // the results do not change)
+                int32_t bsplit = 1;
+                if (!Ln.fp32 && Ln.L1 == 4096) {
+                    int64_t pairs = 0;
+                    int32_t gmax = 1;
+                    for (size_t di = Ln.d0; di < Ln.d1; ++di) {
+                        const FarDesc& D = descs[di];
+                        pairs += int64_t(D.nrhs) * D.nchunk * ((D.A.L2 + rows - 1) / rows);
+                        gmax = std::max(gmax, D.gchunk);
+                    }
+                    const int64_t slots = 2 * 256;
+                    if (pairs > 0 && pairs < slots)
+                        bsplit = int32_t(std::min<int64_t>(gmax, (slots + pairs - 1) / pairs));
+                }
                 for (size_t di = Ln.d0; di < Ln.d1; ++di) {
                     FarDesc& D = descs[di];
                     const int64_t items = int64_t(D.nrhs) * D.nchunk;
                     D.wg_ac = Ln.nac;
                     Ln.nac += items * (D.A.L1 / col_width(D.A.L2, Ln.fp32));
+                    D.bsplit = bsplit;
                     D.wg_b = Ln.nb;
-                    Ln.nb += items * ((D.A.L2 + rows - 1) / rows);
+                    Ln.nb += items * ((D.A.L2 + rows - 1) / rows) * bsplit;
                     D.wg_r = Ln.nr;
                     if (D.nchunk > 1) Ln.nr += int64_t(D.nrhs) * ((D.A.nrows + 255) / 256);
                 }

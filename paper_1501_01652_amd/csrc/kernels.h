@@ -128,7 +128,10 @@ struct FarDesc {
     double* part;
     int64_t ldc, ldo;
     int64_t wg_ac, wg_b, wg_r;
-    int32_t nrhs, nchunk, gchunk, pad;
+    int32_t nrhs, nchunk, gchunk;
+    // workgroups of pass B (the FP64 row kernel) per (item, row): each takes
+    // its share of the chunk's groups (0 or 1: all of them)
+    int32_t bsplit;
     // Blocks of at most L1 = 4096 columns on the FP64 wave-column/row kernels:
     // pass A stores only each column's one nonzero input, x0[j][g][j1] (j1 <
     // ncols), and pass B forms its rows from it; x0off is its offset in the

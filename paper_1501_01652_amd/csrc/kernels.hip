@@ -1051,7 +1051,9 @@ struct FarItem {
     int desc, wg, j, chunk;
 };
 
-__device__ __forceinline__ FarItem far_item(const FarDesc* __restrict__ descs, int ndesc, int which, int per) {
+// split: pass B workgroups carry the descriptor's bsplit (k_pass_bw)
+__device__ __forceinline__ FarItem far_item(const FarDesc* __restrict__ descs, int ndesc, int which, int per,
+                                            bool split = false) {
     const int64_t bid = blockIdx.x;
     FarItem it;
     int64_t local;
@@ -1061,6 +1063,7 @@ __device__ __forceinline__ FarItem far_item(const FarDesc* __restrict__ descs, i
     } else if (which == 1) {
         it.desc = find_desc<FarDesc, &FarDesc::wg_b>(descs, ndesc, bid);
         local = bid - descs[it.desc].wg_b;
+        if (split) per *= max(1, descs[it.desc].bsplit);
     } else {
         it.desc = find_desc<FarDesc, &FarDesc::wg_r>(descs, ndesc, bid);
         local = bid - descs[it.desc].wg_r;
@@ -1852,12 +1855,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     static_assert(L1 == 4096, "rows of 8 x 512 points");
     constexpr int SR = wave_lds_len<512>();
     __shared__ cx<F> sh[8 * SR];
-    const FarItem mp = far_item(descs, ndesc, 1, per_b);
+    const FarItem mp = far_item(descs, ndesc, 1, per_b, true);
     const FarDesc& D = descs[mp.desc];
     const FarArgs& A = D.A;
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int64_t row = mp.wg; // one row per workgroup: mp.wg < L2
+    // one row per workgroup, and of the chunk's groups the share bs of bsplit
+    const int64_t row = mp.wg % A.L2;
+    const int bs = mp.wg / A.L2, nbs = max(1, D.bsplit);
     cx<F>* my = sh + wv * SR;
     // this wave's chirp spectrum (permuted layout)
     const auto hrow = gview((const cx<F>*)D.H) + row * L1 + wv * 512;
@@ -1866,7 +1871,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     for (int s = 0; s < 8; ++s) hv[s] = gload(hrow + lane + 64 * s);
     const auto buf = gview((cx<F>*)D.buf);
     const int ng = A.g1 - A.g0;
-    const int gs = mp.chunk * D.gchunk, ge = min(ng, gs + D.gchunk);
+    const int cs = mp.chunk * D.gchunk, ce = min(ng, cs + D.gchunk), share = (ce - cs + nbs - 1) / nbs;
+    const int gs = cs + bs * share, ge = min(ce, gs + share);
     // columns j1 = t + 512 a >= ncols hold zeros (pass A does not store them),
     // and columns j1 >= nrows feed no output row (pass C skips them): the
     // loads and stores this thread makes, as bit masks over a
