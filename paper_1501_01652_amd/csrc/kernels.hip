@@ -682,17 +682,19 @@ constexpr int CS_LD = 80; // row stride of the coefficient tile (16 mod 32 banks
 #ifndef HANK_MULTI_STAGE
 #define HANK_MULTI_STAGE 1
 #endif
-template <int M, bool SMALL, bool ASY, bool PERT, bool ROT1 = false>
+template <int M, bool SMALL, bool ASY, bool PERT, bool ROT1 = false, bool LEAN = false, int NT = J0_TAYLOR_DEG>
 __device__ __forceinline__ void near_multi_block(const GridArgs& G, NearLane& R, const double (*Cs)[CS_LD],
                                                  const double* Bs, double* Js, int64_t nb, int64_t n1, int kq,
-                                                 int lane, int nblk, v4d (&acc)[4]) {
-    if (ASY) near_anchor(G, R);
-    const HankelSet<M> H = hankel_set<M>();
+                                                 int lane, int nblk, v4d (&acc)[4], const double* tl, bool anchor) {
+    constexpr bool TL = HANK_TAYLOR_LDS && SMALL && NT <= TAY_LDS_NT;
+    if (ASY && anchor) near_anchor(G, R);
+    const HankelSet<M> H = hankel_set<M, LEAN>();
 #if HANK_MULTI_STAGE
     HANK_PRAGMA(unroll HANK_NEAR_UNROLL)
     for (int i = 0; i < 16; ++i) {
         const int col = 4 * i + kq;
-        const double J = near_step<M, SMALL, ASY, PERT, J0_TAYLOR_DEG, false, ROT1>(G, R, PERT ? Bs[col] : 0.0, H);
+        const double J =
+            near_step<M, SMALL, ASY, PERT, NT, LEAN, ROT1, TL>(G, R, PERT ? Bs[col] : 0.0, H, tl);
         Js[64 * i + lane] = (R.active && nb + col < n1) ? J : 0.0;
     }
 #pragma unroll 1
@@ -708,7 +710,7 @@ __device__ __forceinline__ void near_multi_block(const GridArgs& G, NearLane& R,
     HANK_PRAGMA(unroll HANK_MULTI_UNROLL)
     for (int i = 0; i < 16; ++i) {
         const int col = 4 * i + kq;
-        double J = near_step<M, SMALL, ASY, PERT>(G, R, PERT ? Bs[col] : 0.0, H);
+        double J = near_step<M, SMALL, ASY, PERT, NT, LEAN, ROT1, TL>(G, R, PERT ? Bs[col] : 0.0, H, tl);
         J = (R.active && nb + col < n1) ? J : 0.0;
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb)
@@ -717,9 +719,9 @@ __device__ __forceinline__ void near_multi_block(const GridArgs& G, NearLane& R,
 #endif
 }
 
-template <bool PERT>
+template <bool PERT, bool LEAN>
 __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile& T, const uint32_t* bv,
-                                                double (*Cs)[CS_LD], double* Bs, double* Js,
+                                                double (*Cs)[CS_LD], double* Bs, double* Js, const double* tl,
                                                 double* __restrict__ out) {
     const GridArgs& G = P.G;
     const int t = threadIdx.x, lane = t & 63;
@@ -731,6 +733,8 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
     v4d acc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+    bool carried = false; // as in near_sweep
+    int since = 0;
     for (int64_t nb = T.n0; nb < T.n1; nb += 64) {
         // stage: thread t carries column t%64 of right-hand sides t/64 + 4i
         {
@@ -743,17 +747,29 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
             if (PERT && t < 64) Bs[t] = n < T.n1 ? gview(P.b)[n - 1] : 0.0;
         }
         __syncthreads();
-#define BLOCK(M_, S_, A_) near_multi_block<M_, S_, A_, PERT>(G, R, Cs, Bs, Js + 1024 * wave, nb, T.n1, kq, lane, nblk, acc); break
-        // the 8-term small-argument codes run in full here (with the first-order
-        // residual factor where the code says so)
         int var = tile_block_variant(bv, T.n0, nb);
-        var = var == NV_SMALL8 ? NV_SMALL : var == NV_MIX12_8 ? NV_MIX12 : var == NV_MIX6_8 ? NV_MIX6 : var;
-#define BLOCKR(M_, S_, A_) near_multi_block<M_, S_, A_, PERT, PERT>(G, R, Cs, Bs, Js + 1024 * wave, nb, T.n1, kq, lane, nblk, acc); break
+        {
+            const double b0 = PERT ? Bs[kq] : 0.0, b1 = PERT ? Bs[60 + kq] : 0.0;
+            if (var == NV_MIX12 || var == NV_MIX6)
+                var = near_refine_mix<PERT, false>(var, G, R, 16, b0, b1);
+            else if (var == NV_MIX12_8 || var == NV_MIX6_8 || var == NV_MIX6_8R)
+                var = near_refine_mix<PERT, HANK_TAYLOR_LDS != 0>(var, G, R, 16, b0, b1);
+        }
+        const bool anchor = !(LEAN && carried && since < HANK_NEAR_ANCHOR - 1);
+        since = anchor ? 0 : since + 1;
+        carried = !(var == NV_SMALL || var == NV_SMALL8);
+#define BLOCK(M_, S_, A_) near_multi_block<M_, S_, A_, PERT, false, LEAN>(G, R, Cs, Bs, Js + 1024 * wave, nb, T.n1, kq, lane, nblk, acc, tl, anchor); break
+#define BLOCK8(M_, A_) near_multi_block<M_, true, A_, PERT, false, LEAN, 8>(G, R, Cs, Bs, Js + 1024 * wave, nb, T.n1, kq, lane, nblk, acc, tl, anchor); break
+#define BLOCKR(M_, S_, A_, NT_) near_multi_block<M_, S_, A_, PERT, PERT, LEAN, NT_>(G, R, Cs, Bs, Js + 1024 * wave, nb, T.n1, kq, lane, nblk, acc, tl, anchor); break
         switch (var) {
-        case NV_M2R: BLOCKR(2, false, true);
-        case NV_M3R: BLOCKR(3, false, true);
-        case NV_M4R: BLOCKR(4, false, true);
-        case NV_MIX6_8R: BLOCKR(6, true, true);
+        case NV_M6R_WAVE: BLOCKR(6, false, true, J0_TAYLOR_DEG);
+        case NV_M2R: BLOCKR(2, false, true, J0_TAYLOR_DEG);
+        case NV_M3R: BLOCKR(3, false, true, J0_TAYLOR_DEG);
+        case NV_M4R: BLOCKR(4, false, true, J0_TAYLOR_DEG);
+        case NV_MIX6_8R: BLOCKR(6, true, true, 8);
+        case NV_SMALL8: BLOCK8(3, false);
+        case NV_MIX12_8: BLOCK8(12, true);
+        case NV_MIX6_8: BLOCK8(6, true);
         case NV_SMALL: BLOCK(3, true, false);
         case NV_MIX12: BLOCK(12, true, true);
         case NV_MIX6: BLOCK(6, true, true);
@@ -765,6 +781,7 @@ __device__ __forceinline__ void near_multi_body(const NearJob& P, const NearTile
         default: BLOCK(12, false, true);
         }
 #undef BLOCKR
+#undef BLOCK8
 #undef BLOCK
         near_skip16(R);
         __syncthreads();
@@ -790,15 +807,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     double* Js = nullptr;
 #endif
     __shared__ uint32_t sbv[4];
+    __shared__ __align__(16) double tl[HANK_TAYLOR_LDS ? TAY_LDS_PIECES * TAY_LDS_LD : 2];
     const NearProb& Pr = probs[find_desc<NearProb, &NearProb::tile_start>(probs, nprob, blockIdx.x)];
     const NearTile T = Pr.tiles[blockIdx.x - Pr.tile_start];
     if (threadIdx.x < 4) sbv[threadIdx.x] = Pr.tiles[blockIdx.x - Pr.tile_start].bvar[threadIdx.x];
+    if (HANK_TAYLOR_LDS)
+        for (int i = threadIdx.x; i < TAY_LDS_PIECES * TAY_LDS_NT; i += 256) {
+            const int pc = i / TAY_LDS_NT, u = i % TAY_LDS_NT;
+            tl[pc * TAY_LDS_LD + u] =
+                pc < J0_TAYLOR0_PIECES ? g_tab.tay0[pc][u] : g_tab.tay[pc - J0_TAYLOR0_PIECES][u];
+        }
     const NearJob P = near_job(Pr); // by value: scalar registers, loaded once
     double* out = partial + Pr.pbase + T.slot * (int64_t)P.nrhs * 64;
+    // (the body's first barrier orders the LDS copies above before their use)
     if (P.G.col_pert)
-        near_multi_body<true>(P, T, sbv, Cs, Bs, Js, out);
+        P.G.lean ? near_multi_body<true, true>(P, T, sbv, Cs, Bs, Js, tl, out)
+                 : near_multi_body<true, false>(P, T, sbv, Cs, Bs, Js, tl, out);
     else
-        near_multi_body<false>(P, T, sbv, Cs, Bs, Js, out);
+        P.G.lean ? near_multi_body<false, true>(P, T, sbv, Cs, Bs, Js, tl, out)
+                 : near_multi_body<false, false>(P, T, sbv, Cs, Bs, Js, tl, out);
 }
 
 // ---------------------------------------------------------------------------
