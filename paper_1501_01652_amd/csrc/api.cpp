@@ -877,8 +877,10 @@ void prepare_jobs(const std::vector<Job>& jobs_in, Prepared& PR, size_t budget =
                 // pairs than that splits each pair's groups over bsplit
                 // workgroups (pass B transforms the groups independently, so
                 // the results do not change)
+                // (HANK_PASSB_SPLIT=0, read per call, turns the split off)
                 int32_t bsplit = 1;
-                if (!Ln.fp32 && Ln.L1 == 4096) {
+                const char* split_env = std::getenv("HANK_PASSB_SPLIT");
+                if (!Ln.fp32 && Ln.L1 == 4096 && !(split_env && std::atoi(split_env) == 0)) {
                     int64_t pairs = 0;
                     int32_t gmax = 1;
                     for (size_t di = Ln.d0; di < Ln.d1; ++di) {

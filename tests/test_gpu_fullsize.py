@@ -256,3 +256,19 @@ def test_beyond_largest_size_is_rejected():
     st = hank.lib().hank_transform(2, ctypes.c_void_p(c.data_ptr()), n, 1, n, 1e-8,
                                    ctypes.c_void_p(c.data_ptr() + 32), n, None, None)
     assert st == 1  # HANK_EINVAL, before any device work
+
+
+def test_passb_group_split_is_exact(monkeypatch):
+    """Pass B's group split (a launch with fewer (item, row) pairs than the
+    chip holds spreads each pair's groups over several workgroups, here the
+    DHT 2^20 strips) changes which workgroup transforms a group, not the
+    arithmetic: the output is bitwise the same as without it."""
+    N, eps = 1 << 20, 1e-8
+    c = dev(inputs.workload("dht0", N))
+    blocks = hank.plan_blocks("dht0", N, eps, precision=1)
+    assert any(b["fft_l1"] == 4096 and b["fft_len"] // 4096 < 512 for b in blocks), "no block to split"
+    f_split = host(hank.transform("dht0", c, eps, precision=1))
+    monkeypatch.setenv("HANK_PASSB_SPLIT", "0")
+    f_plain = host(hank.transform("dht0", c, eps, precision=1))
+    print("dht0 N=%d eps=%g: max |split - unsplit| = %.3e" % (N, eps, float(np.max(np.abs(f_split - f_plain)))))
+    assert np.array_equal(f_split, f_plain)
