@@ -465,9 +465,10 @@ hank_status build_dev_plan(DevPlan& dp, hipStream_t s) {
 // (at most 64); plans are cached per bucket.
 // Right-hand sides a plan is made for: 1 for order nu > 0 (its near field
 // sums one right-hand side at a time) and for up to three right-hand sides,
-// which run as that many single transforms (measured: 2 right-hand sides
-// 22-27% faster that way than on the several-right-hand-side MFMA kernel, 3
-// about equal, 4 or more slower).
+// which run as that many single transforms (measured on Fourier-Bessel 2e4
+// and Schlomilch 3e4 at 1e-8 and DHT 8192 at 1e-14: 2 right-hand sides 17-31%
+// faster that way than on the several-right-hand-side MFMA kernel, 3 8-12%
+// faster, 4 equal to 13% slower, 5 or more slower).
 constexpr int64_t SINGLE_RHS_MAX = 3;
 int64_t plan_nrhs(int64_t nrhs, int nu) { return (nu > 0 || nrhs <= SINGLE_RHS_MAX) ? 1 : nrhs; }
 
