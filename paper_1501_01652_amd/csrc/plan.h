@@ -105,9 +105,10 @@ struct Plan {
 // Cost-model constants (seconds); refined from measurements through the
 // environment (HANK_COST_FFT, HANK_COST_NEAR, HANK_COST_BLOCK).
 struct CostModel {
-    double fft_pt_group64 = 2.7e-11; // per FFT point per group per right-hand side, FP64 (measured)
-    double fft_pt_group32 = 1.95e-11; // same, FP32
-    double near_entry = 2.0e-12;     // per directly summed entry, one right-hand side (measured)
+    double fft_pt_group64 = 1.8e-11; // per FFT point per group per right-hand side, FP64 (measured)
+    double fft_pt_group32 = 1.5e-11; // same, FP32 (the passes move half the bytes but do the same
+                                     // FFT work; measured FP32-bulk plans run barely faster)
+    double near_entry = 1.2e-12;     // per directly summed entry, one right-hand side (measured)
     double near_plain_entry = 1.3e-12; // the same without root perturbations (Schlomilch, order 0)
     double near_nu_entry = 5.1e-12;  // the same for Schlomilch of order nu > 0 (k_near_nu, measured)
     double near_multi_entry = 4.2e-12; // per entry with several right-hand sides (J_0 once per entry)
