@@ -111,7 +111,9 @@ struct CostModel {
     double near_entry = 1.2e-12;     // per directly summed entry, one right-hand side (measured)
     double near_plain_entry = 1.3e-12; // the same without root perturbations (Schlomilch, order 0)
     double near_nu_entry = 5.1e-12;  // the same for Schlomilch of order nu > 0 (k_near_nu, measured)
-    double near_multi_entry = 4.2e-12; // per entry with several right-hand sides (J_0 once per entry)
+    double near_multi_entry = 5.5e-12; // per entry with several right-hand sides (J_0 once per entry;
+                                       // set by the batched workload's throughput: 3.0e-12..7.0e-12
+                                       // gave 4840..5036 transforms/s, best at 5.5e-12)
     double near_rhs = 4.5e-14;       // per entry and right-hand side of the product (FP64 MFMA)
     double block = 50e-6;            // fixed cost per block: three dependent launches and a reduce
                                      // (measured on single transforms, N = 3000..50000)
