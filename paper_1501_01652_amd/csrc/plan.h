@@ -115,8 +115,11 @@ struct CostModel {
                                        // set by the batched workload's throughput: 3.0e-12..7.0e-12
                                        // gave 4840..5036 transforms/s, best at 5.5e-12)
     double near_rhs = 4.5e-14;       // per entry and right-hand side of the product (FP64 MFMA)
-    double block = 50e-6;            // fixed cost per block: three dependent launches and a reduce
-                                     // (measured on single transforms, N = 3000..50000)
+    double block = 30e-6;            // fixed cost per block: three dependent launches and a reduce
+                                     // (measured on single transforms, N = 3000..50000, as 50e-6;
+                                     // 30e-6 after the kernel changes: batched workload 3% faster,
+                                     // the single-transform configurations unchanged; 15e-6 cost
+                                     // Schlomilch 4096 and Fourier-Bessel 2^16 at 1e-8 20-25%)
 };
 
 // ---- parameter formulas ----
